@@ -1,0 +1,78 @@
+"""The oracle's pins must catch plausible mistakes.
+
+Each case plants one mistake in a copy of ``oracle/oracle.c`` (on the CPU,
+in a temporary directory), builds it, and runs the pin suite against that
+build.  The suite must fail for every planted mistake.
+"""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "oracle.c")
+
+# (name, original text, planted mistake)
+MUTANTS = [
+    ("arithmetic_mean_face", "kf = 2.0 * kp * kn / (kp + kn);", "kf = 0.5 * (kp + kn);"),
+    ("geometric_mean_face", "kf = 2.0 * kp * kn / (kp + kn);", "kf = sqrt(kp * kn);"),
+    ("dirichlet_half_cell", "const double D = p->dt * kp / (p->h * p->h);",
+     "const double D = 2.0 * p->dt * kp / (p->h * p->h);"),
+    ("dirichlet_neighbour_kappa_missing", "const double D = p->dt * kp / (p->h * p->h);",
+     "const double D = p->dt * p->alpha / (p->h * p->h);"),
+    ("conductance_over_h", "const double D = p->dt * kf / (p->h * p->h);",
+     "const double D = p->dt * kf / p->h;"),
+    ("upwind_reversed", "off[f] = -(D + fmax(-F, 0.0));", "off[f] = -(D + fmax(F, 0.0));"),
+    ("upwind_central", "off[f] = -(D + fmax(-F, 0.0));", "off[f] = -(D - 0.5 * F);"),
+    ("outflow_abs", "      diag += D + fmax(F, 0.0);\n      off[f]",
+     "      diag += D + fabs(F);\n      off[f]"),
+    ("flux_number_h2", "const double F = p->dt * (p->u[axis] * normal) / p->h;",
+     "const double F = p->dt * (p->u[axis] * normal) / (p->h * p->h);"),
+    ("bterm_no_inflow", "bterm += (D + fmax(-F, 0.0)) * p->bc_value[f];",
+     "bterm += D * p->bc_value[f];"),
+    ("dirichlet_outflow_dropped",
+     "      const double D = p->dt * kp / (p->h * p->h);\n      diag += D + fmax(F, 0.0);",
+     "      const double D = p->dt * kp / (p->h * p->h);\n      diag += D;"),
+    ("zeroflux_as_dirichlet", "} else if (p->bc_kind[f] == ORC_DIRICHLET) {", "} else {"),
+    ("rhs_sign", "b[c] = Tn[c] + bterm;", "b[c] = Tn[c] - bterm;"),
+    ("neighbour_coefficient_swap",
+     "if (j > 0)      acc += off[2] * x[cell_index(p, i, j - 1, k)];",
+     "if (j > 0)      acc += off[3] * x[cell_index(p, i, j - 1, k)];"),
+    ("neighbour_index_swap",
+     "if (k < nz - 1) acc += off[5] * x[cell_index(p, i, j, k + 1)];",
+     "if (k < nz - 1) acc += off[5] * x[cell_index(p, i, j + 1 < ny ? j + 1 : j, k)];"),
+    ("beta_missing_alpha_over_omega", "const double beta = (rho / rho_prev) * (alpha / omega);",
+     "const double beta = (rho / rho_prev);"),
+    ("p_update_sign", "pv[c] = r[c] + beta * (pv[c] - omega * v[c]);",
+     "pv[c] = r[c] + beta * (pv[c] + omega * v[c]);"),
+    ("alpha_inverted", "alpha = rho / sigma;", "alpha = sigma / rho;"),
+    ("omega_inverted", "omega = ts / tt;", "omega = tt / ts;"),
+    ("x_update_drops_s", "x[c] = x[c] + alpha * pv[c] + omega * s[c];",
+     "x[c] = x[c] + alpha * pv[c];"),
+    ("r_update_sign", "r[c] = s[c] - omega * t[c];", "r[c] = s[c] + omega * t[c];"),
+    ("s_update_sign", "s[c] = r[c] - alpha * v[c];", "s[c] = r[c] + alpha * v[c];"),
+    ("absolute_stop_test", "if (rnorm <= tol * bn) { status = ORC_OK; goto done; }\n    if (omega",
+     "if (rnorm <= tol) { status = ORC_OK; goto done; }\n    if (omega"),
+    ("cg_beta_inverted", "const double beta = rr_new / rr;", "const double beta = rr / rr_new;"),
+    ("cg_step_sign", "x[c] += a * d[c]; r[c] -= a * q[c];", "x[c] -= a * d[c]; r[c] -= a * q[c];"),
+    ("dot_drops_last_plane", "for (int k = 0; k < nz; ++k) total += part[k];",
+     "for (int k = 0; k + 1 < nz; ++k) total += part[k];"),
+]
+
+
+@pytest.mark.parametrize("name,orig,bad", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_pins_catch_planted_mistake(tmp_path, name, orig, bad):
+    src = open(SRC).read()
+    assert src.count(orig) >= 1, f"mutation anchor for {name} not found"
+    mutated = src.replace(orig, bad, 1)
+    csrc = tmp_path / "oracle_mutant.c"
+    csrc.write_text(mutated)
+    lib = tmp_path / "liboracle_mutant.so"
+    subprocess.run(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-o", str(lib),
+                    str(csrc), "-lm"], check=True)
+    env = dict(os.environ, ORACLE_LIB=str(lib), OMP_NUM_THREADS="2")
+    res = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                          os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                         cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert res.returncode != 0, f"pins did not catch mutant {name}:\n{res.stdout[-2000:]}"
