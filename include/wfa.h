@@ -1,0 +1,232 @@
+/*
+ * wfa.h - C-ABI of libwfa.so, an implicit field-equation solver for one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The problem (Woo et al. 2022, section 1.1.2, Eq. 3, generalised): one
+ * backward-Euler step of transport on a uniform Cartesian grid of cubic
+ * cells is the sparse linear system A x = b with a 7-point stencil.  The
+ * paper's form has diagonal 1 and equal off-diagonals -omega (constant
+ * diffusivity, boundary cells held at a constant value); this library
+ * also allows a per-cell diffusivity (harmonic mean on each face),
+ * constant-velocity first-order upwind convection and per-face Dirichlet or
+ * zero-flux boundaries.  Row P of A, for each face f of cell P:
+ *   interior face:  D = dt*kf/h^2 (kf harmonic mean of the two cells),
+ *                   F = dt*(u.n_f)/h;  A[P,P] += D + max(F,0),
+ *                   A[P,N] = -(D + max(-F,0))
+ *   Dirichlet face: ghost at distance h with the cell's own diffusivity;
+ *                   A[P,P] += D + max(F,0), b[P] += (D + max(-F,0))*value
+ *   zero-flux face: no term.
+ * and A[P,P] starts at 1.  The system is solved with BiCGStab (van der Vorst
+ * 1992), or with classic conjugate gradients (the paper's solver, section
+ * 1.1.2) for the symmetric pure-diffusion case.
+ *
+ * Conventions
+ *   - Fields are dense arrays of nx*ny*nz values, x fastest:
+ *     index = i + nx*(j + ny*k) (a torch tensor of shape (nz, ny, nx)).
+ *     No pitch, no padding.
+ *   - Faces are ordered x-, x+, y-, y+, z-, z+.
+ *   - Every data pointer is a caller-owned DEVICE pointer on the current
+ *     HIP device.  The library never allocates device memory: the Krylov
+ *     workspace and the server arena are caller-provided buffers.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *   - Every function returns a status code (WFA_OK = 0) and records a
+ *     message for wfa_last_error().  Arguments are validated before any
+ *     launch; nothing is launched when validation fails.  No C++ exception
+ *     crosses this interface.
+ *   - Functions are thread-safe for distinct grids and servers; calls on one
+ *     grid must not overlap.
+ */
+#ifndef WFA_H
+#define WFA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes -------------------------------------------------------- */
+#define WFA_OK             0
+#define WFA_PENDING        1   /* wfa_poll only: the request is not finished  */
+#define WFA_ERR_INVALID   -1   /* bad dimension, null pointer, bad enum,
+                                  tol <= 0, maxit < 1, bad option            */
+#define WFA_ERR_NOMEM     -2   /* workspace or arena too small               */
+#define WFA_ERR_HIP       -3   /* HIP runtime error (text in wfa_last_error) */
+#define WFA_ERR_BREAKDOWN -4   /* more than WFA_MAX_RESTARTS restarts         */
+#define WFA_ERR_NOCONV    -5   /* maxit reached; x holds the last iterate    */
+#define WFA_ERR_NONFINITE -6   /* NaN/Inf in the data or a Krylov scalar     */
+
+#define WFA_MAX_RESTARTS 3
+
+/* ---- enums ----------------------------------------------------------------- */
+enum {
+  WFA_F64 = 0,      /* FP64 vectors and operator                              */
+  WFA_F32 = 1,      /* FP32 vectors and operator, FP64 dot accumulation       */
+  WFA_F32_IR64 = 2  /* FP64 fields; FP32 inner BiCGStab inside FP64 iterative
+                       refinement (residual, update and norms in FP64)       */
+};
+enum { WFA_COEF_CONST = 0, WFA_COEF_CELL = 1 };
+enum { WFA_BC_DIRICHLET = 0, WFA_BC_ZEROFLUX = 1 };
+enum { WFA_METHOD_BICGSTAB = 0, WFA_METHOD_CG = 1 };
+
+/* ---- problem description --------------------------------------------------- */
+typedef struct {
+  int32_t mode;          /* WFA_COEF_CONST (alpha) or WFA_COEF_CELL (kappa)    */
+  int32_t precision;     /* WFA_F64, WFA_F32 or WFA_F32_IR64                   */
+  double  h;             /* cubic cell side, > 0                               */
+  double  dt;            /* backward-Euler time step, > 0                      */
+  double  alpha;         /* constant diffusivity (CONST), >= 0                 */
+  const void* kappa;     /* CELL: device pointer to nx*ny*nz float32 values,
+                            > 0; kept by pointer until wfa_grid_destroy        */
+  double  u[3];          /* constant velocity; 0 = pure diffusion              */
+  int32_t bc[6];         /* WFA_BC_DIRICHLET / WFA_BC_ZEROFLUX per face        */
+  double  bc_value[6];   /* Dirichlet ghost values (ignored for zero-flux)     */
+} wfa_coeffs;
+
+typedef struct {
+  int32_t status;        /* final code of the solve (WFA_OK, NOCONV, ...)      */
+  int32_t iterations;    /* full iterations (BiCGStab: 2 operator products)   */
+  int32_t refinements;   /* WFA_F32_IR64: outer FP64 refinement steps         */
+  int32_t restarts;      /* breakdown restarts from the true residual          */
+  double  rel_res_recursive; /* recursive ||r|| / ||b|| at exit (FP32_IR64:
+                                the inner solver's last value)                */
+  double  rel_res_true;  /* ||b - A x|| / ||b|| in FP64, at exit               */
+  double  seconds;       /* wall time of the solve (host clock)                */
+} wfa_solve_info;
+
+typedef struct wfa_grid wfa_grid;       /* opaque, host-side */
+typedef struct wfa_server wfa_server;   /* opaque, host-side */
+
+/* ---- grids ------------------------------------------------------------------ */
+
+/* Bytes of device workspace a grid of this size and precision needs
+ * (vectors, per-block partial sums, the device scalar block).  0 when a
+ * dimension is < 1. */
+size_t wfa_workspace_bytes(int nx, int ny, int nz, int precision);
+
+/* Create a grid descriptor.  `c` is copied (kappa by pointer).  `workspace`
+ * is a device buffer of at least wfa_workspace_bytes(...) bytes, 256-byte
+ * aligned, owned by the caller and kept alive until wfa_grid_destroy.
+ * Errors: WFA_ERR_INVALID (dims < 1, h/dt <= 0, alpha < 0, bad enums, CELL
+ * without kappa, null out), WFA_ERR_NOMEM (workspace too small). */
+int wfa_grid_create(int nx, int ny, int nz, const wfa_coeffs* c,
+                    void* workspace, size_t workspace_bytes, wfa_grid** out);
+
+/* Release the host descriptor (the workspace stays the caller's). */
+int wfa_grid_destroy(wfa_grid* g);
+
+/* y = A x with the ghosts held at zero, i.e. the operator alone (boundary
+ * values only enter right-hand sides).  x, y: nx*ny*nz values of the
+ * grid's vector type (double for WFA_F64 and WFA_F32_IR64, float for
+ * WFA_F32); x and y must not overlap.  Asynchronous on `stream`. */
+int wfa_stencil_apply(wfa_grid* g, const void* x, void* y, void* stream);
+
+/* b = T + (Dirichlet boundary terms): the right-hand side of one backward-
+ * Euler step from T (section 1.1.2, Eq. 3).  Same types as apply.  Async. */
+int wfa_rhs(wfa_grid* g, const void* T, void* b, void* stream);
+
+/* Solve A x = b.  x holds the initial guess on entry and the solution (or,
+ * on WFA_ERR_NOCONV, the last iterate) on exit.  Stops at the first full
+ * iteration with recursive ||r|| <= tol*||b||; b == 0 gives x = 0.  Exact
+ * breakdown (rho, sigma or omega == 0) restarts from b - A x, at most
+ * WFA_MAX_RESTARTS times.  `info` may be NULL.  Synchronises `stream`. */
+int wfa_bicgstab_solve(wfa_grid* g, const void* b, void* x, double tol, int maxit,
+                       wfa_solve_info* info, void* stream);
+
+/* Classic conjugate gradients on A x = b (valid when A is symmetric
+ * positive definite: u == 0).  Same contract as wfa_bicgstab_solve; each
+ * iteration is one operator product and two reductions. */
+int wfa_cg_solve(wfa_grid* g, const void* b, void* x, double tol, int maxit,
+                 wfa_solve_info* info, void* stream);
+
+/* nsteps backward-Euler steps in place: T holds T^n on entry and T^{n+nsteps}
+ * on exit.  Each step forms b = T + boundary terms and solves A T' = b from
+ * the initial guess T with the grid's method (BiCGStab unless changed with
+ * WFA_OPT_METHOD).  `info` is an array of nsteps records or NULL.  Stops at
+ * the first step that fails.  Synchronises `stream`. */
+int wfa_timestep(wfa_grid* g, void* T, int nsteps, double tol, int maxit,
+                 wfa_solve_info* info, void* stream);
+
+/* FP64 true relative residual ||b - A x|| / ||b|| (FP64 fields only, i.e.
+ * WFA_F64 or WFA_F32_IR64 grids).  Synchronises `stream`. */
+int wfa_true_residual(wfa_grid* g, const void* b, const void* x, double* rel, void* stream);
+
+/* ---- options and instrumentation -------------------------------------------- */
+enum {
+  WFA_OPT_METHOD = 1,          /* WFA_METHOD_BICGSTAB (default) or _CG         */
+  WFA_OPT_PERSISTENT = 2,      /* 0: one launch per phase (default),
+                                  1: one persistent launch per solve chunk,
+                                  -1: automatic by grid size                   */
+  WFA_OPT_PROFILE = 3,         /* 1: time every phase launch with HIP events   */
+  WFA_OPT_FORCE_BREAKDOWN = 4, /* n > 0: treat sigma as exactly 0 at full
+                                  iteration n of the next solve (once), to
+                                  exercise the restart path from the host      */
+  WFA_OPT_CHECK_EVERY = 5,     /* iterations between host convergence checks;
+                                  0 = adaptive (default)                       */
+  WFA_OPT_IR_INNER_TOL = 6,    /* (value / 1e12) = inner relative tolerance of
+                                  WFA_F32_IR64; default 1e-4 * 1e12            */
+  WFA_OPT_ZCHUNK = 7           /* z planes per workgroup; 0 = tuned            */
+};
+int wfa_grid_set_option(wfa_grid* g, int option, int64_t value);
+
+/* Kernel ids for wfa_kernel_stats. */
+enum {
+  WFA_K_APPLY = 0, WFA_K_INIT = 1, WFA_K_PHASE_A = 2, WFA_K_PHASE_B = 3,
+  WFA_K_PHASE_C = 4, WFA_K_RESIDUAL = 5, WFA_K_PROMOTE = 6, WFA_K_CG_A = 7,
+  WFA_K_CG_B = 8, WFA_K_PERSISTENT = 9, WFA_K_COUNT = 10
+};
+/* With WFA_OPT_PROFILE on: launches and summed event time (ms) of one
+ * kernel since the last reset; `bytes` = algorithmic HBM bytes per launch
+ * (the streams the kernel must read and write once).  reset != 0 clears. */
+int wfa_kernel_stats(wfa_grid* g, int kernel, int64_t* launches, double* ms,
+                     double* bytes_per_launch, int reset);
+
+/* Tile shape the grid uses: x cells, y cells, z planes per workgroup, and
+ * the number of workgroups of one phase launch. */
+int wfa_grid_tiling(wfa_grid* g, int* tx, int* ty, int* zc, int* blocks);
+
+/* Achievable HBM bandwidth probe: copies `bytes` (multiple of 16) from src
+ * to dst `reps` times on `stream` and returns GB/s (read + write bytes). */
+int wfa_stream_probe(const void* src, void* dst, size_t bytes, int reps, double* gbps,
+                     void* stream);
+
+/* ---- serving ------------------------------------------------------------------ */
+
+/* A server owns a caller-provided device arena of arena_bytes (its HBM
+ * budget) and up to max_slots resident solves.  Requests are admitted in
+ * arrival order as arena space and slots free up; all resident solves
+ * advance together in batched launches (continuous batching); a request
+ * finishes independently of the others and its result does not depend on
+ * which requests ran beside it.  A background host thread drives the GPU
+ * on `stream`.  Precision of every request: c->precision. */
+int wfa_server_create(void* arena, size_t arena_bytes, int max_slots, void* stream,
+                      wfa_server** out);
+
+/* Queue one backward-Euler step of T (device, nx*ny*nz, in/out; the
+ * caller keeps it, and kappa, alive until wfa_poll reports completion).
+ * WFA_ERR_NOMEM if the request can never fit the arena. */
+int wfa_submit(wfa_server* sv, int nx, int ny, int nz, const wfa_coeffs* c, void* T,
+               double tol, int maxit, uint64_t* ticket);
+
+/* WFA_PENDING while queued or running, otherwise the request's final code
+ * (info filled, seconds = completion - submission).  A ticket may be polled
+ * again after completion; unknown tickets give WFA_ERR_INVALID. */
+int wfa_poll(wfa_server* sv, uint64_t ticket, wfa_solve_info* info);
+
+/* Block until every submitted request has finished. */
+int wfa_server_drain(wfa_server* sv);
+
+/* Wait for in-flight work, stop the host thread and free the descriptor. */
+int wfa_server_destroy(wfa_server* sv);
+
+/* Thread-local message of the last failing call on this thread. */
+const char* wfa_last_error(void);
+
+/* Library version string. */
+const char* wfa_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WFA_H */

@@ -1,0 +1,769 @@
+// Host side of libwfa: grid descriptors, the Krylov drivers (BiCGStab, CG,
+// FP32-in-FP64 iterative refinement), backward-Euler time stepping, launch
+// profiling, and the C-ABI declared in include/wfa.h.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <chrono>
+#include <new>
+#include <vector>
+
+#include "wfa.h"
+#include "internal.hpp"
+#include "host.hpp"
+
+using namespace wfa;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local char g_err[512] = "";
+
+namespace wfa {
+int set_error(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+  return code;
+}
+}  // namespace wfa
+
+#define HIP_TRY(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return set_error(WFA_ERR_HIP, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_),     \
+                       __FILE__, __LINE__);                                            \
+  } while (0)
+
+extern "C" const char* wfa_last_error(void) { return g_err; }
+extern "C" const char* wfa_version(void) { return "wfa 0.1 (gfx950)"; }
+
+// ---------------------------------------------------------------------------
+// workspace layout
+// ---------------------------------------------------------------------------
+static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+namespace wfa {
+
+size_t partial_slots(int nx, int ny, int nz) {
+  // worst case over the tile shapes the library may choose (ry >= 1, zc >= 1)
+  const size_t tx = (size_t)(nx + kTX - 1) / kTX;
+  const size_t ty = (size_t)(ny + kWaves - 1) / kWaves;
+  size_t s = tx * ty * (size_t)nz;
+  if (s < 2048) s = 2048;
+  return s;
+}
+
+Layout layout_for(int nx, int ny, int nz, int precision) {
+  Layout L{};
+  const size_t n = (size_t)nx * ny * nz;
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
+  L.scalars = take(sizeof(Scalars) * 4);
+  L.partials = take(sizeof(double) * 3 * partial_slots(nx, ny, nz));
+  if (precision == WFA_F32_IR64) {
+    L.b64 = take(8 * n);
+    for (int q = 0; q < kVecs; ++q) L.vec[q] = take(4 * n);
+    L.d32 = take(4 * n);
+  } else {
+    const size_t w = precision == WFA_F32 ? 4 : 8;
+    for (int q = 0; q < kVecs; ++q) L.vec[q] = take(w * n);
+  }
+  L.total = off;
+  return L;
+}
+
+}  // namespace wfa
+
+extern "C" size_t wfa_workspace_bytes(int nx, int ny, int nz, int precision) {
+  if (nx < 1 || ny < 1 || nz < 1) return 0;
+  if (precision < WFA_F64 || precision > WFA_F32_IR64) return 0;
+  return layout_for(nx, ny, nz, precision).total;
+}
+
+// ---------------------------------------------------------------------------
+// grid
+// ---------------------------------------------------------------------------
+namespace wfa {
+
+template <typename T>
+static Op<T> make_op(const wfa_coeffs& c) {
+  Op<T> op{};
+  const double cD = c.mode == WFA_COEF_CELL ? c.dt / (c.h * c.h) : c.dt * c.alpha / (c.h * c.h);
+  op.cD = (T)cD;
+  for (int f = 0; f < 6; ++f) {
+    const int axis = f / 2;
+    const double normal = (f % 2 == 0) ? -1.0 : 1.0;
+    const double F = c.dt * (c.u[axis] * normal) / c.h;
+    op.in[f] = (T)fmax(-F, 0.0);
+    op.out[f] = (T)fmax(F, 0.0);
+    op.bval[f] = (T)c.bc_value[f];
+    if (c.bc[f] == WFA_BC_DIRICHLET) op.dir |= 1u << f;
+  }
+  return op;
+}
+
+int validate_coeffs(int nx, int ny, int nz, const wfa_coeffs* c) {
+  if (!c) return set_error(WFA_ERR_INVALID, "coeffs is NULL");
+  if (nx < 1 || ny < 1 || nz < 1)
+    return set_error(WFA_ERR_INVALID, "grid dimensions must be >= 1 (got %d x %d x %d)", nx, ny, nz);
+  if ((long long)nx * ny > 0x7fffffffLL)
+    return set_error(WFA_ERR_INVALID, "nx*ny must fit in 31 bits");
+  if (c->mode != WFA_COEF_CONST && c->mode != WFA_COEF_CELL)
+    return set_error(WFA_ERR_INVALID, "bad coefficient mode %d", c->mode);
+  if (c->precision < WFA_F64 || c->precision > WFA_F32_IR64)
+    return set_error(WFA_ERR_INVALID, "bad precision %d", c->precision);
+  if (!(c->h > 0.0) || !(c->dt > 0.0) || !isfinite(c->h) || !isfinite(c->dt))
+    return set_error(WFA_ERR_INVALID, "h and dt must be finite and > 0");
+  if (c->mode == WFA_COEF_CONST && !(c->alpha >= 0.0 && isfinite(c->alpha)))
+    return set_error(WFA_ERR_INVALID, "alpha must be finite and >= 0");
+  if (c->mode == WFA_COEF_CELL && !c->kappa)
+    return set_error(WFA_ERR_INVALID, "CELL mode needs a kappa pointer");
+  for (int a = 0; a < 3; ++a)
+    if (!isfinite(c->u[a])) return set_error(WFA_ERR_INVALID, "velocity must be finite");
+  for (int f = 0; f < 6; ++f) {
+    if (c->bc[f] != WFA_BC_DIRICHLET && c->bc[f] != WFA_BC_ZEROFLUX)
+      return set_error(WFA_ERR_INVALID, "bad boundary kind %d on face %d", c->bc[f], f);
+    if (!isfinite(c->bc_value[f])) return set_error(WFA_ERR_INVALID, "boundary value not finite");
+  }
+  return WFA_OK;
+}
+
+void grid_setup(wfa_grid* g, int nx, int ny, int nz, const wfa_coeffs* c, char* ws) {
+  g->nx = nx; g->ny = ny; g->nz = nz;
+  g->n = (size_t)nx * ny * nz;
+  g->c = *c;
+  g->prec = c->precision;
+  g->ws = ws;
+  g->lay = layout_for(nx, ny, nz, c->precision);
+  g->sc = (Scalars*)(ws + g->lay.scalars);
+  g->sc_in = g->sc + 1;
+  g->sc_aux = g->sc + 2;
+  g->partials = (double*)(ws + g->lay.partials);
+  for (int q = 0; q < kVecs; ++q) g->vec[q] = ws + g->lay.vec[q];
+  g->b64 = g->prec == WFA_F32_IR64 ? (double*)(ws + g->lay.b64) : nullptr;
+  g->d32 = g->prec == WFA_F32_IR64 ? (float*)(ws + g->lay.d32) : nullptr;
+  g->op64 = make_op<double>(*c);
+  g->op32 = make_op<float>(*c);
+  g->method = WFA_METHOD_BICGSTAB;
+  g->persistent = 0;
+  g->profile = 0;
+  g->force_bd = 0;
+  g->check_every = 0;
+  g->zchunk = 0;
+  g->ir_inner_tol = 1e-4;
+  const int w = g->prec == WFA_F32 ? 4 : 8;
+  g->tl = make_tiling(nx, ny, nz, w, 0);
+  g->tl32 = make_tiling(nx, ny, nz, 4, 0);
+}
+
+}  // namespace wfa
+
+extern "C" int wfa_grid_create(int nx, int ny, int nz, const wfa_coeffs* c, void* workspace,
+                               size_t workspace_bytes, wfa_grid** out) {
+  if (!out) return set_error(WFA_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  int rc = validate_coeffs(nx, ny, nz, c);
+  if (rc) return rc;
+  if (!workspace) return set_error(WFA_ERR_INVALID, "workspace is NULL");
+  if (((uintptr_t)workspace & 255) != 0)
+    return set_error(WFA_ERR_INVALID, "workspace must be 256-byte aligned");
+  const size_t need = wfa_workspace_bytes(nx, ny, nz, c->precision);
+  if (workspace_bytes < need)
+    return set_error(WFA_ERR_NOMEM, "workspace too small: %zu < %zu bytes", workspace_bytes, need);
+  wfa_grid* g = new (std::nothrow) wfa_grid();
+  if (!g) return set_error(WFA_ERR_NOMEM, "host allocation failed");
+  grid_setup(g, nx, ny, nz, c, (char*)workspace);
+  *out = g;
+  return WFA_OK;
+}
+
+extern "C" int wfa_grid_destroy(wfa_grid* g) {
+  if (!g) return set_error(WFA_ERR_INVALID, "grid is NULL");
+  g->prof.clear();
+  delete g;
+  return WFA_OK;
+}
+
+extern "C" int wfa_grid_set_option(wfa_grid* g, int option, int64_t value) {
+  if (!g) return set_error(WFA_ERR_INVALID, "grid is NULL");
+  switch (option) {
+    case WFA_OPT_METHOD:
+      if (value != WFA_METHOD_BICGSTAB && value != WFA_METHOD_CG)
+        return set_error(WFA_ERR_INVALID, "bad method %lld", (long long)value);
+      g->method = (int)value;
+      return WFA_OK;
+    case WFA_OPT_PERSISTENT:
+      if (value < -1 || value > 1) return set_error(WFA_ERR_INVALID, "bad persistent mode");
+      g->persistent = (int)value;
+      return WFA_OK;
+    case WFA_OPT_PROFILE:
+      g->profile = value != 0;
+      return WFA_OK;
+    case WFA_OPT_FORCE_BREAKDOWN:
+      if (value < 0) return set_error(WFA_ERR_INVALID, "bad breakdown iteration");
+      g->force_bd = (int)value;
+      return WFA_OK;
+    case WFA_OPT_CHECK_EVERY:
+      if (value < 0 || value > 100000) return set_error(WFA_ERR_INVALID, "bad check interval");
+      g->check_every = (int)value;
+      return WFA_OK;
+    case WFA_OPT_IR_INNER_TOL:
+      if (value <= 0) return set_error(WFA_ERR_INVALID, "bad inner tolerance");
+      g->ir_inner_tol = (double)value * 1e-12;
+      return WFA_OK;
+    case WFA_OPT_ZCHUNK: {
+      if (value < 0 || value > g->nz) return set_error(WFA_ERR_INVALID, "bad z chunk");
+      g->zchunk = (int)value;
+      const int w = g->prec == WFA_F32 ? 4 : 8;
+      g->tl = make_tiling(g->nx, g->ny, g->nz, w, g->zchunk);
+      g->tl32 = make_tiling(g->nx, g->ny, g->nz, 4, g->zchunk);
+      return WFA_OK;
+    }
+    default:
+      return set_error(WFA_ERR_INVALID, "unknown option %d", option);
+  }
+}
+
+extern "C" int wfa_grid_tiling(wfa_grid* g, int* tx, int* ty, int* zc, int* blocks) {
+  if (!g) return set_error(WFA_ERR_INVALID, "grid is NULL");
+  if (tx) *tx = kTX;
+  if (ty) *ty = kWaves * g->tl.ry;
+  if (zc) *zc = g->tl.geo.zc;
+  if (blocks) *blocks = g->tl.geo.ntiles;
+  return WFA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// profiling
+// ---------------------------------------------------------------------------
+namespace wfa {
+
+void Profiler::clear() {
+  for (auto& p : pending) {
+    hipEventDestroy(p.e0);
+    hipEventDestroy(p.e1);
+  }
+  pending.clear();
+  for (auto e : pool) hipEventDestroy(e);
+  pool.clear();
+}
+
+hipEvent_t Profiler::get() {
+  if (!pool.empty()) {
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+void Profiler::drain() {
+  for (auto& p : pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(p.e1) == hipSuccess && hipEventElapsedTime(&ms, p.e0, p.e1) == hipSuccess) {
+      launches[p.kernel] += 1;
+      total_ms[p.kernel] += ms;
+    }
+    pool.push_back(p.e0);
+    pool.push_back(p.e1);
+  }
+  pending.clear();
+}
+
+}  // namespace wfa
+
+// Bracket one launch with events when profiling.
+struct ProfScope {
+  wfa_grid* g;
+  int kernel;
+  hipStream_t s;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  ProfScope(wfa_grid* g_, int k, hipStream_t s_) : g(g_), kernel(k), s(s_) {
+    if (g->profile) {
+      e0 = g->prof.get();
+      e1 = g->prof.get();
+      if (e0 && e1) hipEventRecord(e0, s);
+    }
+  }
+  ~ProfScope() {
+    if (g->profile && e0 && e1) {
+      hipEventRecord(e1, s);
+      g->prof.pending.push_back({kernel, e0, e1});
+    }
+  }
+};
+
+static double bytes_per_cell(const wfa_grid* g, int kernel) {
+  const double w = g->prec == WFA_F32 ? 4.0 : 8.0;
+  const double wi = g->prec == WFA_F32_IR64 ? 4.0 : w;  // inner vectors
+  const double k = g->c.mode == WFA_COEF_CELL ? 4.0 : 0.0;
+  switch (kernel) {
+    case WFA_K_APPLY: return 2 * w + k;
+    case WFA_K_INIT: return 4 * w + k;
+    case WFA_K_PHASE_A: return 6 * wi + k;
+    case WFA_K_PHASE_B: return 3 * wi + k;
+    case WFA_K_PHASE_C: return 8 * wi;
+    case WFA_K_RESIDUAL: return 2 * w + k + (g->prec == WFA_F32_IR64 ? 8.0 : 0.0);
+    case WFA_K_PROMOTE: return 20.0;
+    case WFA_K_CG_A: return 4 * wi + k;
+    case WFA_K_CG_B: return 6 * wi;
+    case WFA_K_PERSISTENT: return 17 * wi + 2 * k;
+    default: return 0.0;
+  }
+}
+
+extern "C" int wfa_kernel_stats(wfa_grid* g, int kernel, int64_t* launches, double* ms,
+                                double* bytes_per_launch, int reset) {
+  if (!g) return set_error(WFA_ERR_INVALID, "grid is NULL");
+  if (kernel < 0 || kernel >= WFA_K_COUNT) return set_error(WFA_ERR_INVALID, "bad kernel id");
+  g->prof.drain();
+  if (launches) *launches = g->prof.launches[kernel];
+  if (ms) *ms = g->prof.total_ms[kernel];
+  if (bytes_per_launch) *bytes_per_launch = bytes_per_cell(g, kernel) * (double)g->n;
+  if (reset) {
+    for (int q = 0; q < WFA_K_COUNT; ++q) {
+      g->prof.launches[q] = 0;
+      g->prof.total_ms[q] = 0.0;
+    }
+  }
+  return WFA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// launch contexts
+// ---------------------------------------------------------------------------
+template <typename T>
+static Launch<T> ctx(wfa_grid* g, Scalars* sc, hipStream_t s);
+
+template <>
+Launch<double> ctx<double>(wfa_grid* g, Scalars* sc, hipStream_t s) {
+  Launch<double> L{};
+  L.tl = g->tl;
+  L.op = g->op64;
+  L.cell = g->c.mode == WFA_COEF_CELL;
+  L.kappa = (const float*)g->c.kappa;
+  L.partials = g->partials;
+  L.sc = sc;
+  L.stream = s;
+  return L;
+}
+
+template <>
+Launch<float> ctx<float>(wfa_grid* g, Scalars* sc, hipStream_t s) {
+  Launch<float> L{};
+  L.tl = g->prec == WFA_F32 ? g->tl : g->tl32;
+  L.op = g->op32;
+  L.cell = g->c.mode == WFA_COEF_CELL;
+  L.kappa = (const float*)g->c.kappa;
+  L.partials = g->partials;
+  L.sc = sc;
+  L.stream = s;
+  return L;
+}
+
+static int check_launch(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return set_error(WFA_ERR_HIP, "%s launch: %s", what, hipGetErrorString(e));
+  return WFA_OK;
+}
+
+// Host copy of a device scalar block.
+static int read_scalars(wfa_grid* g, const Scalars* dev, Scalars* host, hipStream_t s) {
+  HIP_TRY(hipMemcpyAsync(host, dev, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (g->profile) g->prof.drain();
+  return WFA_OK;
+}
+
+static int write_scalars(const Scalars* host, Scalars* dev, hipStream_t s) {
+  HIP_TRY(hipMemcpyAsync(dev, host, sizeof(Scalars), hipMemcpyHostToDevice, s));
+  return WFA_OK;
+}
+
+static int status_code(int dev_status) {
+  switch (dev_status) {
+    case ST_CONV: case ST_BZERO: return WFA_OK;
+    case ST_NOCONV: return WFA_ERR_NOCONV;
+    case ST_NONFINITE: return WFA_ERR_NONFINITE;
+    case ST_BREAKDOWN: return WFA_ERR_BREAKDOWN;
+    default: return WFA_ERR_NOCONV;
+  }
+}
+
+// Iterations to launch before the next host check: an estimate of what
+// remains from the residual history, bounded by the iteration budget.
+static int next_chunk(const wfa_grid* g, const Scalars& h, int budget) {
+  int m;
+  if (g->check_every > 0) {
+    m = g->check_every;
+  } else if (h.iter == 0 || !(h.rr > 0.0) || !(h.rr0 > 0.0) || h.rr >= h.rr0) {
+    m = 8;
+  } else {
+    const double rate = log(h.rr / h.rr0) / (double)h.iter;  // < 0
+    const double target = log(h.tol * h.tol * h.bb);
+    double rem = (target - log(h.rr)) / rate;
+    if (!(rem > 0.0)) rem = 1.0;
+    m = (int)ceil(rem * 1.05) + 1;
+    if (m > 512) m = 512;
+  }
+  if (m > budget) m = budget;
+  if (m < 1) m = 1;
+  return m;
+}
+
+// ---------------------------------------------------------------------------
+// BiCGStab (and CG) iteration loops on an initialised scalar block
+// ---------------------------------------------------------------------------
+// Runs iterations until the device status leaves ST_RUN.  A breakdown
+// restarts from the true residual b - A x when `restartable`; otherwise the
+// loop returns with h->restart set (the caller restarts at a higher level).
+template <typename T>
+static int iterate_bicgstab(wfa_grid* g, const Launch<T>& L, T* x, T* r, T* rh, T** p, T** v,
+                            T* t, const T* b, Scalars* h, int* restarts, bool restartable) {
+  int par = 0;
+  int rc = read_scalars(g, L.sc, h, L.stream);
+  if (rc) return rc;
+  while (h->status == ST_RUN) {
+    if (h->restart) {
+      if (!restartable) return WFA_OK;
+      if (++*restarts > WFA_MAX_RESTARTS) { h->status = -1; return WFA_OK; }
+      {
+        ProfScope ps(g, WFA_K_INIT, L.stream);
+        launch_init<T>(L, false, x, b, nullptr, r, rh);
+      }
+      if ((rc = check_launch("init"))) return rc;
+      if ((rc = read_scalars(g, L.sc, h, L.stream))) return rc;
+      continue;
+    }
+    const int m = next_chunk(g, *h, h->maxit - h->iter);
+    for (int q = 0; q < m; ++q) {
+      {
+        ProfScope ps(g, WFA_K_PHASE_A, L.stream);
+        launch_phase_a<T>(L, r, p[par], v[par], p[par ^ 1], v[par ^ 1], rh);
+      }
+      {
+        ProfScope ps(g, WFA_K_PHASE_B, L.stream);
+        launch_phase_b<T>(L, r, v[par ^ 1], t);
+      }
+      {
+        ProfScope ps(g, WFA_K_PHASE_C, L.stream);
+        launch_phase_c<T>(L, x, p[par ^ 1], r, v[par ^ 1], t, rh);
+      }
+      par ^= 1;
+    }
+    if ((rc = check_launch("phase"))) return rc;
+    if ((rc = read_scalars(g, L.sc, h, L.stream))) return rc;
+  }
+  return WFA_OK;
+}
+
+template <typename T>
+static int iterate_cg(wfa_grid* g, const Launch<T>& L, T* x, T* r, T** d, T* q, Scalars* h) {
+  int par = 0;
+  int rc = read_scalars(g, L.sc, h, L.stream);
+  if (rc) return rc;
+  while (h->status == ST_RUN) {
+    const int m = next_chunk(g, *h, h->maxit - h->iter);
+    for (int k = 0; k < m; ++k) {
+      {
+        ProfScope ps(g, WFA_K_CG_A, L.stream);
+        launch_cg_a<T>(L, r, d[par], d[par ^ 1], q);
+      }
+      {
+        ProfScope ps(g, WFA_K_CG_B, L.stream);
+        launch_cg_b<T>(L, x, d[par ^ 1], r, q);
+      }
+      par ^= 1;
+    }
+    if ((rc = check_launch("cg"))) return rc;
+    if ((rc = read_scalars(g, L.sc, h, L.stream))) return rc;
+  }
+  return WFA_OK;
+}
+
+static Scalars fresh_scalars(double tol, int maxit, int force_bd) {
+  Scalars h{};
+  h.tol = tol;
+  h.maxit = maxit;
+  h.iter = 0;
+  h.force_bd = force_bd;
+  h.scale = 1.0;
+  h.inv_scale = 1.0;
+  h.status = ST_RUN;
+  h.counter = 0;
+  return h;
+}
+
+// FP64 true relative residual of Tin-typed x and b.
+template <typename Tin>
+static int true_residual(wfa_grid* g, const Tin* b, const Tin* x, double* rel, hipStream_t s) {
+  Scalars h = fresh_scalars(1.0, 1, 0);
+  int rc = write_scalars(&h, g->sc_aux, s);
+  if (rc) return rc;
+  Launch<double> L = ctx<double>(g, g->sc_aux, s);
+  {
+    ProfScope ps(g, WFA_K_RESIDUAL, s);
+    launch_residual<Tin>(L, x, b, nullptr, nullptr, nullptr, 0);
+  }
+  if ((rc = check_launch("residual"))) return rc;
+  if ((rc = read_scalars(g, g->sc_aux, &h, s))) return rc;
+  *rel = h.bb > 0.0 ? sqrt(h.rr / h.bb) : sqrt(h.rr);
+  return WFA_OK;
+}
+
+// One solve of A x = b in the grid's own vector type T.
+template <typename T>
+static int solve_plain(wfa_grid* g, const T* b_user, T* x, bool form_b, double tol, int maxit,
+                       wfa_solve_info* info, hipStream_t s) {
+  auto t0 = std::chrono::steady_clock::now();
+  T** vec = (T**)g->vec;
+  T *r = vec[0], *rh = vec[1], *t = vec[2];
+  T* p[2] = {vec[3], vec[4]};
+  T* v[2] = {vec[5], vec[6]};
+  T* bw = vec[7];
+  Scalars h = fresh_scalars(tol, maxit, g->force_bd);
+  g->force_bd = 0;
+  int rc = write_scalars(&h, g->sc, s);
+  if (rc) return rc;
+  Launch<T> L = ctx<T>(g, g->sc, s);
+  const T* b = form_b ? bw : b_user;
+  {
+    ProfScope ps(g, WFA_K_INIT, s);
+    launch_init<T>(L, form_b, x, b_user, bw, r, rh);
+  }
+  if ((rc = check_launch("init"))) return rc;
+  int restarts = 0;
+  if (g->method == WFA_METHOD_CG)
+    rc = iterate_cg<T>(g, L, x, r, p, t, &h);
+  else
+    rc = iterate_bicgstab<T>(g, L, x, r, rh, p, v, t, b, &h, &restarts, true);
+  if (rc) return rc;
+  int status;
+  if (h.status == -1) status = WFA_ERR_BREAKDOWN;
+  else status = status_code(h.status);
+  if (h.status == ST_BZERO) {
+    launch_fill<T>(g->n, x, T(0), s);
+    if ((rc = check_launch("fill"))) return rc;
+  }
+  double rel_true = 0.0;
+  if (status != WFA_ERR_NONFINITE) {
+    if ((rc = true_residual<T>(g, b, x, &rel_true, s))) return rc;
+  } else {
+    rel_true = NAN;
+  }
+  if (info) {
+    info->status = status;
+    info->iterations = h.iter;
+    info->refinements = 0;
+    info->restarts = restarts;
+    info->rel_res_recursive = h.bb > 0.0 ? sqrt(h.rr / h.bb) : 0.0;
+    info->rel_res_true = rel_true;
+    info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return status;
+}
+
+// FP32 BiCGStab inside FP64 iterative refinement.
+static int solve_ir(wfa_grid* g, const double* b_user, double* x, bool form_b, double tol,
+                    int maxit, wfa_solve_info* info, hipStream_t s) {
+  auto t0 = std::chrono::steady_clock::now();
+  float** vec = (float**)g->vec;
+  float *r = vec[0], *rh = vec[1], *t = vec[2];
+  float* p[2] = {vec[3], vec[4]};
+  float* v[2] = {vec[5], vec[6]};
+  float* d = g->d32;
+  int rc;
+  Launch<double> L64 = ctx<double>(g, g->sc, s);
+  Launch<float> L32 = ctx<float>(g, g->sc_in, s);
+  const double* b = b_user;
+  if (form_b) {
+    launch_rhs<double>(L64, x, g->b64);
+    if ((rc = check_launch("rhs"))) return rc;
+    b = g->b64;
+  }
+  const int max_ref = 30;
+  int total_it = 0, refinements = 0, restarts = 0;
+  double scale = 1.0, rec = 0.0;
+  Scalars ho{}, hi{};
+  int status = WFA_ERR_NOCONV;
+  const int force_bd = g->force_bd;
+  g->force_bd = 0;
+  for (int ref = 0;; ++ref) {
+    ho = fresh_scalars(tol, maxit, 0);
+    ho.scale = scale;
+    ho.inv_scale = 1.0 / scale;
+    hi = fresh_scalars(g->ir_inner_tol, maxit - total_it, ref == 0 ? force_bd : 0);
+    hi.scale = scale;
+    hi.inv_scale = 1.0 / scale;
+    if ((rc = write_scalars(&ho, g->sc, s))) return rc;
+    if ((rc = write_scalars(&hi, g->sc_in, s))) return rc;
+    {
+      ProfScope ps(g, WFA_K_RESIDUAL, s);
+      launch_residual<double>(L64, x, b, r, rh, g->sc_in, 1);
+    }
+    if ((rc = check_launch("residual"))) return rc;
+    if ((rc = read_scalars(g, g->sc, &ho, s))) return rc;
+    if (ho.status != ST_RUN) {
+      status = status_code(ho.status);
+      if (ho.status == ST_BZERO) {
+        launch_fill<double>(g->n, x, 0.0, s);
+        if ((rc = check_launch("fill"))) return rc;
+      }
+      break;
+    }
+    if (ref >= max_ref || total_it >= maxit) { status = WFA_ERR_NOCONV; break; }
+    // inner FP32 solve of A d = r32 from d = 0
+    // (an inner breakdown ends the inner solve; the next refinement restarts
+    // it from the FP64 true residual)
+    int inner_restarts = 0;
+    if ((rc = iterate_bicgstab<float>(g, L32, d, r, rh, p, v, t, rh, &hi, &inner_restarts,
+                                      false)))
+      return rc;
+    if (hi.status == ST_RUN && hi.restart) ++restarts;
+    if (restarts > WFA_MAX_RESTARTS) { status = WFA_ERR_BREAKDOWN; break; }
+    total_it += hi.iter;
+    rec = hi.bb > 0.0 ? sqrt(hi.rr / hi.bb) : 0.0;
+    if (hi.status == ST_NONFINITE) { status = WFA_ERR_NONFINITE; break; }
+    if (hi.iter > 0) {
+      ProfScope ps(g, WFA_K_PROMOTE, s);
+      launch_promote(g->n, g->tl.pw_blocks, x, d, g->sc_in, s);
+      if ((rc = check_launch("promote"))) return rc;
+      ++refinements;
+    }
+    // next residual scaled by 2^-e so that its entries are O(1) in FP32
+    const double rms = sqrt(ho.rr / (double)g->n);
+    scale = (rms > 0.0 && isfinite(rms)) ? ldexp(1.0, -(int)lround(log2(rms))) : 1.0;
+    if (hi.iter == 0 && hi.status != ST_RUN && hi.status != ST_CONV) {
+      status = status_code(hi.status);
+      break;
+    }
+  }
+  if (info) {
+    info->status = status;
+    info->iterations = total_it;
+    info->refinements = refinements;
+    info->restarts = restarts;
+    info->rel_res_recursive = rec;
+    info->rel_res_true = ho.bb > 0.0 ? sqrt(ho.rr / ho.bb) : 0.0;
+    if (status == WFA_ERR_NONFINITE) info->rel_res_true = NAN;
+    info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return status;
+}
+
+static int validate_solve(wfa_grid* g, const void* b, void* x, double tol, int maxit) {
+  if (!g) return set_error(WFA_ERR_INVALID, "grid is NULL");
+  if (!x) return set_error(WFA_ERR_INVALID, "x is NULL");
+  if (!b) return set_error(WFA_ERR_INVALID, "b is NULL");
+  if (!(tol > 0.0) || !isfinite(tol)) return set_error(WFA_ERR_INVALID, "tol must be > 0");
+  if (maxit < 1) return set_error(WFA_ERR_INVALID, "maxit must be >= 1");
+  return WFA_OK;
+}
+
+namespace wfa {
+int solve_any(wfa_grid* g, const void* b, void* x, bool form_b, double tol, int maxit,
+              wfa_solve_info* info, hipStream_t s) {
+  if (g->method == WFA_METHOD_CG && (g->c.u[0] != 0.0 || g->c.u[1] != 0.0 || g->c.u[2] != 0.0))
+    return set_error(WFA_ERR_INVALID, "CG needs a symmetric operator (u == 0)");
+  switch (g->prec) {
+    case WFA_F64: return solve_plain<double>(g, (const double*)b, (double*)x, form_b, tol, maxit, info, s);
+    case WFA_F32: return solve_plain<float>(g, (const float*)b, (float*)x, form_b, tol, maxit, info, s);
+    default:
+      if (g->method == WFA_METHOD_CG)
+        return set_error(WFA_ERR_INVALID, "CG is available for WFA_F64 and WFA_F32 grids");
+      return solve_ir(g, (const double*)b, (double*)x, form_b, tol, maxit, info, s);
+  }
+}
+}  // namespace wfa
+
+extern "C" int wfa_bicgstab_solve(wfa_grid* g, const void* b, void* x, double tol, int maxit,
+                                  wfa_solve_info* info, void* stream) {
+  int rc = validate_solve(g, b, x, tol, maxit);
+  if (rc) return rc;
+  const int saved = g->method;
+  g->method = WFA_METHOD_BICGSTAB;
+  rc = solve_any(g, b, x, false, tol, maxit, info, (hipStream_t)stream);
+  g->method = saved;
+  return rc;
+}
+
+extern "C" int wfa_cg_solve(wfa_grid* g, const void* b, void* x, double tol, int maxit,
+                            wfa_solve_info* info, void* stream) {
+  int rc = validate_solve(g, b, x, tol, maxit);
+  if (rc) return rc;
+  const int saved = g->method;
+  g->method = WFA_METHOD_CG;
+  rc = solve_any(g, b, x, false, tol, maxit, info, (hipStream_t)stream);
+  g->method = saved;
+  return rc;
+}
+
+extern "C" int wfa_timestep(wfa_grid* g, void* T, int nsteps, double tol, int maxit,
+                            wfa_solve_info* info, void* stream) {
+  int rc = validate_solve(g, T, T, tol, maxit);
+  if (rc) return rc;
+  if (nsteps < 0) return set_error(WFA_ERR_INVALID, "nsteps must be >= 0");
+  for (int k = 0; k < nsteps; ++k) {
+    rc = solve_any(g, nullptr, T, true, tol, maxit, info ? info + k : nullptr, (hipStream_t)stream);
+    if (rc) return rc;
+  }
+  return WFA_OK;
+}
+
+extern "C" int wfa_stencil_apply(wfa_grid* g, const void* x, void* y, void* stream) {
+  if (!g) return set_error(WFA_ERR_INVALID, "grid is NULL");
+  if (!x || !y) return set_error(WFA_ERR_INVALID, "x and y must be non-NULL");
+  const size_t w = g->prec == WFA_F32 ? 4 : 8;
+  const char* xb = (const char*)x;
+  const char* yb = (const char*)y;
+  if (xb < yb + w * g->n && yb < xb + w * g->n)
+    return set_error(WFA_ERR_INVALID, "x and y overlap");
+  hipStream_t s = (hipStream_t)stream;
+  if (g->prec == WFA_F32) {
+    ProfScope ps(g, WFA_K_APPLY, s);
+    launch_apply<float>(ctx<float>(g, g->sc, s), (const float*)x, (float*)y);
+  } else {
+    ProfScope ps(g, WFA_K_APPLY, s);
+    launch_apply<double>(ctx<double>(g, g->sc, s), (const double*)x, (double*)y);
+  }
+  return check_launch("apply");
+}
+
+extern "C" int wfa_rhs(wfa_grid* g, const void* T, void* b, void* stream) {
+  if (!g) return set_error(WFA_ERR_INVALID, "grid is NULL");
+  if (!T || !b) return set_error(WFA_ERR_INVALID, "T and b must be non-NULL");
+  hipStream_t s = (hipStream_t)stream;
+  if (g->prec == WFA_F32)
+    launch_rhs<float>(ctx<float>(g, g->sc, s), (const float*)T, (float*)b);
+  else
+    launch_rhs<double>(ctx<double>(g, g->sc, s), (const double*)T, (double*)b);
+  return check_launch("rhs");
+}
+
+extern "C" int wfa_true_residual(wfa_grid* g, const void* b, const void* x, double* rel,
+                                 void* stream) {
+  if (!g || !b || !x || !rel) return set_error(WFA_ERR_INVALID, "NULL argument");
+  if (g->prec == WFA_F32)
+    return true_residual<float>(g, (const float*)b, (const float*)x, rel, (hipStream_t)stream);
+  return true_residual<double>(g, (const double*)b, (const double*)x, rel, (hipStream_t)stream);
+}
+
+extern "C" int wfa_stream_probe(const void* src, void* dst, size_t bytes, int reps, double* gbps,
+                                void* stream) {
+  if (!src || !dst || !gbps || reps < 1 || bytes < 16 || (bytes % 16) != 0)
+    return set_error(WFA_ERR_INVALID, "bad stream probe arguments");
+  if ((((uintptr_t)src) | ((uintptr_t)dst)) & 15)
+    return set_error(WFA_ERR_INVALID, "probe buffers must be 16-byte aligned");
+  hipError_t e = hipSuccess;
+  *gbps = copy_probe(src, dst, bytes, reps, (hipStream_t)stream, &e);
+  if (e != hipSuccess) return set_error(WFA_ERR_HIP, "probe: %s", hipGetErrorString(e));
+  return WFA_OK;
+}

@@ -1,0 +1,398 @@
+// Device-side building blocks of libwfa: the 7-point operator on one cell,
+// the z-marching LDS-staged plane engine, deterministic block and grid
+// reductions, and the device scalar block of a Krylov solve.
+//
+// Operator (Woo et al. 2022, section 1.1.2, Eq. 3, generalised to a per-cell
+// diffusivity, constant-velocity first-order upwind convection and per-face
+// Dirichlet / zero-flux boundaries): for cell P and each face f,
+//   interior:  D = cD * harmonic(kP, kN)   (cD = dt/h^2; CONST: D = dt*alpha/h^2)
+//              diag += D + out_f,  coupling (D + in_f) with the neighbour,
+//              where out_f = max(F_f, 0), in_f = max(-F_f, 0), F_f = dt (u.n_f)/h
+//   Dirichlet: D = cD * kP at distance h;  diag += D + out_f,
+//              b += (D + in_f) * value_f
+//   zero-flux: nothing.
+// diag starts at 1.  (A x)_P = diag x_P - sum_f coupling_f x_N.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace wfa {
+
+constexpr int kThreads = 256;      // 4 wave64 per workgroup
+constexpr int kWaves = kThreads / 64;
+constexpr int kTX = 64;            // tile width in x: one wave spans one row
+
+// ---- device status of a solve ---------------------------------------------
+enum DevStatus : int32_t {
+  ST_RUN = 0,        // iterating
+  ST_CONV = 1,       // converged
+  ST_NOCONV = 2,     // iteration limit reached
+  ST_NONFINITE = 3,  // NaN / Inf in a reduction
+  ST_BZERO = 4,      // right-hand side is exactly zero: x = 0
+  ST_BREAKDOWN = 5   // CG: non-positive curvature
+};
+
+// Scalars of one Krylov solve, resident in device memory.  Written only by
+// the last workgroup of a phase launch (or by one thread of a persistent
+// launch between grid barriers); read by every workgroup of the next phase.
+struct alignas(64) Scalars {
+  double rho, rho_prev, alpha, omega, beta;
+  double bb, rr, tol;          // ||b||^2, last ||r||^2, relative tolerance
+  double sigma, ts, tt, rr0;   // last reduced values (diagnostics / trace)
+  double scale, inv_scale;     // mixed precision: residual scaling by 2^-e
+  int32_t status, iter, maxit, first, restart, szero, x_zero, force_bd;
+  uint32_t counter;            // last-workgroup arrival counter (self-resetting)
+  int32_t pad[7];
+};
+
+// ---- geometry and operator constants (kernel arguments, by value) ----------
+struct Geo {
+  int nx, ny, nz;
+  int tiles_x, tiles_y, zchunks, zc;  // tile grid; zc = planes per tile
+  int ntiles;                         // tiles_x * tiles_y * zchunks
+  long long plane;                    // nx * ny
+};
+
+template <typename T>
+struct Op {
+  T cD;            // dt/h^2 (CELL) or dt*alpha/h^2 (CONST)
+  T in[6];         // inflow coupling per face:  max(-F_f, 0)
+  T out[6];        // outflow diagonal per face: max( F_f, 0)
+  T bval[6];       // Dirichlet ghost values
+  uint32_t dir;    // bit f set: face f is Dirichlet
+};
+
+// Faces: 0 x-, 1 x+, 2 y-, 3 y+, 4 z-, 5 z+.  `inside` bit f: the neighbour
+// across face f exists.
+template <typename T, bool CELL>
+__device__ __forceinline__ T cell_apply(const Op<T>& op, T c, const T nb[6], T kP,
+                                        const T kN[6], uint32_t inside) {
+  T diag = T(1), acc = T(0);
+#pragma unroll
+  for (int f = 0; f < 6; ++f) {
+    if (inside & (1u << f)) {
+      const T D = CELL ? op.cD * (T(2) * kP * kN[f] / (kP + kN[f])) : op.cD;
+      diag += D + op.out[f];
+      acc += (D + op.in[f]) * nb[f];
+    } else if (op.dir & (1u << f)) {
+      const T D = CELL ? op.cD * kP : op.cD;
+      diag += D + op.out[f];
+    }
+  }
+  return diag * c - acc;
+}
+
+// Dirichlet contribution of cell P to the right-hand side.
+template <typename T, bool CELL>
+__device__ __forceinline__ T cell_bterm(const Op<T>& op, T kP, uint32_t inside) {
+  T s = T(0);
+#pragma unroll
+  for (int f = 0; f < 6; ++f) {
+    if (!(inside & (1u << f)) && (op.dir & (1u << f))) {
+      const T D = CELL ? op.cD * kP : op.cD;
+      s += (D + op.in[f]) * op.bval[f];
+    }
+  }
+  return s;
+}
+
+__device__ __forceinline__ uint32_t inside_mask(const Geo& g, int i, int j, int k) {
+  return (i > 0 ? 1u : 0u) | (i < g.nx - 1 ? 2u : 0u) | (j > 0 ? 4u : 0u) |
+         (j < g.ny - 1 ? 8u : 0u) | (k > 0 ? 16u : 0u) | (k < g.nz - 1 ? 32u : 0u);
+}
+
+// ---- XCD-aware workgroup -> tile mapping ------------------------------------
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2).  Give each XCD a contiguous range of tiles so that tiles sharing halo
+// rows run on the same L2.
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+  const int q = nb >> 3, rem = nb & 7;
+  const int xcd = b & 7, slot = b >> 3;
+  const int start = xcd < rem ? xcd * (q + 1) : rem * (q + 1) + (xcd - rem) * q;
+  return start + slot;
+}
+
+// ---- reductions ---------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+
+// Deterministic block sum of NV values; result valid in thread 0.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* red /*LDS kWaves*NV*/) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) v[q] = wave_sum(v[q]);
+  if (lane == 0) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) red[wave * NV + q] = v[q];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      double s = 0.0;
+      for (int w = 0; w < kWaves; ++w) s += red[w * NV + q];
+      v[q] = s;
+    }
+  }
+  __syncthreads();
+}
+
+// Fixed-order sum of partials[q*n + t] over t, by one workgroup; result in
+// thread 0.  Identical for any launch that produced the same partials.
+template <int NV>
+__device__ __forceinline__ void reduce_partials(const double* partials, int n,
+                                                double (&out)[NV], double* red) {
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    double s = 0.0;
+    for (int t = threadIdx.x; t < n; t += kThreads) s += partials[(size_t)q * n + t];
+    out[q] = s;
+  }
+  block_sum<NV>(out, red);
+}
+
+// Publish this workgroup's partial sums; the last workgroup to arrive
+// reduces all of them in fixed order and calls fin(sums) in thread 0.
+// Release/acquire at agent scope orders the partial stores across XCDs.
+template <int NV, class Fin>
+__device__ __forceinline__ void publish_and_finalize(double (&v)[NV], int slot, int nslots,
+                                                     double* partials, Scalars* sc,
+                                                     double* red, Fin fin) {
+  __shared__ int last;
+  block_sum<NV>(v, red);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) partials[(size_t)q * nslots + slot] = v[q];
+    __threadfence();
+    const uint32_t prev = __hip_atomic_fetch_add(&sc->counter, 1u, __ATOMIC_ACQ_REL,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+    last = (prev == (uint32_t)(nslots - 1));
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  double s[NV];
+  reduce_partials<NV>(partials, nslots, s, red);
+  if (threadIdx.x == 0) {
+    fin(s);
+    __hip_atomic_store(&sc->counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// ---- the z-marching plane engine ----------------------------------------------
+//
+// A tile is kTX x TY cells of the x-y plane times zc planes in z.  Each of
+// the 4 waves owns RY consecutive rows; lane l owns column x0 + l.  For each
+// output plane k the staged vector u (computed on the fly from the phase's
+// input arrays, also on the x-y halo) is written to an LDS plane with a
+// one-cell halo; the x and y neighbours come from LDS and the z neighbours
+// from registers (u at k-1 and k+1).  Loads for plane k+2 and the
+// epilogue's loads for plane k+1 are issued before plane k is computed, so
+// one plane of work hides each load's latency.
+//
+// Phase policy Ph provides:
+//   struct Raw;  Raw fetch(size_t idx);  T combine(const Raw&);   -- stage
+//   struct ERaw; ERaw efetch(size_t idx);                         -- epilogue loads
+//   static constexpr int NV;                                      -- dot partials
+//   void epilogue(size_t idx, T u, T Au, T kP, uint32_t inside,
+//                 const ERaw&, double (&acc)[NV]);                -- stores + dots
+template <int RY>
+struct TileShape {
+  static constexpr int TY = kWaves * RY;
+  static constexpr int LW = kTX + 2;
+  static constexpr int LH = TY + 2;
+  static constexpr int NHALO = 2 * kTX + 2 * TY;
+  static_assert(NHALO <= kThreads, "halo must fit one cell per thread");
+};
+
+template <typename T, bool CELL, int RY, class Ph>
+__device__ __forceinline__ void march_tile(const Geo& g, const Op<T>& op,
+                                           const float* __restrict__ kappa, int tile,
+                                           Ph& ph, double (&acc)[Ph::NV], T* su,
+                                           T* sk) {
+  using TS = TileShape<RY>;
+  constexpr int TY = TS::TY, LW = TS::LW, LH = TS::LH;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int tx = tile % g.tiles_x;
+  const int rest = tile / g.tiles_x;
+  const int ty = rest % g.tiles_y;
+  const int tz = rest / g.tiles_y;
+  const int x0 = tx * kTX, y0 = ty * TY;
+  const int k0 = tz * g.zc;
+  const int k1 = min(k0 + g.zc, g.nz);
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const size_t plane = (size_t)g.plane;
+
+  // own cells
+  const int i = x0 + lane;
+  bool own[RY];
+  int poff[RY];      // offset inside a plane
+  int lidx[RY];      // LDS index
+  uint32_t ins_xy[RY];
+#pragma unroll
+  for (int r = 0; r < RY; ++r) {
+    const int j = y0 + wave * RY + r;
+    own[r] = (i < nx) && (j < ny);
+    poff[r] = own[r] ? i + nx * j : 0;
+    lidx[r] = (wave * RY + r + 1) * LW + lane + 1;
+    ins_xy[r] = (i > 0 ? 1u : 0u) | (i < nx - 1 ? 2u : 0u) | (j > 0 ? 4u : 0u) |
+                (j < ny - 1 ? 8u : 0u);
+  }
+  // halo cell of this thread
+  int hl = -1, hoff = 0;
+  bool hval = false;
+  {
+    const int hs = threadIdx.x;
+    int hi = 0, hj = 0;
+    if (hs < kTX) { hi = x0 + hs; hj = y0 - 1; hl = hs + 1; }
+    else if (hs < 2 * kTX) { hi = x0 + hs - kTX; hj = y0 + TY; hl = (LH - 1) * LW + hs - kTX + 1; }
+    else if (hs < 2 * kTX + TY) { hi = x0 - 1; hj = y0 + hs - 2 * kTX; hl = (hs - 2 * kTX + 1) * LW; }
+    else if (hs < TS::NHALO) { hi = x0 + kTX; hj = y0 + hs - 2 * kTX - TY; hl = (hs - 2 * kTX - TY + 1) * LW + LW - 1; }
+    if (hl >= 0) {
+      hval = hi >= 0 && hi < nx && hj >= 0 && hj < ny;
+      hoff = hval ? hi + nx * hj : 0;
+    }
+  }
+
+  using Raw = typename Ph::Raw;
+  using ERaw = typename Ph::ERaw;
+  T up[RY], uc[RY], un[RY];
+  T kpv[RY], kcv[RY], knv[RY];
+  T hc = T(0), kh = T(0);
+  Raw rn[RY];
+  Raw rh{};
+  float krn[RY];
+  float krh = 0.f;
+  ERaw ec[RY], en[RY];
+
+  // plane k0 - 1 (own cells only)
+#pragma unroll
+  for (int r = 0; r < RY; ++r) {
+    up[r] = T(0);
+    kpv[r] = T(1);
+    if (k0 > 0 && own[r]) {
+      const size_t idx = (size_t)(k0 - 1) * plane + poff[r];
+      up[r] = ph.combine(ph.fetch(idx));
+      if (CELL) kpv[r] = (T)kappa[idx];
+    }
+  }
+  // plane k0: own + halo
+#pragma unroll
+  for (int r = 0; r < RY; ++r) {
+    uc[r] = T(0);
+    kcv[r] = T(1);
+    if (own[r]) {
+      const size_t idx = (size_t)k0 * plane + poff[r];
+      uc[r] = ph.combine(ph.fetch(idx));
+      if (CELL) kcv[r] = (T)kappa[idx];
+    }
+  }
+  if (hval) {
+    const size_t idx = (size_t)k0 * plane + hoff;
+    hc = ph.combine(ph.fetch(idx));
+    if (CELL) kh = (T)kappa[idx];
+  }
+  // raw loads for plane k0 + 1 and epilogue loads for plane k0
+  const bool has_n0 = (k0 + 1 <= k1) && (k0 + 1 < nz);
+#pragma unroll
+  for (int r = 0; r < RY; ++r) {
+    krn[r] = 1.f;
+    if (has_n0 && own[r]) {
+      const size_t idx = (size_t)(k0 + 1) * plane + poff[r];
+      rn[r] = ph.fetch(idx);
+      if (CELL) krn[r] = kappa[idx];
+    }
+    if (own[r]) ec[r] = ph.efetch((size_t)k0 * plane + poff[r]);
+  }
+  if (hval && k0 + 1 < k1) {
+    const size_t idx = (size_t)(k0 + 1) * plane + hoff;
+    rh = ph.fetch(idx);
+    if (CELL) krh = kappa[idx];
+  }
+
+  int buf = 0;
+  for (int k = k0; k < k1; ++k) {
+    T* L = su + buf * (LH * LW);
+    T* LK = CELL ? sk + buf * (LH * LW) : nullptr;
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      L[lidx[r]] = uc[r];
+      if (CELL) LK[lidx[r]] = kcv[r];
+    }
+    if (hl >= 0) {
+      L[hl] = hval ? hc : T(0);
+      if (CELL) LK[hl] = hval ? kh : T(1);
+    }
+    __syncthreads();
+
+    // stage plane k + 1
+    const bool has_n = (k + 1 <= k1) && (k + 1 < nz);
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      un[r] = T(0);
+      knv[r] = T(1);
+      if (has_n && own[r]) {
+        un[r] = ph.combine(rn[r]);
+        if (CELL) knv[r] = (T)krn[r];
+      }
+    }
+    T hn = T(0), khn = T(1);
+    if (hval && k + 1 < k1) {
+      hn = ph.combine(rh);
+      if (CELL) khn = (T)krh;
+    }
+    // issue loads for plane k + 2 and epilogue loads for plane k + 1
+    const bool fetch2 = (k + 2 <= k1) && (k + 2 < nz);
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      if (fetch2 && own[r]) {
+        const size_t idx = (size_t)(k + 2) * plane + poff[r];
+        rn[r] = ph.fetch(idx);
+        if (CELL) krn[r] = kappa[idx];
+      }
+      if (k + 1 < k1 && own[r]) en[r] = ph.efetch((size_t)(k + 1) * plane + poff[r]);
+    }
+    if (hval && k + 2 < k1) {
+      const size_t idx = (size_t)(k + 2) * plane + hoff;
+      rh = ph.fetch(idx);
+      if (CELL) krh = kappa[idx];
+    }
+
+    // compute plane k
+    const uint32_t ins_z = (k > 0 ? 16u : 0u) | (k < nz - 1 ? 32u : 0u);
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      if (own[r]) {
+        const int l = lidx[r];
+        T nb[6] = {L[l - 1], L[l + 1], L[l - LW], L[l + LW], up[r], un[r]};
+        T kn6[6];
+        if (CELL) {
+          kn6[0] = LK[l - 1]; kn6[1] = LK[l + 1]; kn6[2] = LK[l - LW];
+          kn6[3] = LK[l + LW]; kn6[4] = kpv[r]; kn6[5] = knv[r];
+        } else {
+#pragma unroll
+          for (int f = 0; f < 6; ++f) kn6[f] = T(1);
+        }
+        const uint32_t ins = ins_xy[r] | ins_z;
+        const T Au = cell_apply<T, CELL>(op, uc[r], nb, kcv[r], kn6, ins);
+        ph.epilogue((size_t)k * plane + poff[r], uc[r], Au, kcv[r], ins, ec[r], acc);
+      }
+    }
+    // rotate
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      up[r] = uc[r]; uc[r] = un[r];
+      kpv[r] = kcv[r]; kcv[r] = knv[r];
+      ec[r] = en[r];
+    }
+    hc = hn; kh = khn;
+    buf ^= 1;
+  }
+  __syncthreads();  // LDS planes are reused by the next tile of this workgroup
+}
+
+}  // namespace wfa

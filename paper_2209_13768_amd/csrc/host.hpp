@@ -1,0 +1,75 @@
+// Host-side descriptor of a grid and helpers shared by the solver driver and
+// the server.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "wfa.h"
+#include "internal.hpp"
+
+namespace wfa {
+
+constexpr int kVecs = 8;  // r, rh, t, p0, p1, v0, v1, b (b unused by IR inner)
+
+// Byte offsets of the workspace sub-buffers (each 256-byte aligned).
+struct Layout {
+  size_t scalars;           // 4 Scalars blocks: solve, inner solve, aux, spare
+  size_t partials;          // 3 x partial_slots doubles
+  size_t vec[kVecs];        // Krylov vectors (FP64 or FP32; FP32 for IR)
+  size_t b64, d32;          // IR only: FP64 right-hand side, FP32 correction
+  size_t total;
+};
+
+Layout layout_for(int nx, int ny, int nz, int precision);
+size_t partial_slots(int nx, int ny, int nz);
+
+struct Profiler {
+  struct Pending {
+    int kernel;
+    hipEvent_t e0, e1;
+  };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> pool;
+  int64_t launches[WFA_K_COUNT] = {};
+  double total_ms[WFA_K_COUNT] = {};
+  hipEvent_t get();
+  void drain();
+  void clear();
+};
+
+int set_error(int code, const char* fmt, ...);
+int validate_coeffs(int nx, int ny, int nz, const wfa_coeffs* c);
+
+}  // namespace wfa
+
+struct wfa_grid {
+  int nx, ny, nz;
+  size_t n;
+  wfa_coeffs c;
+  int prec;
+  char* ws;
+  wfa::Layout lay;
+  wfa::Scalars* sc;      // the solve
+  wfa::Scalars* sc_in;   // inner solve of iterative refinement
+  wfa::Scalars* sc_aux;  // true residual
+  double* partials;
+  void* vec[wfa::kVecs];
+  double* b64;
+  float* d32;
+  wfa::Op<double> op64;
+  wfa::Op<float> op32;
+  wfa::Tiling tl;        // tiling of the grid's vector type
+  wfa::Tiling tl32;      // tiling of FP32 inner vectors
+  int method, persistent, profile, force_bd, check_every, zchunk;
+  double ir_inner_tol;
+  wfa::Profiler prof;
+};
+
+namespace wfa {
+void grid_setup(wfa_grid* g, int nx, int ny, int nz, const wfa_coeffs* c, char* ws);
+int solve_any(wfa_grid* g, const void* b, void* x, bool form_b, double tol, int maxit,
+              wfa_solve_info* info, hipStream_t s);
+}  // namespace wfa

@@ -1,0 +1,76 @@
+// Host-side interfaces between the solver driver and the kernel launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "device.hpp"
+
+namespace wfa {
+
+// Tile shape of one grid.  A function of the grid shape and vector type
+// only, so that a solve's reduction order does not depend on anything else
+// (other requests in a batch, the launch mode).
+struct Tiling {
+  int ry;          // rows per wave (TY = 4 * ry)
+  Geo geo;         // tile grid
+  int pw_blocks;   // workgroups of the pointwise kernels
+};
+
+Tiling make_tiling(int nx, int ny, int nz, int elem_bytes, int zc_override);
+
+// Pointers of one phase launch.
+template <typename T>
+struct Launch {
+  Tiling tl;
+  Op<T> op;
+  bool cell;
+  const float* kappa;
+  double* partials;
+  Scalars* sc;
+  hipStream_t stream;
+};
+
+// y = A x
+template <typename T>
+void launch_apply(const Launch<T>& L, const T* x, T* y);
+// b = T + boundary terms (form_b) or given b; r = b - A x; rh = r; partial
+// sums (b,b), (r,r); finalize sets up the first iteration.
+template <typename T>
+void launch_init(const Launch<T>& L, bool form_b, const T* x, const T* b_in, T* b_out, T* r,
+                 T* rh);
+// b = T + boundary terms only
+template <typename T>
+void launch_rhs(const Launch<T>& L, const T* x, T* b);
+// p' = r + beta (p - omega v) (p' = r on the first iteration); v' = A p';
+// sigma = (rh, v')
+template <typename T>
+void launch_phase_a(const Launch<T>& L, const T* r, const T* p, const T* v, T* p_out, T* v_out,
+                    const T* rh);
+// s = r - alpha v; t = A s; (t,s), (t,t)
+template <typename T>
+void launch_phase_b(const Launch<T>& L, const T* r, const T* v, T* t);
+// x += alpha p + omega s; r = s - omega t; (rh, r), (r, r)
+template <typename T>
+void launch_phase_c(const Launch<T>& L, T* x, const T* p, T* r, const T* v, const T* t,
+                    const T* rh);
+// CG: d' = r + beta d (d' = r first); q = A d'; (d', q)
+template <typename T>
+void launch_cg_a(const Launch<T>& L, const T* r, const T* d, T* d_out, T* q);
+// CG: x += alpha d; r -= alpha q; (r, r)
+template <typename T>
+void launch_cg_b(const Launch<T>& L, T* x, const T* d, T* r, const T* q);
+// FP64 residual of Tin-typed x, b: (r,r), (b,b); optionally r32 = fp32(r *
+// scale) into r32 and rh32 and (r32, r32) for the inner solve (sc_inner).
+template <typename Tin>
+void launch_residual(const Launch<double>& L, const Tin* x, const Tin* b, float* r32,
+                     float* rh32, Scalars* sc_inner, int mode);
+// x64 += inv_scale * d32 (scalars of the inner solve)
+void launch_promote(size_t n, int blocks, double* x, const float* d, const Scalars* sc_inner,
+                    hipStream_t s);
+template <typename T>
+void launch_fill(size_t n, T* y, T v, hipStream_t s);
+double copy_probe(const void* src, void* dst, size_t bytes, int reps, hipStream_t s,
+                  hipError_t* err);
+
+}  // namespace wfa

@@ -1,0 +1,355 @@
+// Phase policies of the z-marching engine (march_tile) and the finalizers
+// that turn each pass's global sums into the next Krylov scalars.  Shared by
+// the single-solve kernels and the batched serving kernels, so that a solve
+// computes exactly the same values in either.
+#pragma once
+#include <math.h>
+
+#include "device.hpp"
+
+namespace wfa {
+
+// ============================================================================
+// finalizers (thread 0 of the last workgroup)
+// ============================================================================
+__device__ __forceinline__ bool fin_ok(double v) { return isfinite(v); }
+
+struct FinInit {
+  Scalars* sc;
+  __device__ void operator()(const double (&s)[2]) const {
+    const double bb = s[0], rr = s[1];
+    sc->bb = bb; sc->rr = rr; sc->rr0 = rr;
+    sc->rho = rr; sc->rho_prev = 1.0; sc->alpha = 1.0; sc->omega = 1.0; sc->beta = 0.0;
+    sc->first = 1; sc->restart = 0; sc->szero = 0;
+    if (!fin_ok(bb) || !fin_ok(rr)) sc->status = ST_NONFINITE;
+    else if (bb == 0.0) sc->status = ST_BZERO;
+    else if (sqrt(rr) <= sc->tol * sqrt(bb)) sc->status = ST_CONV;
+    else if (sc->iter >= sc->maxit) sc->status = ST_NOCONV;
+    else sc->status = ST_RUN;
+  }
+};
+
+struct FinA {
+  Scalars* sc;
+  __device__ void operator()(const double (&s)[1]) const {
+    double sigma = s[0];
+    if (sc->force_bd > 0 && sc->iter + 1 == sc->force_bd) { sigma = 0.0; sc->force_bd = 0; }
+    sc->sigma = sigma;
+    if (!fin_ok(sigma)) sc->status = ST_NONFINITE;
+    else if (sigma == 0.0) sc->restart = 1;
+    else sc->alpha = sc->rho / sigma;
+  }
+};
+
+struct FinB {
+  Scalars* sc;
+  __device__ void operator()(const double (&s)[2]) const {
+    const double ts = s[0], tt = s[1];
+    sc->ts = ts; sc->tt = tt;
+    if (!fin_ok(ts) || !fin_ok(tt)) sc->status = ST_NONFINITE;
+    else if (tt == 0.0) { sc->szero = 1; sc->omega = 0.0; }
+    else sc->omega = ts / tt;
+  }
+};
+
+struct FinC {
+  Scalars* sc;
+  __device__ void operator()(const double (&s)[2]) const {
+    const double rho_new = s[0], rr = s[1];
+    sc->iter += 1;
+    sc->rr = rr;
+    sc->x_zero = 0;
+    if (sc->szero) sc->status = ST_CONV;
+    else if (!fin_ok(rr)) sc->status = ST_NONFINITE;
+    else if (sqrt(rr) <= sc->tol * sqrt(sc->bb)) sc->status = ST_CONV;
+    else if (sc->omega == 0.0) sc->restart = 1;
+    else if (sc->iter >= sc->maxit) sc->status = ST_NOCONV;
+    else if (!fin_ok(rho_new)) sc->status = ST_NONFINITE;
+    else if (rho_new == 0.0) sc->restart = 1;
+    else {
+      sc->beta = (rho_new / sc->rho) * (sc->alpha / sc->omega);
+      sc->rho_prev = sc->rho;
+      sc->rho = rho_new;
+      sc->first = 0;
+    }
+  }
+};
+
+struct FinCgA {
+  Scalars* sc;
+  __device__ void operator()(const double (&s)[1]) const {
+    const double dq = s[0];
+    sc->sigma = dq;
+    if (!fin_ok(dq)) sc->status = ST_NONFINITE;
+    else if (dq <= 0.0) sc->status = ST_BREAKDOWN;
+    else sc->alpha = sc->rho / dq;
+  }
+};
+
+struct FinCgB {
+  Scalars* sc;
+  __device__ void operator()(const double (&s)[1]) const {
+    const double rr = s[0];
+    sc->iter += 1;
+    sc->rr = rr;
+    if (!fin_ok(rr)) sc->status = ST_NONFINITE;
+    else if (sqrt(rr) <= sc->tol * sqrt(sc->bb)) sc->status = ST_CONV;
+    else if (sc->iter >= sc->maxit) sc->status = ST_NOCONV;
+    else {
+      sc->beta = rr / sc->rho;
+      sc->rho = rr;
+      sc->first = 0;
+    }
+  }
+};
+
+// True residual: (r,r), (b,b) into sc.  IR mode: also set up the inner solve.
+struct FinResid {
+  Scalars* sc;
+  Scalars* inner;  // may be null
+  __device__ void operator()(const double (&s)[3]) const {
+    const double rr = s[0], bb = s[1], rho = s[2];
+    sc->rr = rr; sc->bb = bb;
+    if (!fin_ok(rr) || !fin_ok(bb)) sc->status = ST_NONFINITE;
+    else if (bb == 0.0) sc->status = ST_BZERO;
+    else if (sqrt(rr) <= sc->tol * sqrt(bb)) sc->status = ST_CONV;
+    else sc->status = ST_RUN;
+    if (inner) {
+      inner->bb = rho; inner->rr = rho; inner->rr0 = rho;
+      inner->rho = rho; inner->rho_prev = 1.0; inner->alpha = 1.0; inner->omega = 1.0;
+      inner->beta = 0.0; inner->first = 1; inner->restart = 0; inner->szero = 0;
+      inner->x_zero = 1; inner->iter = 0;
+      if (sc->status != ST_RUN) inner->status = ST_CONV;
+      else if (!fin_ok(rho)) inner->status = ST_NONFINITE;
+      else if (rho == 0.0) inner->status = ST_CONV;
+      else inner->status = ST_RUN;
+    }
+  }
+};
+
+struct FinNone {
+  __device__ void operator()(const double (&)[1]) const {}
+};
+
+// ============================================================================
+// stencil phase policies (see march_tile)
+// ============================================================================
+template <typename T>
+struct PhApply {
+  static constexpr int NV = 1;
+  const T* __restrict__ x;
+  T* __restrict__ y;
+  struct Raw { T x; };
+  struct ERaw {};
+  __device__ void bind(const Scalars*) {}
+  __device__ Raw fetch(size_t i) const { return {x[i]}; }
+  __device__ T combine(const Raw& r) const { return r.x; }
+  __device__ ERaw efetch(size_t) const { return {}; }
+  __device__ void epilogue(size_t i, T, T Au, T, uint32_t, const ERaw&, double (&)[NV]) const {
+    y[i] = Au;
+  }
+};
+
+template <typename T, bool CELL>
+struct PhRhs {
+  static constexpr int NV = 1;
+  Op<T> op;
+  const T* __restrict__ x;
+  T* __restrict__ b;
+  struct Raw { T x; };
+  struct ERaw {};
+  __device__ void bind(const Scalars*) {}
+  __device__ Raw fetch(size_t i) const { return {x[i]}; }
+  __device__ T combine(const Raw& r) const { return r.x; }
+  __device__ ERaw efetch(size_t) const { return {}; }
+  __device__ void epilogue(size_t i, T u, T, T kP, uint32_t ins, const ERaw&,
+                           double (&)[NV]) const {
+    b[i] = u + cell_bterm<T, CELL>(op, kP, ins);
+  }
+};
+
+template <typename T, bool CELL, bool FORM_B>
+struct PhInit {
+  static constexpr int NV = 2;
+  Op<T> op;
+  const T* __restrict__ x;
+  const T* __restrict__ b_in;
+  T* __restrict__ b_out;
+  T* __restrict__ r;
+  T* __restrict__ rh;
+  struct Raw { T x; };
+  struct ERaw { T b; };
+  __device__ void bind(const Scalars*) {}
+  __device__ Raw fetch(size_t i) const { return {x[i]}; }
+  __device__ T combine(const Raw& q) const { return q.x; }
+  __device__ ERaw efetch(size_t i) const {
+    if (FORM_B) return {T(0)};
+    return {b_in[i]};
+  }
+  __device__ void epilogue(size_t i, T u, T Au, T kP, uint32_t ins, const ERaw& e,
+                           double (&acc)[NV]) const {
+    const T bv = FORM_B ? u + cell_bterm<T, CELL>(op, kP, ins) : e.b;
+    const T rv = bv - Au;
+    if (FORM_B) b_out[i] = bv;
+    r[i] = rv;
+    rh[i] = rv;
+    acc[0] += (double)bv * (double)bv;
+    acc[1] += (double)rv * (double)rv;
+  }
+};
+
+template <typename T>
+struct PhA {
+  static constexpr int NV = 1;
+  const T* __restrict__ r;
+  const T* __restrict__ p;
+  const T* __restrict__ v;
+  T* __restrict__ p_out;
+  T* __restrict__ v_out;
+  const T* __restrict__ rh;
+  T beta, omega;
+  int first;
+  struct Raw { T r, p, v; };
+  struct ERaw { T rh; };
+  __device__ void bind(const Scalars* sc) {
+    beta = (T)sc->beta;
+    omega = (T)sc->omega;
+    first = sc->first;
+  }
+  __device__ Raw fetch(size_t i) const {
+    if (first) return {r[i], T(0), T(0)};
+    return {r[i], p[i], v[i]};
+  }
+  __device__ T combine(const Raw& q) const {
+    return first ? q.r : q.r + beta * (q.p - omega * q.v);
+  }
+  __device__ ERaw efetch(size_t i) const { return {rh[i]}; }
+  __device__ void epilogue(size_t i, T u, T Au, T, uint32_t, const ERaw& e,
+                           double (&acc)[NV]) const {
+    p_out[i] = u;
+    v_out[i] = Au;
+    acc[0] += (double)e.rh * (double)Au;
+  }
+};
+
+template <typename T>
+struct PhB {
+  static constexpr int NV = 2;
+  const T* __restrict__ r;
+  const T* __restrict__ v;
+  T* __restrict__ t;
+  T alpha;
+  struct Raw { T r, v; };
+  struct ERaw {};
+  __device__ void bind(const Scalars* sc) { alpha = (T)sc->alpha; }
+  __device__ Raw fetch(size_t i) const { return {r[i], v[i]}; }
+  __device__ T combine(const Raw& q) const { return q.r - alpha * q.v; }
+  __device__ ERaw efetch(size_t) const { return {}; }
+  __device__ void epilogue(size_t i, T s, T Au, T, uint32_t, const ERaw&,
+                           double (&acc)[NV]) const {
+    t[i] = Au;
+    acc[0] += (double)Au * (double)s;
+    acc[1] += (double)Au * (double)Au;
+  }
+};
+
+template <typename T>
+struct PhCgA {
+  static constexpr int NV = 1;
+  const T* __restrict__ r;
+  const T* __restrict__ d;
+  T* __restrict__ d_out;
+  T* __restrict__ q;
+  T beta;
+  int first;
+  struct Raw { T r, d; };
+  struct ERaw {};
+  __device__ void bind(const Scalars* sc) {
+    beta = (T)sc->beta;
+    first = sc->first;
+  }
+  __device__ Raw fetch(size_t i) const {
+    if (first) return {r[i], T(0)};
+    return {r[i], d[i]};
+  }
+  __device__ T combine(const Raw& z) const { return first ? z.r : z.r + beta * z.d; }
+  __device__ ERaw efetch(size_t) const { return {}; }
+  __device__ void epilogue(size_t i, T u, T Au, T, uint32_t, const ERaw&,
+                           double (&acc)[NV]) const {
+    d_out[i] = u;
+    q[i] = Au;
+    acc[0] += (double)u * (double)Au;
+  }
+};
+
+// FP64 residual of Tin fields (mode 0: norms only; mode 1: also emit the
+// scaled FP32 residual for the inner solve of iterative refinement).
+template <typename Tin>
+struct PhResid {
+  static constexpr int NV = 3;
+  const Tin* __restrict__ x;
+  const Tin* __restrict__ b;
+  float* __restrict__ r32;
+  float* __restrict__ rh32;
+  double scale;
+  int emit;
+  struct Raw { double x; };
+  struct ERaw { double b; };
+  __device__ void bind(const Scalars* sc) { scale = sc->scale; }
+  __device__ Raw fetch(size_t i) const { return {(double)x[i]}; }
+  __device__ double combine(const Raw& q) const { return q.x; }
+  __device__ ERaw efetch(size_t i) const { return {(double)b[i]}; }
+  __device__ void epilogue(size_t i, double, double Au, double, uint32_t, const ERaw& e,
+                           double (&acc)[NV]) const {
+    const double rv = e.b - Au;
+    acc[0] += rv * rv;
+    acc[1] += e.b * e.b;
+    if (emit) {
+      const float r32v = (float)(rv * scale);
+      r32[i] = r32v;
+      rh32[i] = r32v;
+      acc[2] += (double)r32v * (double)r32v;
+    }
+  }
+};
+
+// ============================================================================
+// pointwise passes: the range of elements one workgroup of a `blocks`-wide
+// launch covers (the same split in single-solve and batched launches)
+// ============================================================================
+template <typename T>
+__device__ __forceinline__ void phase_c_range(size_t n, int blk, int blocks, T* __restrict__ x,
+                                              const T* __restrict__ p, T* __restrict__ r,
+                                              const T* __restrict__ v, const T* __restrict__ t,
+                                              const T* __restrict__ rh, const Scalars* sc,
+                                              double (&acc)[2]) {
+  const T alpha = (T)sc->alpha, omega = (T)sc->omega;
+  const bool xz = sc->x_zero != 0;
+  const size_t stride = (size_t)blocks * kThreads;
+  for (size_t e = (size_t)blk * kThreads + threadIdx.x; e < n; e += stride) {
+    const T s = r[e] - alpha * v[e];
+    const T xo = xz ? T(0) : x[e];
+    x[e] = xo + alpha * p[e] + omega * s;
+    const T rn = s - omega * t[e];
+    r[e] = rn;
+    acc[0] += (double)rh[e] * (double)rn;
+    acc[1] += (double)rn * (double)rn;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void cg_b_range(size_t n, int blk, int blocks, T* __restrict__ x,
+                                           const T* __restrict__ d, T* __restrict__ r,
+                                           const T* __restrict__ q, const Scalars* sc,
+                                           double (&acc)[1]) {
+  const T alpha = (T)sc->alpha;
+  const size_t stride = (size_t)blocks * kThreads;
+  for (size_t e = (size_t)blk * kThreads + threadIdx.x; e < n; e += stride) {
+    x[e] += alpha * d[e];
+    const T rn = r[e] - alpha * q[e];
+    r[e] = rn;
+    acc[0] += (double)rn * (double)rn;
+  }
+}
+
+}  // namespace wfa

@@ -1,0 +1,605 @@
+// Continuous-batching server: many backward-Euler solves resident in one
+// caller-provided HBM arena, advanced together by batched launches.
+//
+// A host worker thread owns the GPU side.  Each round it
+//   1. admits queued requests in arrival order while a slot is free and the
+//      arena can hold the request's Krylov workspace;
+//   2. starts new requests (right-hand side + first residual) and refines
+//      requests whose inner solve ended (FP64 update + FP64 residual);
+//   3. launches `chunk` batched BiCGStab iterations over every resident
+//      solve (finished or paused solves are skipped on the device);
+//   4. reads all slots' device scalar blocks with one copy and retires,
+//      refines or restarts requests.
+// A request's arithmetic never depends on its neighbours (tiles, partial
+// sums, reduction order and decisions are per solve), so its result is the
+// same alone and in any mix.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <vector>
+
+#include "batched.hpp"
+#include "host.hpp"
+#include "internal.hpp"
+#include "wfa.h"
+
+using namespace wfa;
+
+namespace {
+
+constexpr int kScalarsPerSlot = 4;
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// First-fit allocator over [0, size) with coalescing free list.
+struct Heap {
+  std::map<size_t, size_t> free_;  // offset -> length
+  size_t size = 0;
+  void init(size_t n) { size = n; free_.clear(); if (n) free_[0] = n; }
+  bool alloc(size_t n, size_t* off) {
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= n) {
+        *off = it->first;
+        const size_t rest = it->second - n;
+        const size_t o = it->first + n;
+        free_.erase(it);
+        if (rest) free_[o] = rest;
+        return true;
+      }
+    }
+    return false;
+  }
+  void release(size_t off, size_t n) {
+    auto it = free_.emplace(off, n).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+};
+
+enum Phase { Q_QUEUED, R_START, R_ITER, R_REFINE, R_FINAL, R_DONE };
+
+struct Request {
+  uint64_t ticket;
+  int nx, ny, nz;
+  wfa_coeffs c;
+  void* T;
+  double tol;
+  int maxit;
+  Phase phase = Q_QUEUED;
+  int slot = -1;
+  size_t off = 0, bytes = 0;
+  wfa_grid g{};
+  int total_it = 0, refinements = 0, restarts = 0;
+  double scale = 1.0;
+  double last_rec = 0.0;
+  double t_submit = 0.0, t_done = 0.0;
+  wfa_solve_info info{};
+  int code = WFA_PENDING;
+};
+
+}  // namespace
+
+struct wfa_server {
+  char* arena;
+  size_t arena_bytes;
+  int max_slots;
+  hipStream_t stream;
+  // device regions inside the arena
+  Scalars* slot_sc;          // max_slots * kScalarsPerSlot
+  SolveDesc<float>* d32;     // max_slots
+  SolveDesc<double>* d64;    // max_slots
+  int* bases;                // 4 * (max_slots + 1)
+  size_t heap_base;
+  Heap heap;
+  // host mirrors
+  std::vector<Scalars> h_sc;
+  std::vector<SolveDesc<float>> h_d32;
+  std::vector<SolveDesc<double>> h_d64;
+  std::vector<int> h_bases;
+  // requests
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<Request*> queue;
+  std::map<uint64_t, Request*> reqs;
+  std::vector<Request*> slots;
+  uint64_t next_ticket = 1;
+  int inflight = 0;  // queued + resident
+  bool stop = false;
+  int worker_error = WFA_OK;
+  char worker_msg[256] = "";
+  int parity32 = 0, parity64 = 0;
+  int chunk = 4;
+  std::thread worker;
+};
+
+namespace {
+
+bool is_f32_batch(const Request* r) { return r->c.precision != WFA_F64; }
+
+// Workspace bytes one request needs from the heap.
+size_t request_bytes(int nx, int ny, int nz, int precision) {
+  return align256(wfa_workspace_bytes(nx, ny, nz, precision));
+}
+
+int fail(wfa_server* sv, const char* what, hipError_t e) {
+  snprintf(sv->worker_msg, sizeof sv->worker_msg, "%s: %s", what, hipGetErrorString(e));
+  sv->worker_error = WFA_ERR_HIP;
+  return WFA_ERR_HIP;
+}
+
+Scalars fresh(double tol, int maxit) {
+  Scalars h{};
+  h.tol = tol;
+  h.maxit = maxit;
+  h.scale = 1.0;
+  h.inv_scale = 1.0;
+  h.status = ST_RUN;
+  return h;
+}
+
+template <typename T>
+SolveDesc<T> make_desc(Request* r, T* x) {
+  wfa_grid& g = r->g;
+  SolveDesc<T> d{};
+  const Tiling& tl = (sizeof(T) == 4 && g.prec == WFA_F32_IR64) ? g.tl32 : g.tl;
+  d.geo = tl.geo;
+  if constexpr (sizeof(T) == 4) d.op = g.op32; else d.op = g.op64;
+  d.kappa = (const float*)g.c.kappa;
+  T** v = (T**)g.vec;
+  d.x = x;
+  d.r = v[0]; d.rh = v[1]; d.t = v[2]; d.p0 = v[3]; d.p1 = v[4]; d.v0 = v[5]; d.v1 = v[6];
+  d.partials = g.partials;
+  d.sc = g.prec == WFA_F32_IR64 ? g.sc_in : g.sc;
+  d.n = g.n;
+  d.cell = g.c.mode == WFA_COEF_CELL;
+  d.pw_blocks = tl.pw_blocks;
+  return d;
+}
+
+// Start a just-admitted request: right-hand side and first residual (IR)
+// or the BiCGStab initialisation (plain).
+int start_request(wfa_server* sv, Request* r) {
+  wfa_grid& g = r->g;
+  hipStream_t s = sv->stream;
+  if (g.prec == WFA_F32_IR64) {
+    Scalars ho = fresh(r->tol, r->maxit), hi = fresh(1e-4, r->maxit);
+    sv->h_sc[r->slot * kScalarsPerSlot + 0] = ho;
+    sv->h_sc[r->slot * kScalarsPerSlot + 1] = hi;
+    hipMemcpyAsync(g.sc, &sv->h_sc[r->slot * kScalarsPerSlot], 2 * sizeof(Scalars),
+                   hipMemcpyHostToDevice, s);
+    Launch<double> L{g.tl, g.op64, g.c.mode == WFA_COEF_CELL, (const float*)g.c.kappa,
+                     g.partials, g.sc, s};
+    launch_rhs<double>(L, (const double*)r->T, g.b64);
+    float** v = (float**)g.vec;
+    launch_residual<double>(L, (const double*)r->T, g.b64, v[0], v[1], g.sc_in, 1);
+  } else {
+    Scalars h = fresh(r->tol, r->maxit);
+    sv->h_sc[r->slot * kScalarsPerSlot] = h;
+    hipMemcpyAsync(g.sc, &sv->h_sc[r->slot * kScalarsPerSlot], sizeof(Scalars),
+                   hipMemcpyHostToDevice, s);
+    if (g.prec == WFA_F64) {
+      Launch<double> L{g.tl, g.op64, g.c.mode == WFA_COEF_CELL, (const float*)g.c.kappa,
+                       g.partials, g.sc, s};
+      double** v = (double**)g.vec;
+      launch_init<double>(L, true, (double*)r->T, nullptr, v[7], v[0], v[1]);
+    } else {
+      Launch<float> L{g.tl, g.op32, g.c.mode == WFA_COEF_CELL, (const float*)g.c.kappa,
+                      g.partials, g.sc, s};
+      float** v = (float**)g.vec;
+      launch_init<float>(L, true, (float*)r->T, nullptr, v[7], v[0], v[1]);
+    }
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(sv, "start", e);
+  r->phase = R_ITER;
+  return WFA_OK;
+}
+
+// IR: apply the inner correction and compute the next FP64 residual.
+int refine_request(wfa_server* sv, Request* r, double scale_next) {
+  wfa_grid& g = r->g;
+  hipStream_t s = sv->stream;
+  launch_promote(g.n, g.tl.pw_blocks, (double*)r->T, g.d32, g.sc_in, s);
+  Scalars ho = fresh(r->tol, r->maxit);
+  ho.scale = scale_next; ho.inv_scale = 1.0 / scale_next;
+  Scalars hi = fresh(1e-4, r->maxit - r->total_it);
+  hi.scale = scale_next; hi.inv_scale = 1.0 / scale_next;
+  sv->h_sc[r->slot * kScalarsPerSlot + 0] = ho;
+  sv->h_sc[r->slot * kScalarsPerSlot + 1] = hi;
+  hipMemcpyAsync(g.sc, &sv->h_sc[r->slot * kScalarsPerSlot], 2 * sizeof(Scalars),
+                 hipMemcpyHostToDevice, s);
+  Launch<double> L{g.tl, g.op64, g.c.mode == WFA_COEF_CELL, (const float*)g.c.kappa,
+                   g.partials, g.sc, s};
+  float** v = (float**)g.vec;
+  launch_residual<double>(L, (const double*)r->T, g.b64, v[0], v[1], g.sc_in, 1);
+  r->scale = scale_next;
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(sv, "refine", e);
+  r->phase = R_ITER;
+  return WFA_OK;
+}
+
+// Plain precisions: FP64 true residual of the final iterate into sc_aux.
+int final_residual(wfa_server* sv, Request* r) {
+  wfa_grid& g = r->g;
+  hipStream_t s = sv->stream;
+  sv->h_sc[r->slot * kScalarsPerSlot + 2] = fresh(1.0, 1);
+  hipMemcpyAsync(g.sc_aux, &sv->h_sc[r->slot * kScalarsPerSlot + 2], sizeof(Scalars),
+                 hipMemcpyHostToDevice, s);
+  Launch<double> L{g.tl, g.op64, g.c.mode == WFA_COEF_CELL, (const float*)g.c.kappa,
+                   g.partials, g.sc_aux, s};
+  void** v = g.vec;
+  if (g.prec == WFA_F64)
+    launch_residual<double>(L, (const double*)r->T, (const double*)v[7], nullptr, nullptr, nullptr, 0);
+  else
+    launch_residual<float>(L, (const float*)r->T, (const float*)v[7], nullptr, nullptr, nullptr, 0);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(sv, "final residual", e);
+  r->phase = R_FINAL;
+  return WFA_OK;
+}
+
+void retire(wfa_server* sv, Request* r, int code, double rel_true) {
+  r->t_done = now_s();
+  r->code = code;
+  r->info.status = code;
+  r->info.iterations = r->total_it;
+  r->info.refinements = r->refinements;
+  r->info.restarts = r->restarts;
+  r->info.rel_res_recursive = r->last_rec;
+  r->info.rel_res_true = rel_true;
+  r->info.seconds = r->t_done - r->t_submit;
+  r->phase = R_DONE;
+  sv->heap.release(r->off, r->bytes);
+  sv->slots[r->slot] = nullptr;
+  r->slot = -1;
+  --sv->inflight;
+}
+
+int code_of(int st) {
+  switch (st) {
+    case ST_CONV: case ST_BZERO: return WFA_OK;
+    case ST_NOCONV: return WFA_ERR_NOCONV;
+    case ST_NONFINITE: return WFA_ERR_NONFINITE;
+    case ST_BREAKDOWN: return WFA_ERR_BREAKDOWN;
+    default: return WFA_ERR_NOCONV;
+  }
+}
+
+// Inspect one resident request after a round (scalars already on the host).
+int advance(wfa_server* sv, Request* r) {
+  const Scalars* hs = &sv->h_sc[r->slot * kScalarsPerSlot];
+  wfa_grid& g = r->g;
+  if (r->phase == R_FINAL) {
+    // IR: the outer block holds the FP64 residual of the last refinement;
+    // plain precisions: the true residual went to the aux block
+    const Scalars& a = g.prec == WFA_F32_IR64 ? hs[0] : hs[2];
+    const double rel = a.bb > 0.0 ? sqrt(a.rr / a.bb) : sqrt(a.rr);
+    int code = r->code;
+    if (g.prec == WFA_F32_IR64 && a.status == ST_CONV) code = WFA_OK;
+    retire(sv, r, code, rel);
+    return WFA_OK;
+  }
+  if (g.prec == WFA_F32_IR64) {
+    const Scalars& o = hs[0];
+    const Scalars& in = hs[1];
+    if (o.status != ST_RUN) {
+      if (o.status == ST_BZERO) launch_fill<double>(g.n, (double*)r->T, 0.0, sv->stream);
+      retire(sv, r, code_of(o.status), o.bb > 0.0 ? sqrt(o.rr / o.bb) : 0.0);
+      return WFA_OK;
+    }
+    if (in.status == ST_RUN && !in.restart) return WFA_OK;  // still iterating
+    r->total_it += in.iter;
+    r->last_rec = in.bb > 0.0 ? sqrt(in.rr / in.bb) : 0.0;
+    if (in.restart) ++r->restarts;
+    if (in.status == ST_NONFINITE) {
+      retire(sv, r, WFA_ERR_NONFINITE, NAN);
+      return WFA_OK;
+    }
+    if (r->restarts > WFA_MAX_RESTARTS) {
+      retire(sv, r, WFA_ERR_BREAKDOWN, sqrt(o.rr / o.bb));
+      return WFA_OK;
+    }
+    if (in.iter > 0) ++r->refinements;
+    if (r->refinements >= 30 || r->total_it >= r->maxit) {
+      // apply the last correction, then report the FP64 residual as NOCONV
+      r->code = WFA_ERR_NOCONV;
+    }
+    const double rms = sqrt(o.rr / (double)g.n);
+    const double scale = (rms > 0.0 && isfinite(rms)) ? ldexp(1.0, -(int)lround(log2(rms))) : 1.0;
+    r->phase = R_REFINE;
+    int rc = refine_request(sv, r, scale);
+    if (rc) return rc;
+    if (r->code == WFA_ERR_NOCONV) r->phase = R_FINAL;  // read the residual next round
+    return WFA_OK;
+  }
+  // plain FP64 / FP32 BiCGStab
+  const Scalars& h = hs[0];
+  if (h.status == ST_RUN && !h.restart) return WFA_OK;
+  if (h.status == ST_RUN && h.restart) {
+    if (++r->restarts > WFA_MAX_RESTARTS) {
+      r->total_it = h.iter;
+      r->code = WFA_ERR_BREAKDOWN;
+      return final_residual(sv, r);
+    }
+    if (g.prec == WFA_F64) {
+      Launch<double> L{g.tl, g.op64, g.c.mode == WFA_COEF_CELL, (const float*)g.c.kappa,
+                       g.partials, g.sc, sv->stream};
+      double** v = (double**)g.vec;
+      launch_init<double>(L, false, (double*)r->T, v[7], nullptr, v[0], v[1]);
+    } else {
+      Launch<float> L{g.tl, g.op32, g.c.mode == WFA_COEF_CELL, (const float*)g.c.kappa,
+                      g.partials, g.sc, sv->stream};
+      float** v = (float**)g.vec;
+      launch_init<float>(L, false, (float*)r->T, v[7], nullptr, v[0], v[1]);
+    }
+    return WFA_OK;
+  }
+  r->total_it = h.iter;
+  r->last_rec = h.bb > 0.0 ? sqrt(h.rr / h.bb) : 0.0;
+  r->code = code_of(h.status);
+  if (h.status == ST_BZERO) {
+    if (g.prec == WFA_F64) launch_fill<double>(g.n, (double*)r->T, 0.0, sv->stream);
+    else launch_fill<float>(g.n, (float*)r->T, 0.0f, sv->stream);
+  }
+  return final_residual(sv, r);
+}
+
+// Rebuild the batched work tables of the resident set.
+void build_tables(wfa_server* sv, int* n32, int* tiles32, int* pw32, int* n64, int* tiles64,
+                  int* pw64) {
+  const int S = sv->max_slots;
+  int a = 0, b = 0, t32 = 0, p32 = 0, t64 = 0, p64 = 0;
+  int* tb32 = &sv->h_bases[0];
+  int* pb32 = &sv->h_bases[S + 1];
+  int* tb64 = &sv->h_bases[2 * (S + 1)];
+  int* pb64 = &sv->h_bases[3 * (S + 1)];
+  for (int s = 0; s < S; ++s) {
+    Request* r = sv->slots[s];
+    if (!r || (r->phase != R_ITER && r->phase != R_REFINE)) continue;
+    if (is_f32_batch(r)) {
+      float* x = r->g.prec == WFA_F32_IR64 ? r->g.d32 : (float*)r->T;
+      sv->h_d32[a] = make_desc<float>(r, x);
+      tb32[a] = t32; pb32[a] = p32;
+      t32 += sv->h_d32[a].geo.ntiles; p32 += sv->h_d32[a].pw_blocks;
+      ++a;
+    } else {
+      sv->h_d64[b] = make_desc<double>(r, (double*)r->T);
+      tb64[b] = t64; pb64[b] = p64;
+      t64 += sv->h_d64[b].geo.ntiles; p64 += sv->h_d64[b].pw_blocks;
+      ++b;
+    }
+  }
+  tb32[a] = t32; pb32[a] = p32; tb64[b] = t64; pb64[b] = p64;
+  *n32 = a; *tiles32 = t32; *pw32 = p32; *n64 = b; *tiles64 = t64; *pw64 = p64;
+}
+
+void worker_main(wfa_server* sv) {
+  std::vector<Request*> admitted;
+  while (true) {
+    admitted.clear();
+    {
+      std::unique_lock<std::mutex> lk(sv->mu);
+      // admission in arrival order: slot + arena space
+      while (!sv->queue.empty()) {
+        Request* r = sv->queue.front();
+        int slot = -1;
+        for (int s = 0; s < sv->max_slots; ++s)
+          if (!sv->slots[s]) { slot = s; break; }
+        size_t off = 0;
+        if (slot < 0 || !sv->heap.alloc(r->bytes, &off)) break;
+        sv->queue.pop_front();
+        r->slot = slot;
+        r->off = off;
+        sv->slots[slot] = r;
+        admitted.push_back(r);
+      }
+      bool any = false;
+      for (auto* r : sv->slots) any = any || r != nullptr;
+      if (!any && admitted.empty()) {
+        if (sv->stop) break;
+        sv->cv_work.wait(lk);
+        continue;
+      }
+    }
+    int rc = WFA_OK;
+    for (Request* r : admitted) {
+      char* ws = sv->arena + sv->heap_base + r->off;
+      grid_setup(&r->g, r->nx, r->ny, r->nz, &r->c, ws);
+      // the slot's scalar blocks live in the server's contiguous region
+      r->g.sc = sv->slot_sc + r->slot * kScalarsPerSlot;
+      r->g.sc_in = r->g.sc + 1;
+      r->g.sc_aux = r->g.sc + 2;
+      if ((rc = start_request(sv, r))) break;
+    }
+    int n32 = 0, t32 = 0, p32 = 0, n64 = 0, t64 = 0, p64 = 0;
+    if (!rc) {
+      build_tables(sv, &n32, &t32, &p32, &n64, &t64, &p64);
+      const int S = sv->max_slots;
+      hipMemcpyAsync(sv->d32, sv->h_d32.data(), sizeof(SolveDesc<float>) * std::max(n32, 1),
+                     hipMemcpyHostToDevice, sv->stream);
+      hipMemcpyAsync(sv->d64, sv->h_d64.data(), sizeof(SolveDesc<double>) * std::max(n64, 1),
+                     hipMemcpyHostToDevice, sv->stream);
+      hipMemcpyAsync(sv->bases, sv->h_bases.data(), sizeof(int) * 4 * (S + 1),
+                     hipMemcpyHostToDevice, sv->stream);
+      for (int q = 0; q < sv->chunk; ++q) {
+        if (n32) {
+          launch_batch_iteration<float>(sv->d32, sv->bases, t32, sv->bases + (S + 1), p32, n32,
+                                        sv->parity32, sv->stream);
+          sv->parity32 ^= 1;
+        }
+        if (n64) {
+          launch_batch_iteration<double>(sv->d64, sv->bases + 2 * (S + 1), t64,
+                                         sv->bases + 3 * (S + 1), p64, n64, sv->parity64,
+                                         sv->stream);
+          sv->parity64 ^= 1;
+        }
+      }
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) rc = fail(sv, "batched iteration", e);
+    }
+    if (!rc) {
+      hipError_t e = hipMemcpyAsync(sv->h_sc.data(), sv->slot_sc,
+                                    sizeof(Scalars) * kScalarsPerSlot * sv->max_slots,
+                                    hipMemcpyDeviceToHost, sv->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(sv->stream);
+      if (e != hipSuccess) rc = fail(sv, "scalar readback", e);
+    }
+    std::unique_lock<std::mutex> lk(sv->mu);
+    if (rc) {
+      // fail every resident and queued request; the server stays unusable
+      for (auto*& r : sv->slots)
+        if (r) { r->code = rc; r->phase = R_DONE; r->t_done = now_s(); r = nullptr; }
+      for (auto* r : sv->queue) { r->code = rc; r->phase = R_DONE; r->t_done = now_s(); }
+      sv->queue.clear();
+      sv->inflight = 0;
+      sv->cv_done.notify_all();
+      break;
+    }
+    for (int s = 0; s < sv->max_slots; ++s) {
+      Request* r = sv->slots[s];
+      if (!r || r->phase == R_START) continue;
+      if ((rc = advance(sv, r))) break;
+    }
+    sv->cv_done.notify_all();
+    if (rc) break;
+  }
+}
+
+}  // namespace
+
+extern "C" int wfa_server_create(void* arena, size_t arena_bytes, int max_slots, void* stream,
+                                 wfa_server** out) {
+  if (!out) return set_error(WFA_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!arena || ((uintptr_t)arena & 255)) return set_error(WFA_ERR_INVALID, "arena must be non-NULL and 256-byte aligned");
+  if (max_slots < 1 || max_slots > 4096) return set_error(WFA_ERR_INVALID, "max_slots must be in [1, 4096]");
+  const size_t sc_bytes = align256(sizeof(Scalars) * kScalarsPerSlot * max_slots);
+  const size_t d32_bytes = align256(sizeof(SolveDesc<float>) * max_slots);
+  const size_t d64_bytes = align256(sizeof(SolveDesc<double>) * max_slots);
+  const size_t b_bytes = align256(sizeof(int) * 4 * (max_slots + 1));
+  const size_t meta = sc_bytes + d32_bytes + d64_bytes + b_bytes;
+  if (arena_bytes <= meta) return set_error(WFA_ERR_NOMEM, "arena smaller than the slot tables");
+  wfa_server* sv = new (std::nothrow) wfa_server();
+  if (!sv) return set_error(WFA_ERR_NOMEM, "host allocation failed");
+  sv->arena = (char*)arena;
+  sv->arena_bytes = arena_bytes;
+  sv->max_slots = max_slots;
+  sv->stream = (hipStream_t)stream;
+  sv->slot_sc = (Scalars*)sv->arena;
+  sv->d32 = (SolveDesc<float>*)(sv->arena + sc_bytes);
+  sv->d64 = (SolveDesc<double>*)(sv->arena + sc_bytes + d32_bytes);
+  sv->bases = (int*)(sv->arena + sc_bytes + d32_bytes + d64_bytes);
+  sv->heap_base = meta;
+  sv->heap.init(arena_bytes - meta);
+  sv->h_sc.assign((size_t)kScalarsPerSlot * max_slots, Scalars{});
+  sv->h_d32.assign(max_slots, SolveDesc<float>{});
+  sv->h_d64.assign(max_slots, SolveDesc<double>{});
+  sv->h_bases.assign(4 * (max_slots + 1), 0);
+  sv->slots.assign(max_slots, nullptr);
+  if (const char* c = getenv("WFA_SERVER_CHUNK")) {
+    const int v = atoi(c);
+    if (v >= 1 && v <= 1024) sv->chunk = v;
+  }
+  try {
+    sv->worker = std::thread(worker_main, sv);
+  } catch (...) {
+    delete sv;
+    return set_error(WFA_ERR_NOMEM, "could not start the server thread");
+  }
+  *out = sv;
+  return WFA_OK;
+}
+
+extern "C" int wfa_submit(wfa_server* sv, int nx, int ny, int nz, const wfa_coeffs* c, void* T,
+                          double tol, int maxit, uint64_t* ticket) {
+  if (!sv || !ticket) return set_error(WFA_ERR_INVALID, "NULL argument");
+  int rc = validate_coeffs(nx, ny, nz, c);
+  if (rc) return rc;
+  if (!T) return set_error(WFA_ERR_INVALID, "T is NULL");
+  if (!(tol > 0.0) || !isfinite(tol) || maxit < 1) return set_error(WFA_ERR_INVALID, "bad tol or maxit");
+  const size_t bytes = request_bytes(nx, ny, nz, c->precision);
+  if (bytes > sv->heap.size)
+    return set_error(WFA_ERR_NOMEM, "request needs %zu bytes, arena holds %zu", bytes, sv->heap.size);
+  Request* r = new (std::nothrow) Request();
+  if (!r) return set_error(WFA_ERR_NOMEM, "host allocation failed");
+  r->nx = nx; r->ny = ny; r->nz = nz;
+  r->c = *c;
+  r->T = T;
+  r->tol = tol;
+  r->maxit = maxit;
+  r->bytes = bytes;
+  r->t_submit = now_s();
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (sv->worker_error) {
+      delete r;
+      return set_error(sv->worker_error, "server failed: %s", sv->worker_msg);
+    }
+    r->ticket = sv->next_ticket++;
+    sv->reqs[r->ticket] = r;
+    sv->queue.push_back(r);
+    ++sv->inflight;
+  }
+  sv->cv_work.notify_one();
+  *ticket = r->ticket;
+  return WFA_OK;
+}
+
+extern "C" int wfa_poll(wfa_server* sv, uint64_t ticket, wfa_solve_info* info) {
+  if (!sv) return set_error(WFA_ERR_INVALID, "server is NULL");
+  std::lock_guard<std::mutex> lk(sv->mu);
+  auto it = sv->reqs.find(ticket);
+  if (it == sv->reqs.end()) return set_error(WFA_ERR_INVALID, "unknown ticket %llu", (unsigned long long)ticket);
+  Request* r = it->second;
+  if (r->phase != R_DONE) return WFA_PENDING;
+  if (info) *info = r->info;
+  if (r->code < 0 && r->code == sv->worker_error)
+    set_error(r->code, "server failed: %s", sv->worker_msg);
+  return r->code;
+}
+
+extern "C" int wfa_server_drain(wfa_server* sv) {
+  if (!sv) return set_error(WFA_ERR_INVALID, "server is NULL");
+  std::unique_lock<std::mutex> lk(sv->mu);
+  sv->cv_done.wait(lk, [&] { return sv->inflight == 0 || sv->worker_error != 0; });
+  if (sv->worker_error) return set_error(sv->worker_error, "server failed: %s", sv->worker_msg);
+  return WFA_OK;
+}
+
+extern "C" int wfa_server_destroy(wfa_server* sv) {
+  if (!sv) return set_error(WFA_ERR_INVALID, "server is NULL");
+  {
+    std::unique_lock<std::mutex> lk(sv->mu);
+    sv->cv_done.wait(lk, [&] { return sv->inflight == 0 || sv->worker_error != 0; });
+    sv->stop = true;
+  }
+  sv->cv_work.notify_all();
+  if (sv->worker.joinable()) sv->worker.join();
+  for (auto& kv : sv->reqs) delete kv.second;
+  delete sv;
+  return WFA_OK;
+}

@@ -1,0 +1,108 @@
+"""Serving: continuous batching of many solves in one HBM arena.
+
+Each request is one backward-Euler step of the 32^3 heat physics on its own
+grid (dims from {32,...,192}), FP32 BiCGStab inside FP64 refinement to 1e-10.
+A request's result must be bitwise the same alone, in a mix, and through the
+single-grid entry point, and its FP64 residual (evaluated by the oracle's
+operator) must meet the tolerance.
+"""
+import numpy as np
+import pytest
+
+from paper_2209_13768_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+DIMS = [(32, 48, 32), (64, 32, 48), (48, 48, 48), (32, 32, 96), (96, 64, 32), (40, 36, 28)]
+
+
+@pytest.fixture(scope="module")
+def wfa():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2209_13768_amd import wfa as w
+    w.lib()
+    return w
+
+
+def _requests(dims=DIMS):
+    return [inputs.Request(q, 0.0, *d) for q, d in enumerate(dims)]
+
+
+def _serve(wfa, reqs, budget, slots, precision=None, tol=1e-10):
+    import torch
+    sv = wfa.Server(budget, max_slots=slots)
+    outs, tickets = [], []
+    for q, rq in enumerate(reqs):
+        prob = rq.problem()
+        prec = precision[q] if isinstance(precision, list) else (precision or wfa.F32_IR64)
+        dtype = torch.float32 if prec == wfa.F32 else torch.float64
+        T = torch.from_numpy(prob.T0).to("cuda", dtype)
+        tickets.append(sv.submit_problem(prob, T, precision=prec, tol=tol, maxit=20000))
+        outs.append(T)
+    sv.drain()
+    infos = []
+    for t in tickets:
+        code, info = sv.poll(t)
+        assert code == wfa.OK, (code, info)
+        infos.append(info)
+    sv.close()
+    return [o.cpu().double().numpy() for o in outs], infos
+
+
+def test_alone_vs_mix_bitwise(wfa, oracle_mod):
+    reqs = _requests()
+    budget = 1 << 30
+    mix, infos = _serve(wfa, reqs, budget, slots=8)
+    alone = [_serve(wfa, [r], budget, slots=1)[0][0] for r in reqs]
+    for a, m, rq, info in zip(alone, mix, reqs, infos):
+        assert np.array_equal(a, m), rq
+        prob = rq.problem()
+        o = oracle_mod.Oracle(prob)
+        assert o.true_relres(o.rhs(prob.T0), m) <= 1e-10
+        assert info.rel_res_true <= 1e-10 and info.refinements >= 1
+
+
+def test_server_matches_single_grid_path(wfa):
+    import torch
+    reqs = _requests(DIMS[:3])
+    served, infos = _serve(wfa, reqs, 1 << 30, slots=4)
+    for rq, s, info in zip(reqs, served, infos):
+        prob = rq.problem()
+        g = wfa.Grid.from_problem(prob, precision=wfa.F32_IR64)
+        T = g.field(prob.T0)
+        gi = g.timestep(T, 1, tol=1e-10, maxit=20000)[0]
+        assert np.array_equal(T.cpu().numpy(), s)
+        assert gi.iterations == info.iterations and gi.refinements == info.refinements
+
+
+def test_small_budget_admits_one_at_a_time(wfa):
+    reqs = _requests(DIMS[:4])
+    need = max(wfa.workspace_bytes(r.nx, r.ny, r.nz, wfa.F32_IR64) for r in reqs)
+    budget = need + (4 << 20)          # room for the slot tables + one workspace
+    small, _ = _serve(wfa, reqs, budget, slots=8)
+    big, _ = _serve(wfa, reqs, 1 << 30, slots=8)
+    for a, b in zip(small, big):
+        assert np.array_equal(a, b)
+
+
+def test_reject_request_larger_than_arena(wfa):
+    import torch
+    sv = wfa.Server(8 << 20, max_slots=2)
+    T = torch.zeros((96, 96, 96), dtype=torch.float64, device="cuda")
+    with pytest.raises(wfa.WfaError) as e:
+        sv.submit(T, h=1 / 97, dt=1e-3)
+    assert e.value.code == wfa.ERR_NOMEM
+    sv.close()
+
+
+def test_mixed_precisions_in_one_server(wfa, oracle_mod):
+    reqs = _requests(DIMS[:4])
+    precs = [wfa.F64, wfa.F32_IR64, wfa.F64, wfa.F32_IR64]
+    mix, infos = _serve(wfa, reqs, 1 << 30, slots=8, precision=precs)
+    for rq, m, p in zip(reqs, mix, precs):
+        alone, _ = _serve(wfa, [rq], 1 << 30, slots=1, precision=[p])
+        assert np.array_equal(alone[0], m)
+        prob = rq.problem()
+        o = oracle_mod.Oracle(prob)
+        assert o.true_relres(o.rhs(prob.T0), m) <= 1e-10
