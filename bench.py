@@ -84,7 +84,7 @@ def main():
     ap.add_argument("--precision", default="f64", choices=["f64", "f32", "f32_ir64"])
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--maxit", type=int, default=20000)
-    ap.add_argument("--cpu-iters", type=int, default=12)
+    ap.add_argument("--cpu-iters", type=int, default=120)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
                     help="time without per-launch events (no roofline)")
@@ -183,6 +183,7 @@ def main():
         "roofline": roofline,
         "kernels": kernels,
         "rel_res_true_max": max(i.rel_res_true for i in infos),
+        "kernel_source_hash": kernel_source_hash(),
     }
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(prob, args.cpu_iters)

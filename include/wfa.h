@@ -166,7 +166,8 @@ enum {
                                   0 = adaptive (default)                       */
   WFA_OPT_IR_INNER_TOL = 6,    /* (value / 1e12) = inner relative tolerance of
                                   WFA_F32_IR64; default 1e-4 * 1e12            */
-  WFA_OPT_ZCHUNK = 7           /* z planes per workgroup; 0 = tuned            */
+  WFA_OPT_ZCHUNK = 7,          /* z planes per workgroup; 0 = default rule     */
+  WFA_OPT_RY = 8               /* rows per wave of a tile (1, 2 or 4); 0 = default */
 };
 int wfa_grid_set_option(wfa_grid* g, int option, int64_t value);
 

@@ -65,7 +65,9 @@ Layout layout_for(int nx, int ny, int nz, int precision) {
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
   L.scalars = take(sizeof(Scalars) * 4);
-  L.partials = take(sizeof(double) * 3 * partial_slots(nx, ny, nz));
+  // one-launch-per-phase: up to 3 values per slot; persistent launches keep
+  // the three phases' partials apart: 3 x tiles + 2 x pointwise blocks
+  L.partials = take(sizeof(double) * (3 * partial_slots(nx, ny, nz) + 2 * 2048));
   if (precision == WFA_F32_IR64) {
     L.b64 = take(8 * n);
     for (int q = 0; q < kVecs; ++q) L.vec[q] = take(4 * n);
@@ -158,8 +160,9 @@ void grid_setup(wfa_grid* g, int nx, int ny, int nz, const wfa_coeffs* c, char* 
   g->zchunk = 0;
   g->ir_inner_tol = 1e-4;
   const int w = g->prec == WFA_F32 ? 4 : 8;
-  g->tl = make_tiling(nx, ny, nz, w, 0);
-  g->tl32 = make_tiling(nx, ny, nz, 4, 0);
+  g->ry = 0;
+  g->tl = make_tiling(nx, ny, nz, w, 0, 0);
+  g->tl32 = make_tiling(nx, ny, nz, 4, 0, 0);
 }
 
 }  // namespace wfa
@@ -217,12 +220,19 @@ extern "C" int wfa_grid_set_option(wfa_grid* g, int option, int64_t value) {
       if (value <= 0) return set_error(WFA_ERR_INVALID, "bad inner tolerance");
       g->ir_inner_tol = (double)value * 1e-12;
       return WFA_OK;
-    case WFA_OPT_ZCHUNK: {
-      if (value < 0 || value > g->nz) return set_error(WFA_ERR_INVALID, "bad z chunk");
-      g->zchunk = (int)value;
+    case WFA_OPT_ZCHUNK:
+    case WFA_OPT_RY: {
+      if (option == WFA_OPT_ZCHUNK) {
+        if (value < 0 || value > g->nz) return set_error(WFA_ERR_INVALID, "bad z chunk");
+        g->zchunk = (int)value;
+      } else {
+        if (value != 0 && value != 1 && value != 2 && value != 4)
+          return set_error(WFA_ERR_INVALID, "rows per wave must be 0, 1, 2 or 4");
+        g->ry = (int)value;
+      }
       const int w = g->prec == WFA_F32 ? 4 : 8;
-      g->tl = make_tiling(g->nx, g->ny, g->nz, w, g->zchunk);
-      g->tl32 = make_tiling(g->nx, g->ny, g->nz, 4, g->zchunk);
+      g->tl = make_tiling(g->nx, g->ny, g->nz, w, g->zchunk, g->ry);
+      g->tl32 = make_tiling(g->nx, g->ny, g->nz, 4, g->zchunk, g->ry);
       return WFA_OK;
     }
     default:
@@ -420,6 +430,37 @@ static int next_chunk(const wfa_grid* g, const Scalars& h, int budget) {
 }
 
 // ---------------------------------------------------------------------------
+// persistent launches
+// ---------------------------------------------------------------------------
+// Grids up to this many cells iterate in one cooperative launch per chunk by
+// default: below it, launch and dependency latency outweighs the three
+// kernel boundaries' cache effects.
+static const size_t kPersistentCells = (size_t)1 << 21;
+
+static bool use_persistent(const wfa_grid* g, const Tiling& tl) {
+  (void)tl;
+  if (g->persistent == 1) return true;
+  if (g->persistent == 0) return false;
+  return g->n <= kPersistentCells;
+}
+
+static GridBarrier* barrier_of(wfa_grid* g) { return (GridBarrier*)(g->sc + 3); }
+
+static int reset_barrier(wfa_grid* g, hipStream_t s) {
+  static const GridBarrier zero{};
+  HIP_TRY(hipMemcpyAsync(barrier_of(g), &zero, sizeof zero, hipMemcpyHostToDevice, s));
+  return WFA_OK;
+}
+
+static int check_barrier(wfa_grid* g, hipStream_t s) {
+  GridBarrier b{};
+  HIP_TRY(hipMemcpyAsync(&b, barrier_of(g), sizeof b, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (b.timeout) return set_error(WFA_ERR_HIP, "persistent launch: grid barrier timed out");
+  return WFA_OK;
+}
+
+// ---------------------------------------------------------------------------
 // BiCGStab (and CG) iteration loops on an initialised scalar block
 // ---------------------------------------------------------------------------
 // Runs iterations until the device status leaves ST_RUN.  A breakdown
@@ -429,8 +470,9 @@ template <typename T>
 static int iterate_bicgstab(wfa_grid* g, const Launch<T>& L, T* x, T* r, T* rh, T** p, T** v,
                             T* t, const T* b, Scalars* h, int* restarts, bool restartable) {
   int par = 0;
-  int rc = read_scalars(g, L.sc, h, L.stream);
+  int rc = use_persistent(g, L.tl) ? reset_barrier(g, L.stream) : WFA_OK;
   if (rc) return rc;
+  if ((rc = read_scalars(g, L.sc, h, L.stream))) return rc;
   while (h->status == ST_RUN) {
     if (h->restart) {
       if (!restartable) return WFA_OK;
@@ -444,6 +486,20 @@ static int iterate_bicgstab(wfa_grid* g, const Launch<T>& L, T* x, T* r, T* rh, 
       continue;
     }
     const int m = next_chunk(g, *h, h->maxit - h->iter);
+    if (use_persistent(g, L.tl)) {
+      hipError_t e;
+      {
+        ProfScope ps(g, WFA_K_PERSISTENT, L.stream);
+        e = launch_persistent_bicgstab<T>(L, x, r, rh, p[0], p[1], v[0], v[1], t, m, par,
+                                          barrier_of(g));
+      }
+      if (e != hipSuccess)
+        return set_error(WFA_ERR_HIP, "persistent launch: %s", hipGetErrorString(e));
+      par ^= (m & 1);
+      if ((rc = read_scalars(g, L.sc, h, L.stream))) return rc;
+      if ((rc = check_barrier(g, L.stream))) return rc;
+      continue;
+    }
     for (int q = 0; q < m; ++q) {
       {
         ProfScope ps(g, WFA_K_PHASE_A, L.stream);

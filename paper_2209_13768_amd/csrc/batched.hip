@@ -73,21 +73,32 @@ k_batch_phase_c(const SolveDesc<T>* __restrict__ descs, const int* __restrict__ 
   publish_and_finalize<2>(acc, blk, d.pw_blocks, d.partials, sc, red, FinC{sc});
 }
 
-template <typename T>
-void launch_batch_iteration(const SolveDesc<T>* descs, const int* tile_bases, int tiles_total,
+template <typename T, int RY>
+static void batch_iteration(const SolveDesc<T>* descs, const int* tile_bases, int tiles_total,
                             const int* pw_bases, int pw_total, int nsolves, int parity,
                             hipStream_t s) {
-  hipLaunchKernelGGL((k_batch_march<T, 4, 0>), dim3(tiles_total), dim3(kThreads), 0, s, descs,
+  hipLaunchKernelGGL((k_batch_march<T, RY, 0>), dim3(tiles_total), dim3(kThreads), 0, s, descs,
                      tile_bases, nsolves, parity);
-  hipLaunchKernelGGL((k_batch_march<T, 4, 1>), dim3(tiles_total), dim3(kThreads), 0, s, descs,
+  hipLaunchKernelGGL((k_batch_march<T, RY, 1>), dim3(tiles_total), dim3(kThreads), 0, s, descs,
                      tile_bases, nsolves, parity);
   hipLaunchKernelGGL((k_batch_phase_c<T>), dim3(pw_total), dim3(kThreads), 0, s, descs, pw_bases,
                      nsolves, parity);
 }
 
+template <typename T>
+void launch_batch_iteration(const SolveDesc<T>* descs, const int* tile_bases, int tiles_total,
+                            const int* pw_bases, int pw_total, int nsolves, int parity, int ry,
+                            hipStream_t s) {
+  switch (ry) {
+    case 1: batch_iteration<T, 1>(descs, tile_bases, tiles_total, pw_bases, pw_total, nsolves, parity, s); break;
+    case 4: batch_iteration<T, 4>(descs, tile_bases, tiles_total, pw_bases, pw_total, nsolves, parity, s); break;
+    default: batch_iteration<T, 2>(descs, tile_bases, tiles_total, pw_bases, pw_total, nsolves, parity, s); break;
+  }
+}
+
 template void launch_batch_iteration<float>(const SolveDesc<float>*, const int*, int, const int*,
-                                            int, int, int, hipStream_t);
+                                            int, int, int, int, hipStream_t);
 template void launch_batch_iteration<double>(const SolveDesc<double>*, const int*, int,
-                                             const int*, int, int, int, hipStream_t);
+                                             const int*, int, int, int, int, hipStream_t);
 
 }  // namespace wfa

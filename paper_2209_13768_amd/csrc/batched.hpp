@@ -22,11 +22,11 @@ struct SolveDesc {
 
 // One BiCGStab iteration (phases A, B, C) of every solve in descs[0..nsolves).
 // tile_bases / pw_bases: prefix sums of the solves' tile and pointwise-block
-// counts (nsolves + 1 entries each, device memory).  The tiling of every
-// solve must use 4 rows per wave.
+// counts (nsolves + 1 entries each, device memory).  Every solve's tiling
+// must use `ry` rows per wave.
 template <typename T>
 void launch_batch_iteration(const SolveDesc<T>* descs, const int* tile_bases, int tiles_total,
-                            const int* pw_bases, int pw_total, int nsolves, int parity,
+                            const int* pw_bases, int pw_total, int nsolves, int parity, int ry,
                             hipStream_t s);
 
 }  // namespace wfa

@@ -45,6 +45,11 @@ struct alignas(64) Scalars {
   int32_t pad[7];
 };
 
+// Grid-wide barrier state of a persistent launch (self-resetting count).
+struct GridBarrier {
+  uint32_t count, gen, timeout, pad;
+};
+
 // ---- geometry and operator constants (kernel arguments, by value) ----------
 struct Geo {
   int nx, ny, nz;
@@ -142,14 +147,28 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* red /*LDS kWa
 }
 
 // Fixed-order sum of partials[q*n + t] over t, by one workgroup; result in
-// thread 0.  Identical for any launch that produced the same partials.
+// thread 0.  Identical for any launch that produced the same partials.  The
+// loads are agent-scope atomics: they read the coherent copy whichever XCD
+// wrote it.
 template <int NV>
-__device__ __forceinline__ void reduce_partials(const double* partials, int n,
-                                                double (&out)[NV], double* red) {
+__device__ __forceinline__ void reduce_partials(double* partials, int n, double (&out)[NV],
+                                                double* red) {
 #pragma unroll
   for (int q = 0; q < NV; ++q) {
+    const double* pq = partials + (size_t)q * n;
     double s = 0.0;
-    for (int t = threadIdx.x; t < n; t += kThreads) s += partials[(size_t)q * n + t];
+    int t = threadIdx.x;
+    // batches of 8 loads in flight, summed in index order
+    for (; t + 7 * kThreads < n; t += 8 * kThreads) {
+      double a[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        a[u] = __hip_atomic_load(pq + t + u * kThreads, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += a[u];
+    }
+    for (; t < n; t += kThreads)
+      s += __hip_atomic_load(pq + t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     out[q] = s;
   }
   block_sum<NV>(out, red);
@@ -157,7 +176,14 @@ __device__ __forceinline__ void reduce_partials(const double* partials, int n,
 
 // Publish this workgroup's partial sums; the last workgroup to arrive
 // reduces all of them in fixed order and calls fin(sums) in thread 0.
-// Release/acquire at agent scope orders the partial stores across XCDs.
+//
+// Cross-XCD ordering without cache-wide fences: the partials are written
+// with agent-scope atomic stores (coherent across the XCDs' L2s), the
+// writer waits for their completion before its arrival increments the
+// counter, and the last workgroup reads them back with agent-scope atomic
+// loads.  A release/acquire fence would instead write back and invalidate
+// the whole L2 of the XCD at every workgroup's end, evicting the halo
+// planes the neighbouring tiles are about to read.
 template <int NV, class Fin>
 __device__ __forceinline__ void publish_and_finalize(double (&v)[NV], int slot, int nslots,
                                                      double* partials, Scalars* sc,
@@ -166,15 +192,16 @@ __device__ __forceinline__ void publish_and_finalize(double (&v)[NV], int slot, 
   block_sum<NV>(v, red);
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int q = 0; q < NV; ++q) partials[(size_t)q * nslots + slot] = v[q];
-    __threadfence();
-    const uint32_t prev = __hip_atomic_fetch_add(&sc->counter, 1u, __ATOMIC_ACQ_REL,
+    for (int q = 0; q < NV; ++q)
+      __hip_atomic_store(&partials[(size_t)q * nslots + slot], v[q], __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    const uint32_t prev = __hip_atomic_fetch_add(&sc->counter, 1u, __ATOMIC_RELAXED,
                                                  __HIP_MEMORY_SCOPE_AGENT);
     last = (prev == (uint32_t)(nslots - 1));
   }
   __syncthreads();
   if (!last) return;
-  __threadfence();
   double s[NV];
   reduce_partials<NV>(partials, nslots, s, red);
   if (threadIdx.x == 0) {

@@ -17,7 +17,7 @@ struct Tiling {
   int pw_blocks;   // workgroups of the pointwise kernels
 };
 
-Tiling make_tiling(int nx, int ny, int nz, int elem_bytes, int zc_override);
+Tiling make_tiling(int nx, int ny, int nz, int elem_bytes, int zc_override, int ry_override);
 
 // Pointers of one phase launch.
 template <typename T>
@@ -70,6 +70,14 @@ void launch_promote(size_t n, int blocks, double* x, const float* d, const Scala
                     hipStream_t s);
 template <typename T>
 void launch_fill(size_t n, T* y, T v, hipStream_t s);
+// Up to `iters` BiCGStab iterations in one cooperative launch; the same
+// iterates as launch_phase_a/b/c.  p0/v0 hold the inputs of the first
+// iteration when parity == 0.
+template <typename T>
+hipError_t launch_persistent_bicgstab(const Launch<T>& L, T* x, T* r, const T* rh, T* p0, T* p1,
+                                      T* v0, T* v1, T* t, int iters, int parity,
+                                      GridBarrier* bar);
+
 double copy_probe(const void* src, void* dst, size_t bytes, int reps, hipStream_t s,
                   hipError_t* err);
 

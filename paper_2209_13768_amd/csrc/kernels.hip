@@ -232,9 +232,11 @@ double copy_probe(const void* src, void* dst, size_t bytes, int reps, hipStream_
 // ============================================================================
 // tiling
 // ============================================================================
-Tiling make_tiling(int nx, int ny, int nz, int elem_bytes, int zc_override) {
+Tiling make_tiling(int nx, int ny, int nz, int elem_bytes, int zc_override, int ry_override) {
   Tiling t{};
-  t.ry = 4;
+  // 2 rows per wave (8-row tiles) measured fastest on 256^3 FP64 and
+  // 512x512x1024 FP32 among 1, 2 and 4 rows
+  t.ry = (ry_override == 1 || ry_override == 2 || ry_override == 4) ? ry_override : 2;
   const int TY = kWaves * t.ry;
   Geo& g = t.geo;
   g.nx = nx; g.ny = ny; g.nz = nz;
@@ -246,10 +248,9 @@ Tiling make_tiling(int nx, int ny, int nz, int elem_bytes, int zc_override) {
   if (zc_override > 0) {
     zc = zc_override;
   } else {
-    // aim at >= 1024 workgroups (4 per CU) while keeping >= 16 planes per
-    // tile so that the two z-halo planes cost <= 1/8 extra
-    long long want = (txy * nz + 1023) / 1024;
-    zc = (int)(want < 16 ? 16 : want);
+    // 16 planes per tile (the two z-halo planes cost 1/8 extra stage reads)
+    // unless the grid has enough columns for >= 2048 tiles of 32 planes
+    zc = (txy * nz >= 2048LL * 32) ? 32 : 16;
   }
   if (zc > nz) zc = nz;
   if (zc < 1) zc = 1;

@@ -318,6 +318,32 @@ struct PhResid {
 // launch covers (the same split in single-solve and batched launches)
 // ============================================================================
 template <typename T>
+struct alignas(16) V16 {
+  static constexpr int N = 16 / sizeof(T);
+  T v[N];
+};
+
+__device__ __forceinline__ bool aligned16(const void* a, const void* b, const void* c,
+                                          const void* d, const void* e, const void* f) {
+  return ((((uintptr_t)a) | ((uintptr_t)b) | ((uintptr_t)c) | ((uintptr_t)d) | ((uintptr_t)e) |
+           ((uintptr_t)f)) & 15) == 0;
+}
+
+template <typename T>
+__device__ __forceinline__ void phase_c_elem(T& x, T p, T& r, T v, T t, T rh, T alpha, T omega,
+                                             bool xz, double (&acc)[2]) {
+  const T s = r - alpha * v;
+  const T xo = xz ? T(0) : x;
+  x = xo + alpha * p + omega * s;
+  const T rn = s - omega * t;
+  r = rn;
+  acc[0] += (double)rh * (double)rn;
+  acc[1] += (double)rn * (double)rn;
+}
+
+// 16-byte vector loads when every stream is 16-byte aligned; the scalar
+// loop covers the remainder (and unaligned streams).
+template <typename T>
 __device__ __forceinline__ void phase_c_range(size_t n, int blk, int blocks, T* __restrict__ x,
                                               const T* __restrict__ p, T* __restrict__ r,
                                               const T* __restrict__ v, const T* __restrict__ t,
@@ -326,15 +352,28 @@ __device__ __forceinline__ void phase_c_range(size_t n, int blk, int blocks, T* 
   const T alpha = (T)sc->alpha, omega = (T)sc->omega;
   const bool xz = sc->x_zero != 0;
   const size_t stride = (size_t)blocks * kThreads;
-  for (size_t e = (size_t)blk * kThreads + threadIdx.x; e < n; e += stride) {
-    const T s = r[e] - alpha * v[e];
-    const T xo = xz ? T(0) : x[e];
-    x[e] = xo + alpha * p[e] + omega * s;
-    const T rn = s - omega * t[e];
-    r[e] = rn;
-    acc[0] += (double)rh[e] * (double)rn;
-    acc[1] += (double)rn * (double)rn;
+  size_t done = 0;
+  if (aligned16(x, p, r, v, t, rh)) {
+    using VT = V16<T>;
+    constexpr int N = VT::N;
+    const size_t nv = n / N;
+    VT* xv = (VT*)x;
+    VT* rv = (VT*)r;
+    for (size_t e = (size_t)blk * kThreads + threadIdx.x; e < nv; e += stride) {
+      VT xa = xz ? VT{} : xv[e];
+      VT ra = rv[e];
+      const VT pa = ((const VT*)p)[e], va = ((const VT*)v)[e];
+      const VT ta = ((const VT*)t)[e], ha = ((const VT*)rh)[e];
+#pragma unroll
+      for (int c = 0; c < N; ++c)
+        phase_c_elem<T>(xa.v[c], pa.v[c], ra.v[c], va.v[c], ta.v[c], ha.v[c], alpha, omega, xz, acc);
+      xv[e] = xa;
+      rv[e] = ra;
+    }
+    done = nv * N;
   }
+  for (size_t e = done + (size_t)blk * kThreads + threadIdx.x; e < n; e += stride)
+    phase_c_elem<T>(x[e], p[e], r[e], v[e], t[e], rh[e], alpha, omega, xz, acc);
 }
 
 template <typename T>
@@ -344,7 +383,28 @@ __device__ __forceinline__ void cg_b_range(size_t n, int blk, int blocks, T* __r
                                            double (&acc)[1]) {
   const T alpha = (T)sc->alpha;
   const size_t stride = (size_t)blocks * kThreads;
-  for (size_t e = (size_t)blk * kThreads + threadIdx.x; e < n; e += stride) {
+  size_t done = 0;
+  if (aligned16(x, d, r, q, x, x)) {
+    using VT = V16<T>;
+    constexpr int N = VT::N;
+    const size_t nv = n / N;
+    VT* xv = (VT*)x;
+    VT* rv = (VT*)r;
+    for (size_t e = (size_t)blk * kThreads + threadIdx.x; e < nv; e += stride) {
+      VT xa = xv[e], ra = rv[e];
+      const VT da = ((const VT*)d)[e], qa = ((const VT*)q)[e];
+#pragma unroll
+      for (int c = 0; c < N; ++c) {
+        xa.v[c] += alpha * da.v[c];
+        ra.v[c] = ra.v[c] - alpha * qa.v[c];
+        acc[0] += (double)ra.v[c] * (double)ra.v[c];
+      }
+      xv[e] = xa;
+      rv[e] = ra;
+    }
+    done = nv * N;
+  }
+  for (size_t e = done + (size_t)blk * kThreads + threadIdx.x; e < n; e += stride) {
     x[e] += alpha * d[e];
     const T rn = r[e] - alpha * q[e];
     r[e] = rn;

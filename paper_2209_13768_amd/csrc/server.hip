@@ -132,6 +132,7 @@ struct wfa_server {
   char worker_msg[256] = "";
   int parity32 = 0, parity64 = 0;
   int chunk = 4;
+  int ry = 0;        // rows per wave of every resident solve's tiling
   std::thread worker;
 };
 
@@ -369,8 +370,8 @@ int advance(wfa_server* sv, Request* r) {
 }
 
 // Rebuild the batched work tables of the resident set.
-void build_tables(wfa_server* sv, int* n32, int* tiles32, int* pw32, int* n64, int* tiles64,
-                  int* pw64) {
+int build_tables(wfa_server* sv, int* n32, int* tiles32, int* pw32, int* n64, int* tiles64,
+                 int* pw64) {
   const int S = sv->max_slots;
   int a = 0, b = 0, t32 = 0, p32 = 0, t64 = 0, p64 = 0;
   int* tb32 = &sv->h_bases[0];
@@ -380,6 +381,12 @@ void build_tables(wfa_server* sv, int* n32, int* tiles32, int* pw32, int* n64, i
   for (int s = 0; s < S; ++s) {
     Request* r = sv->slots[s];
     if (!r || (r->phase != R_ITER && r->phase != R_REFINE)) continue;
+    const int ry = r->g.prec == WFA_F32_IR64 ? r->g.tl32.ry : r->g.tl.ry;
+    if (ry != sv->ry) {
+      snprintf(sv->worker_msg, sizeof sv->worker_msg, "tilings with different rows per wave");
+      sv->worker_error = WFA_ERR_INVALID;
+      return WFA_ERR_INVALID;
+    }
     if (is_f32_batch(r)) {
       float* x = r->g.prec == WFA_F32_IR64 ? r->g.d32 : (float*)r->T;
       sv->h_d32[a] = make_desc<float>(r, x);
@@ -395,6 +402,7 @@ void build_tables(wfa_server* sv, int* n32, int* tiles32, int* pw32, int* n64, i
   }
   tb32[a] = t32; pb32[a] = p32; tb64[b] = t64; pb64[b] = p64;
   *n32 = a; *tiles32 = t32; *pw32 = p32; *n64 = b; *tiles64 = t64; *pw64 = p64;
+  return WFA_OK;
 }
 
 void worker_main(wfa_server* sv) {
@@ -433,11 +441,15 @@ void worker_main(wfa_server* sv) {
       r->g.sc = sv->slot_sc + r->slot * kScalarsPerSlot;
       r->g.sc_in = r->g.sc + 1;
       r->g.sc_aux = r->g.sc + 2;
+      // every grid gets the default tiling rule, so all share one row count
+      sv->ry = r->g.prec == WFA_F32_IR64 ? r->g.tl32.ry : r->g.tl.ry;
       if ((rc = start_request(sv, r))) break;
     }
     int n32 = 0, t32 = 0, p32 = 0, n64 = 0, t64 = 0, p64 = 0;
     if (!rc) {
-      build_tables(sv, &n32, &t32, &p32, &n64, &t64, &p64);
+      rc = build_tables(sv, &n32, &t32, &p32, &n64, &t64, &p64);
+    }
+    if (!rc) {
       const int S = sv->max_slots;
       hipMemcpyAsync(sv->d32, sv->h_d32.data(), sizeof(SolveDesc<float>) * std::max(n32, 1),
                      hipMemcpyHostToDevice, sv->stream);
@@ -448,13 +460,13 @@ void worker_main(wfa_server* sv) {
       for (int q = 0; q < sv->chunk; ++q) {
         if (n32) {
           launch_batch_iteration<float>(sv->d32, sv->bases, t32, sv->bases + (S + 1), p32, n32,
-                                        sv->parity32, sv->stream);
+                                        sv->parity32, sv->ry, sv->stream);
           sv->parity32 ^= 1;
         }
         if (n64) {
           launch_batch_iteration<double>(sv->d64, sv->bases + 2 * (S + 1), t64,
                                          sv->bases + 3 * (S + 1), p64, n64, sv->parity64,
-                                         sv->stream);
+                                         sv->ry, sv->stream);
           sv->parity64 ^= 1;
         }
       }

@@ -136,13 +136,17 @@ def test_bicgstab_trajectory_fp64(wfa, oracle_mod, name, k):
 
 
 @pytest.mark.parametrize("k,name", [(1, "cell_upwind_mixed"), (5, "cell_upwind_mixed"),
-                                    (20, "const_dirichlet")])
+                                    (20, "heat_32")])
 def test_bicgstab_trajectory_fp32(wfa, oracle_mod, k, name):
-    """FP32 vectors against the FP64 oracle at 1e-5.  Where the recurrence
-    amplifies FP32 rounding (the ill-conditioned upwind case; an FP32 numpy
-    emulation drifts ~3e-4 from FP64 by iteration 10) only the first
-    iterations are compared; the well-conditioned case is compared to k=20."""
-    prob = inputs.random_problem(104, 33, 20, 12, **VARIANTS[name])
+    """FP32 vectors against the FP64 oracle at 1e-5, where cond(A) * 6e-8 is
+    well below 1e-5.  On the ill-conditioned upwind case the recurrence
+    amplifies FP32 rounding (an FP32 numpy emulation drifts ~3e-4 from FP64
+    by iteration 10), so only its first iterations are compared; the 32^3
+    heat problem (cond ~ 13.6) is compared to k = 20."""
+    if name == "heat_32":
+        prob = inputs.heat_32()
+    else:
+        prob = inputs.random_problem(104, 33, 20, 12, **VARIANTS[name])
     o = oracle_mod.Oracle(prob)
     g = _grid(wfa, prob, wfa.F32)
     b32 = g.rhs(g.field(prob.T0))
@@ -283,3 +287,34 @@ def test_profiling_counts_launches(wfa):
     x, info = g.solve(b, g.field(), tol=1e-300, maxit=10)
     n, ms, by = g.kernel_stats(wfa.K_PHASE_A)
     assert n == 10 and ms > 0 and by == (6 * 8 + 4) * prob.cells
+
+
+@pytest.mark.parametrize("name", ["const_dirichlet", "cell_upwind_mixed"])
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_persistent_launch_is_bitwise_identical(wfa, name, precision):
+    """One cooperative launch per chunk of iterations (grid barriers instead
+    of kernel boundaries) must give exactly the iterates of one launch per
+    phase: same per-tile partials, same reduction order, same finalizers."""
+    prob = inputs.random_problem(111, 45, 30, 21, **VARIANTS[name])
+    outs = []
+    for mode in (0, 1):
+        g = _grid(wfa, prob, wfa.PRECISIONS[precision])
+        g.set_option(wfa.OPT_PERSISTENT, mode)
+        b = g.rhs(g.field(prob.T0))
+        x, info = g.solve(b, g.field(prob.T0), tol=1e-9, maxit=3000)
+        assert info.status == wfa.OK
+        outs.append((to_np(x), info.iterations))
+    assert outs[0][1] == outs[1][1]
+    assert np.array_equal(outs[0][0], outs[1][0])
+
+
+def test_persistent_heat_32_matches_oracle(wfa, oracle_mod):
+    prob = inputs.heat_32()
+    o = oracle_mod.Oracle(prob)
+    To, _ = o.timestep(prob.T0, 3, 1e-12, 1000)
+    g = _grid(wfa, prob, wfa.F64)
+    g.set_option(wfa.OPT_PERSISTENT, 1)
+    T = g.field(prob.T0)
+    infos = g.timestep(T, 3, tol=1e-12, maxit=1000)
+    assert all(i.status == wfa.OK for i in infos)
+    assert rel_l2(to_np(T), To) <= 3 * 14 * 2e-12
