@@ -343,6 +343,138 @@ done:
 }
 
 /*
+ * BiCGStab with two global reductions per iteration (the paper suggests
+ * pipelined / reduction-limited Krylov variants, sections 3.2.2 and 5).
+ * Same iterates as orc_bicgstab in exact arithmetic, reorganised so that
+ * each iteration needs two synchronisation points:
+ *   pass 1: apply the previous iteration's update
+ *             s = r - alpha v,  r <- s - omega t,  x <- x + alpha p + omega s
+ *           then p <- r + beta (p - omega v)  (p = r on the first pass)
+ *           v = A p; reduce sigma = (rh, v), and (rh, r), ||r||^2 of the
+ *           updated r: the iteration just completed is checked here.
+ *   pass 2: s = r - alpha v, t = A s; reduce (t,s), (t,t), (rh,s), (rh,t):
+ *           omega = (t,s)/(t,t), and the next rho is predicted from
+ *           (rh, s - omega t) = (rh,s) - omega (rh,t) so that beta is known
+ *           before the next pass 1.
+ * alpha uses the exact rho of pass 1; beta the predicted one.  Breakdown
+ * (exact zero rho, sigma or omega) restarts from b - A x as in
+ * orc_bicgstab; a zero omega is applied (x += alpha p, r = s) before the
+ * restart; tt == 0 (s == 0) ends with x + alpha p.
+ */
+int orc_bicgstab2(const orc_problem* p, const double* b, double* x, double tol,
+                  int maxit, double* r_out, orc_info* info)
+{
+  const long n = cells(p);
+  const size_t bytes = sizeof(double) * (size_t)n;
+  double* r = (double*)malloc(bytes);
+  double* rh = (double*)malloc(bytes);
+  double* pv = (double*)malloc(bytes);
+  double* v = (double*)malloc(bytes);
+  double* s = (double*)malloc(bytes);
+  double* t = (double*)malloc(bytes);
+  int status = ORC_NOCONV, it = 0, restarts = 0;
+  double rnorm = 0.0;
+
+  const double bn = sqrt(dot(p, b, b));
+  if (!isfinite(bn) || !all_finite(x, n)) { status = ORC_NONFINITE; goto done; }
+  if (bn == 0.0) {
+    memset(x, 0, bytes);
+    memset(r, 0, bytes);
+    status = ORC_OK;
+    goto done;
+  }
+
+  double rho, alpha, omega, beta;
+  int first, pending_restart, szero;
+restart:
+  residual(p, b, x, r);
+  memcpy(rh, r, bytes);
+  rho = dot(p, rh, r);
+  rnorm = sqrt(dot(p, r, r));
+  if (!isfinite(rnorm)) { status = ORC_NONFINITE; goto done; }
+  if (rnorm <= tol * bn) { status = ORC_OK; goto done; }
+  if (it >= maxit) { status = ORC_NOCONV; goto done; }
+  alpha = omega = beta = 0.0;
+  first = 1;
+  pending_restart = 0;
+  szero = 0;
+
+  for (;;) {
+    /* ---- pass 1 */
+    if (first) {
+      memcpy(pv, r, bytes);
+    } else {
+#pragma omp parallel for schedule(static)
+      for (long c = 0; c < n; ++c) {
+        const double sc = r[c] - alpha * v[c];
+        r[c] = sc - omega * t[c];
+        x[c] = x[c] + alpha * pv[c] + omega * sc;
+        pv[c] = r[c] + beta * (pv[c] - omega * v[c]);
+      }
+    }
+    orc_apply(p, pv, v);
+    const double sigma = dot(p, rh, v);
+    if (!first) {
+      ++it;
+      const double rho_exact = dot(p, rh, r);
+      rnorm = sqrt(dot(p, r, r));
+      if (!isfinite(rnorm)) { status = ORC_NONFINITE; goto done; }
+      if (szero || rnorm <= tol * bn) { status = ORC_OK; goto done; }
+      if (pending_restart) goto do_restart;
+      if (it >= maxit) { status = ORC_NOCONV; goto done; }
+      if (!isfinite(rho_exact)) { status = ORC_NONFINITE; goto done; }
+      if (rho_exact == 0.0) goto do_restart;
+      rho = rho_exact;
+    }
+    if (!isfinite(sigma)) { status = ORC_NONFINITE; goto done; }
+    if (sigma == 0.0) goto do_restart;
+    alpha = rho / sigma;
+    /* ---- pass 2 */
+#pragma omp parallel for schedule(static)
+    for (long c = 0; c < n; ++c) s[c] = r[c] - alpha * v[c];
+    orc_apply(p, s, t);
+    const double ts = dot(p, t, s);
+    const double tt = dot(p, t, t);
+    const double rs = dot(p, rh, s);
+    const double rt = dot(p, rh, t);
+    if (!isfinite(ts) || !isfinite(tt) || !isfinite(rs) || !isfinite(rt)) {
+      status = ORC_NONFINITE;
+      goto done;
+    }
+    if (tt == 0.0) {
+      omega = 0.0;
+      szero = 1;
+    } else {
+      omega = ts / tt;
+      if (omega == 0.0) pending_restart = 1;
+    }
+    if (!szero && !pending_restart) {
+      const double rho_pred = rs - omega * rt;
+      beta = (rho_pred / rho) * (alpha / omega);
+    } else {
+      beta = 0.0;
+    }
+    first = 0;
+    continue;
+  do_restart:
+    if (++restarts > ORC_MAX_RESTARTS) { status = ORC_BREAKDOWN; goto done; }
+    goto restart;
+  }
+
+done:
+  if (info) {
+    info->status = status;
+    info->iterations = it;
+    info->restarts = restarts;
+    info->rel_res_recursive = bn > 0.0 ? rnorm / bn : 0.0;
+    info->rel_res_true = (status == ORC_NONFINITE) ? NAN : orc_true_relres(p, b, x);
+  }
+  if (r_out) memcpy(r_out, r, bytes);
+  free(r); free(rh); free(pv); free(v); free(s); free(t);
+  return status;
+}
+
+/*
  * Classic conjugate gradients (section 1.1.2: the paper's solver for the
  * symmetric positive-definite pure-diffusion system), unpreconditioned, with
  * the same stopping test as orc_bicgstab.  Each iteration is one product

@@ -67,6 +67,23 @@ struct Op {
   uint32_t dir;    // bit f set: face f is Dirichlet
 };
 
+// Reciprocal of a positive normal number: the hardware estimate refined by
+// two Newton steps (each doubles the correct bits), to within a few ulp of
+// 1/a -- the harmonic-mean faces need no IEEE-exact division, and this is
+// a third of its instructions.
+__device__ __forceinline__ double pos_rcp(double a) {
+  double y = __builtin_amdgcn_rcp(a);
+  double e = __builtin_fma(-a, y, 1.0);
+  y = __builtin_fma(y, e, y);
+  e = __builtin_fma(-a, y, 1.0);
+  return __builtin_fma(y, e, y);
+}
+__device__ __forceinline__ float pos_rcp(float a) {
+  float y = __builtin_amdgcn_rcpf(a);
+  const float e = __builtin_fmaf(-a, y, 1.0f);
+  return __builtin_fmaf(y, e, y);
+}
+
 // Faces: 0 x-, 1 x+, 2 y-, 3 y+, 4 z-, 5 z+.  `inside` bit f: the neighbour
 // across face f exists.
 template <typename T, bool CELL>
@@ -76,7 +93,7 @@ __device__ __forceinline__ T cell_apply(const Op<T>& op, T c, const T nb[6], T k
 #pragma unroll
   for (int f = 0; f < 6; ++f) {
     if (inside & (1u << f)) {
-      const T D = CELL ? op.cD * (T(2) * kP * kN[f] / (kP + kN[f])) : op.cD;
+      const T D = CELL ? op.cD * (T(2) * kP * kN[f] * pos_rcp(kP + kN[f])) : op.cD;
       diag += D + op.out[f];
       acc += (D + op.in[f]) * nb[f];
     } else if (op.dir & (1u << f)) {
@@ -243,6 +260,8 @@ __device__ __forceinline__ void march_tile(const Geo& g, const Op<T>& op,
                                            T* sk) {
   using TS = TileShape<RY>;
   constexpr int TY = TS::TY, LW = TS::LW, LH = TS::LH;
+  constexpr int PD = Ph::PD;  // planes of loads in flight ahead of the compute
+  static_assert(PD == 1 || PD == 2, "prefetch depth 1 or 2");
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int tx = tile % g.tiles_x;
   const int rest = tile / g.tiles_x;
@@ -287,16 +306,41 @@ __device__ __forceinline__ void march_tile(const Geo& g, const Op<T>& op,
 
   using Raw = typename Ph::Raw;
   using ERaw = typename Ph::ERaw;
-  T up[RY], uc[RY], un[RY];
-  T kpv[RY], kcv[RY], knv[RY];
-  T hc = T(0), kh = T(0);
-  Raw rn[RY];
-  Raw rh{};
-  float krn[RY];
-  float krh = 0.f;
-  ERaw ec[RY], en[RY];
+  // Loads of one plane that are in flight: own cells' stage inputs and
+  // diffusivity, the halo cell's, and the epilogue's inputs.
+  struct PlaneLoads {
+    Raw o[RY];
+    float ko[RY];
+    Raw h;
+    float kh;
+    ERaw e[RY];
+  };
+  // Issue the loads of plane kp (stage inputs up to the z-halo plane k1,
+  // halo and epilogue inputs for output planes only).
+  auto issue = [&](PlaneLoads& S, int kp) {
+    const bool stage = (kp <= k1) && (kp < nz);
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      if (stage && own[r]) {
+        const size_t idx = (size_t)kp * plane + poff[r];
+        S.o[r] = ph.fetch(idx);
+        if (CELL) S.ko[r] = kappa[idx];
+      }
+      if (kp < k1 && own[r]) S.e[r] = ph.efetch((size_t)kp * plane + poff[r]);
+    }
+    if (hval && kp < k1) {
+      const size_t idx = (size_t)kp * plane + hoff;
+      S.h = ph.fetch(idx);
+      if (CELL) S.kh = kappa[idx];
+    }
+  };
 
-  // plane k0 - 1 (own cells only)
+  T up[RY], uc[RY];
+  T kpv[RY], kcv[RY];
+  T hc = T(0), kh = T(0);
+  ERaw ec[RY];
+
+  // plane k0 - 1 (own cells only) and plane k0 (own + halo), staged directly
 #pragma unroll
   for (int r = 0; r < RY; ++r) {
     up[r] = T(0);
@@ -306,16 +350,13 @@ __device__ __forceinline__ void march_tile(const Geo& g, const Op<T>& op,
       up[r] = ph.combine(ph.fetch(idx));
       if (CELL) kpv[r] = (T)kappa[idx];
     }
-  }
-  // plane k0: own + halo
-#pragma unroll
-  for (int r = 0; r < RY; ++r) {
     uc[r] = T(0);
     kcv[r] = T(1);
     if (own[r]) {
       const size_t idx = (size_t)k0 * plane + poff[r];
       uc[r] = ph.combine(ph.fetch(idx));
       if (CELL) kcv[r] = (T)kappa[idx];
+      ec[r] = ph.efetch(idx);
     }
   }
   if (hval) {
@@ -323,71 +364,47 @@ __device__ __forceinline__ void march_tile(const Geo& g, const Op<T>& op,
     hc = ph.combine(ph.fetch(idx));
     if (CELL) kh = (T)kappa[idx];
   }
-  // raw loads for plane k0 + 1 and epilogue loads for plane k0
-  const bool has_n0 = (k0 + 1 <= k1) && (k0 + 1 < nz);
-#pragma unroll
-  for (int r = 0; r < RY; ++r) {
-    krn[r] = 1.f;
-    if (has_n0 && own[r]) {
-      const size_t idx = (size_t)(k0 + 1) * plane + poff[r];
-      rn[r] = ph.fetch(idx);
-      if (CELL) krn[r] = kappa[idx];
-    }
-    if (own[r]) ec[r] = ph.efetch((size_t)k0 * plane + poff[r]);
-  }
-  if (hval && k0 + 1 < k1) {
-    const size_t idx = (size_t)(k0 + 1) * plane + hoff;
-    rh = ph.fetch(idx);
-    if (CELL) krh = kappa[idx];
-  }
+  PlaneLoads L0, L1;
+  issue(L0, k0 + 1);
+  if (PD == 2) issue(L1, k0 + 2);
 
   int buf = 0;
-  for (int k = k0; k < k1; ++k) {
-    T* L = su + buf * (LH * LW);
-    T* LK = CELL ? sk + buf * (LH * LW) : nullptr;
+  // One output plane k; S holds the loads of plane k+1 and is refilled
+  // with plane k+1+PD.
+  auto step = [&](int k, PlaneLoads& S) {
+    T* Lu = su + buf * (LH * LW);
+    T* Lk = CELL ? sk + buf * (LH * LW) : nullptr;
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
-      L[lidx[r]] = uc[r];
-      if (CELL) LK[lidx[r]] = kcv[r];
+      Lu[lidx[r]] = uc[r];
+      if (CELL) Lk[lidx[r]] = kcv[r];
     }
     if (hl >= 0) {
-      L[hl] = hval ? hc : T(0);
-      if (CELL) LK[hl] = hval ? kh : T(1);
+      Lu[hl] = hval ? hc : T(0);
+      if (CELL) Lk[hl] = hval ? kh : T(1);
     }
     __syncthreads();
 
-    // stage plane k + 1
+    // stage plane k + 1 from its (now due) loads
     const bool has_n = (k + 1 <= k1) && (k + 1 < nz);
+    T un[RY], knv[RY];
+    ERaw en[RY];
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
       un[r] = T(0);
       knv[r] = T(1);
       if (has_n && own[r]) {
-        un[r] = ph.combine(rn[r]);
-        if (CELL) knv[r] = (T)krn[r];
+        un[r] = ph.combine(S.o[r]);
+        if (CELL) knv[r] = (T)S.ko[r];
       }
+      en[r] = S.e[r];
     }
     T hn = T(0), khn = T(1);
     if (hval && k + 1 < k1) {
-      hn = ph.combine(rh);
-      if (CELL) khn = (T)krh;
+      hn = ph.combine(S.h);
+      if (CELL) khn = (T)S.kh;
     }
-    // issue loads for plane k + 2 and epilogue loads for plane k + 1
-    const bool fetch2 = (k + 2 <= k1) && (k + 2 < nz);
-#pragma unroll
-    for (int r = 0; r < RY; ++r) {
-      if (fetch2 && own[r]) {
-        const size_t idx = (size_t)(k + 2) * plane + poff[r];
-        rn[r] = ph.fetch(idx);
-        if (CELL) krn[r] = kappa[idx];
-      }
-      if (k + 1 < k1 && own[r]) en[r] = ph.efetch((size_t)(k + 1) * plane + poff[r]);
-    }
-    if (hval && k + 2 < k1) {
-      const size_t idx = (size_t)(k + 2) * plane + hoff;
-      rh = ph.fetch(idx);
-      if (CELL) krh = kappa[idx];
-    }
+    issue(S, k + 1 + PD);
 
     // compute plane k
     const uint32_t ins_z = (k > 0 ? 16u : 0u) | (k < nz - 1 ? 32u : 0u);
@@ -395,11 +412,11 @@ __device__ __forceinline__ void march_tile(const Geo& g, const Op<T>& op,
     for (int r = 0; r < RY; ++r) {
       if (own[r]) {
         const int l = lidx[r];
-        T nb[6] = {L[l - 1], L[l + 1], L[l - LW], L[l + LW], up[r], un[r]};
+        T nb[6] = {Lu[l - 1], Lu[l + 1], Lu[l - LW], Lu[l + LW], up[r], un[r]};
         T kn6[6];
         if (CELL) {
-          kn6[0] = LK[l - 1]; kn6[1] = LK[l + 1]; kn6[2] = LK[l - LW];
-          kn6[3] = LK[l + LW]; kn6[4] = kpv[r]; kn6[5] = knv[r];
+          kn6[0] = Lk[l - 1]; kn6[1] = Lk[l + 1]; kn6[2] = Lk[l - LW];
+          kn6[3] = Lk[l + LW]; kn6[4] = kpv[r]; kn6[5] = knv[r];
         } else {
 #pragma unroll
           for (int f = 0; f < 6; ++f) kn6[f] = T(1);
@@ -418,6 +435,15 @@ __device__ __forceinline__ void march_tile(const Geo& g, const Op<T>& op,
     }
     hc = hn; kh = khn;
     buf ^= 1;
+  };
+
+  for (int k = k0; k < k1;) {
+    step(k, L0);
+    ++k;
+    if (PD == 2 && k < k1) {
+      step(k, L1);
+      ++k;
+    }
   }
   __syncthreads();  // LDS planes are reused by the next tile of this workgroup
 }

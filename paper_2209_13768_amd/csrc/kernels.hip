@@ -56,16 +56,14 @@ void dispatch_march(const Launch<T>& L, const Ph& ph, const Fin& fin, bool gated
   if (L.cell) {
     switch (L.tl.ry) {
       case 1: WFA_MARCH(true, 1); break;
-      case 2: WFA_MARCH(true, 2); break;
-      case 8: WFA_MARCH(true, 8); break;
-      default: WFA_MARCH(true, 4); break;
+      case 4: WFA_MARCH(true, 4); break;
+      default: WFA_MARCH(true, 2); break;
     }
   } else {
     switch (L.tl.ry) {
       case 1: WFA_MARCH(false, 1); break;
-      case 2: WFA_MARCH(false, 2); break;
-      case 8: WFA_MARCH(false, 8); break;
-      default: WFA_MARCH(false, 4); break;
+      case 4: WFA_MARCH(false, 4); break;
+      default: WFA_MARCH(false, 2); break;
     }
   }
 #undef WFA_MARCH
@@ -254,6 +252,10 @@ Tiling make_tiling(int nx, int ny, int nz, int elem_bytes, int zc_override, int 
   }
   if (zc > nz) zc = nz;
   if (zc < 1) zc = 1;
+  // small grids: thinner tiles until there are >= 128 of them (measured on
+  // 32^3 and 64^3, where a pass is a few microseconds and parallelism wins)
+  if (zc_override <= 0)
+    while (zc > 2 && txy * ((nz + zc - 1) / zc) < 128) zc /= 2;
   g.zc = zc;
   g.zchunks = (nz + zc - 1) / zc;
   g.ntiles = (int)(txy * g.zchunks);

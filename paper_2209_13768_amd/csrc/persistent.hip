@@ -22,9 +22,12 @@ namespace wfa {
 // and leaves, so every wave of the grid always exits.
 __device__ __forceinline__ bool grid_sync(GridBarrier* b, uint32_t nblocks, int spin_limit) {
   __shared__ int ok;
-  __threadfence();  // this wave's stores reach the coherence point
+  // every wave's stores have reached its XCD's L2 ...
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
   if (threadIdx.x == 0) {
+    // ... one wave writes that L2 back (release) for the whole workgroup
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     int good = 1;
     const uint32_t gen = __hip_atomic_load(&b->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
@@ -45,10 +48,11 @@ __device__ __forceinline__ bool grid_sync(GridBarrier* b, uint32_t nblocks, int 
         }
       }
     }
+    // and invalidates stale lines of the CU's L1 and the XCD's L2 (acquire)
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     ok = good;
   }
   __syncthreads();
-  __threadfence();  // see every other workgroup's stores
   return ok != 0;
 }
 

@@ -137,6 +137,7 @@ struct FinNone {
 template <typename T>
 struct PhApply {
   static constexpr int NV = 1;
+  static constexpr int PD = 1;
   const T* __restrict__ x;
   T* __restrict__ y;
   struct Raw { T x; };
@@ -153,6 +154,7 @@ struct PhApply {
 template <typename T, bool CELL>
 struct PhRhs {
   static constexpr int NV = 1;
+  static constexpr int PD = 1;
   Op<T> op;
   const T* __restrict__ x;
   T* __restrict__ b;
@@ -171,6 +173,7 @@ struct PhRhs {
 template <typename T, bool CELL, bool FORM_B>
 struct PhInit {
   static constexpr int NV = 2;
+  static constexpr int PD = 1;
   Op<T> op;
   const T* __restrict__ x;
   const T* __restrict__ b_in;
@@ -201,6 +204,7 @@ struct PhInit {
 template <typename T>
 struct PhA {
   static constexpr int NV = 1;
+  static constexpr int PD = 1;
   const T* __restrict__ r;
   const T* __restrict__ p;
   const T* __restrict__ v;
@@ -235,6 +239,7 @@ struct PhA {
 template <typename T>
 struct PhB {
   static constexpr int NV = 2;
+  static constexpr int PD = 2;
   const T* __restrict__ r;
   const T* __restrict__ v;
   T* __restrict__ t;
@@ -256,6 +261,7 @@ struct PhB {
 template <typename T>
 struct PhCgA {
   static constexpr int NV = 1;
+  static constexpr int PD = 1;
   const T* __restrict__ r;
   const T* __restrict__ d;
   T* __restrict__ d_out;
@@ -287,6 +293,7 @@ struct PhCgA {
 template <typename Tin>
 struct PhResid {
   static constexpr int NV = 3;
+  static constexpr int PD = 1;
   const Tin* __restrict__ x;
   const Tin* __restrict__ b;
   float* __restrict__ r32;

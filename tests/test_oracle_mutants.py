@@ -56,6 +56,13 @@ MUTANTS = [
      "if (rnorm <= tol) { status = ORC_OK; goto done; }\n    if (omega"),
     ("cg_beta_inverted", "const double beta = rr_new / rr;", "const double beta = rr / rr_new;"),
     ("cg_step_sign", "x[c] += a * d[c]; r[c] -= a * q[c];", "x[c] -= a * d[c]; r[c] -= a * q[c];"),
+    ("bicgstab2_beta_uses_exact_rho", "const double rho_pred = rs - omega * rt;",
+     "const double rho_pred = rs + omega * rt;"),
+    ("bicgstab2_x_update_order", "x[c] = x[c] + alpha * pv[c] + omega * sc;",
+     "x[c] = x[c] + alpha * pv[c] + omega * r[c];"),
+    ("bicgstab2_r_update_sign", "r[c] = sc - omega * t[c];", "r[c] = sc + omega * t[c];"),
+    ("bicgstab2_p_update", "pv[c] = r[c] + beta * (pv[c] - omega * v[c]);\n      }",
+     "pv[c] = r[c] + beta * pv[c];\n      }"),
     ("dot_drops_last_plane", "for (int k = 0; k < nz; ++k) total += part[k];",
      "for (int k = 0; k + 1 < nz; ++k) total += part[k];"),
 ]

@@ -401,3 +401,52 @@ def test_stop_rule_is_relative_and_first_crossing(oracle_mod):
     assert i1.rel_res_recursive <= tol
     _, i0 = o.bicgstab(b, p.T0, tol, i1.iterations - 1)
     assert i0.status == oracle_mod.NOCONV and i0.rel_res_recursive > tol
+
+
+# ------------------------------------------------- two-reduction BiCGStab
+@pytest.mark.parametrize("name", sorted(P5_CASES))
+def test_bicgstab2_dense_direct_solve(oracle_mod, name):
+    p = inputs.random_problem(53, 4, 4, 4, **P5_CASES[name])
+    o = oracle_mod.Oracle(p)
+    A = dense_by_columns(o)
+    b = o.rhs(p.T0)
+    x_ref = np.linalg.solve(A, b.ravel()).reshape(p.shape)
+    x, info = o.bicgstab2(b, p.T0, 1e-14, 400)
+    assert info.status == oracle_mod.OK
+    assert rel_l2(x, x_ref) <= 1e-12
+
+
+@pytest.mark.parametrize("cell,u", [(False, (0.0, 0.0, 0.0)), (True, (1.0, 0.5, 0.25))])
+def test_bicgstab2_follows_textbook_iterates(oracle_mod, cell, u):
+    """Both organisations produce the same iterates in exact arithmetic:
+    after k iterations they agree to rounding (before BiCGStab's recurrence
+    amplifies it)."""
+    p = inputs.random_problem(54, 20, 15, 12, cell=cell, u=u, bc_kind=inputs.MIXED_BC_KIND)
+    o = oracle_mod.Oracle(p)
+    b = o.rhs(p.T0)
+    for k in (1, 2, 3, 5):
+        x1, i1 = o.bicgstab(b, p.T0, 1e-300, k)
+        x2, i2, r2 = o.bicgstab2(b, p.T0, 1e-300, k, want_r=True)
+        assert i1.iterations == i2.iterations == k
+        assert rel_l2(x2, x1) <= 1e-13
+        assert abs(i2.rel_res_recursive - i1.rel_res_recursive) <= 1e-12 * i1.rel_res_recursive
+        assert rel_l2(r2, b - o.apply(x2)) * np.linalg.norm(b) <= 1e-13 * np.linalg.norm(b)
+
+
+def test_bicgstab2_status_paths_and_stop_rule(oracle_mod):
+    p = inputs.random_problem(55, 8, 7, 6, u=(1.0, 2.0, 0.5), bc_kind=inputs.MIXED_BC_KIND)
+    o = oracle_mod.Oracle(p)
+    b = o.rhs(p.T0)
+    x, info = o.bicgstab2(np.zeros(p.shape), p.T0, 1e-10, 50)
+    assert info.status == oracle_mod.OK and info.iterations == 0 and not x.any()
+    bad = b.copy()
+    bad[0, 1, 2] = np.inf
+    assert o.bicgstab2(bad, p.T0, 1e-10, 50)[1].status == oracle_mod.NONFINITE
+    tol = 1e-6
+    x1, i1 = o.bicgstab2(b, p.T0, tol, 500)
+    s = 2.0 ** 40
+    x2, i2 = o.bicgstab2(b * s, p.T0 * s, tol, 500)
+    assert i1.status == i2.status == oracle_mod.OK and i1.iterations == i2.iterations
+    assert np.array_equal(x1 * s, x2)
+    _, i0 = o.bicgstab2(b, p.T0, tol, i1.iterations - 1)
+    assert i0.status == oracle_mod.NOCONV and i0.rel_res_recursive > tol
