@@ -1,10 +1,12 @@
 """Benchmark: BiCGStab cell-iterations/s and HBM-roofline fraction on one MI355X.
 
-Workload (a "step" = one backward-Euler time step = one BiCGStab solve of the
-whole grid): 256^3 convection-diffusion, FP64, log-normal per-cell
-diffusivity (mu 0, sigma 1), velocity (1, 0.5, 0.25) with first-order
-upwind, dt 1e-2, x- Dirichlet 1 / x+ Dirichlet 0 / y, z zero-flux, BiCGStab
-to a relative residual of 1e-8.  Inputs are synthetic and seeded
+Default workload (a "step" = one backward-Euler time step = one BiCGStab
+solve of the whole grid): 256^3 convection-diffusion, FP64, log-normal
+per-cell diffusivity (mu 0, sigma 1), velocity (1, 0.5, 0.25) with
+first-order upwind, dt 1e-2, x- Dirichlet 1 / x+ Dirichlet 0 / y, z
+zero-flux, BiCGStab to a relative residual of 1e-8, solved with the
+two-reduction organisation of BiCGStab (the textbook three-pass one is timed
+on the same steps for comparison).  Inputs are synthetic and seeded
 (paper_2209_13768_amd.inputs.convdiff).
 
 Prints one JSON line.  `value` = cells x BiCGStab iterations / seconds over
@@ -15,6 +17,10 @@ kernel in the timed region; `traffic` is the HBM bytes per launch measured
 with rocprofv3 counters (profiles/) when they were taken from the current
 kernel sources, else null.  `cpu_baseline` times the FP64 CPU oracle on a
 bounded sample of the same workload on this host.
+
+Other workloads (--workload): heat32 (32^3, 10 steps), poisson_large
+(512x512x1024 FP32, 500 iterations), mixed384 (FP32 inside FP64 refinement
+vs FP64), serve (Poisson request stream through the batching server).
 """
 import argparse
 import hashlib
@@ -75,43 +81,26 @@ def cpu_baseline(prob, iters: int):
     }
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--n", type=int, default=256, help="grid cells per axis")
-    ap.add_argument("--precision", default="f64", choices=["f64", "f32", "f32_ir64"])
-    ap.add_argument("--tol", type=float, default=1e-8)
-    ap.add_argument("--maxit", type=int, default=20000)
-    ap.add_argument("--cpu-iters", type=int, default=120)
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-profile", action="store_true",
-                    help="time without per-launch events (no roofline)")
-    args = ap.parse_args()
+def percentile(vals, q):
+    v = sorted(vals)
+    if not v:
+        return None
+    return v[min(len(v) - 1, int(round(q / 100 * (len(v) - 1))))]
 
-    world = int(os.environ.get("WORLD_SIZE", "1"))
-    if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this benchmark runs on exactly one GPU; the solver has no "
-                          "multi-GPU path (see DESIGN.md for how it would shard)",
-                          "n_gpus": args.gpus}))
-        sys.exit(2)
 
-    import torch
-    from paper_2209_13768_amd import inputs, wfa
-
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    torch.cuda.set_device(0)
+def run_convdiff(args, torch, inputs, wfa):
+    """The headline workload: 256^3 convection-diffusion time steps."""
     prob = inputs.convdiff(n=args.n)
     prec = wfa.PRECISIONS[args.precision]
     g = wfa.Grid.from_problem(prob, precision=prec)
+    g.set_option(wfa.OPT_METHOD, METHODS[args.method])
     T0 = g.field(prob.T0)
     T = g.field(prob.T0)
     stream = torch.cuda.current_stream()
 
     # warmup: the first steps of the time integration
     for _ in range(args.warmup):
-        g.timestep(T, 1, tol=args.tol, maxit=args.maxit)
+        g.timestep(T, 1, tol=args.tol, maxit=args.maxit, check=False)
     T.copy_(T0)
     torch.cuda.synchronize()
 
@@ -127,7 +116,7 @@ def main():
     e0.record(stream)
     for _ in range(args.steps):
         s0 = time.perf_counter()
-        infos += g.timestep(T, 1, tol=args.tol, maxit=args.maxit)
+        infos += g.timestep(T, 1, tol=args.tol, maxit=args.maxit, check=False)
         step_ms.append((time.perf_counter() - s0) * 1e3)
     e1.record(stream)
     torch.cuda.synchronize()
@@ -141,9 +130,9 @@ def main():
         for k, name in enumerate(wfa.KERNEL_NAMES):
             n, ms, by = g.kernel_stats(k)
             if n:
-                kernels[name] = {"launches": n, "ms_total": ms, "ms_avg": ms / n,
+                kernels[name] = {"launches": n, "ms_total": round(ms, 3), "us_avg": round(ms / n * 1e3, 2),
                                  "alg_bytes_per_launch": by,
-                                 "gbps": by / (ms / n * 1e-3) / 1e9}
+                                 "gbps": round(by / (ms / n * 1e-3) / 1e9, 1)}
         dom = max(kernels, key=lambda k: kernels[k]["ms_total"])
         kd = kernels[dom]
         achieved = kd["gbps"]
@@ -152,14 +141,9 @@ def main():
                     "frac": round(achieved / HBM_PEAK_GBPS, 4),
                     "traffic": load_traffic(dom)}
     w = 4 if prec == wfa.F32 else 8
-    alg_bytes_iter = (17 * w + 2 * 4) * prob.cells   # 17 vector streams + 2 kappa reads
+    streams = STREAMS[args.method]
+    alg_bytes_iter = (streams * w + 2 * 4) * prob.cells   # vector streams + 2 kappa reads
     whole = alg_bytes_iter * iters / (total_ms * 1e-3) / 1e9
-
-    step_ms_sorted = sorted(step_ms)
-
-    def pct(p):
-        return step_ms_sorted[min(len(step_ms_sorted) - 1, int(round(p / 100 * (len(step_ms_sorted) - 1))))]
-
     line = {
         "metric": "BiCGStab cell-iters/s and % HBM roofline on 1 MI355X; p50/p99 solve latency",
         "value": value,
@@ -174,10 +158,11 @@ def main():
         "dtype": {"f64": "f64", "f32": "f32", "f32_ir64": "f32+f64"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"convdiff_{args.n}^3_{args.precision}", "grid": [args.n] * 3,
-                   "precision": args.precision, "tol": args.tol,
+                   "precision": args.precision, "tol": args.tol, "method": args.method,
                    "physics": "lognormal kappa, u=(1,0.5,0.25) upwind, dt=1e-2, mixed BC"},
         "iterations_per_step": iters / args.steps,
-        "solve_latency_ms": {"p50": pct(50), "p99": pct(99)},
+        "solve_latency_ms": {"p50": percentile(step_ms, 50), "p99": percentile(step_ms, 99)},
+        "alg_bytes_per_cell_iter": streams * w + 8,
         "whole_step_gbps": round(whole, 1),
         "whole_step_frac": round(whole / HBM_PEAK_GBPS, 4),
         "roofline": roofline,
@@ -185,9 +170,211 @@ def main():
         "rel_res_true_max": max(i.rel_res_true for i in infos),
         "kernel_source_hash": kernel_source_hash(),
     }
+    if args.compare and args.method != "bicgstab":
+        # the textbook three-pass BiCGStab on the same steps, for comparison
+        g.set_option(wfa.OPT_METHOD, METHODS["bicgstab"])
+        T.copy_(T0)
+        for k in range(wfa.K_COUNT):
+            g.kernel_stats(k, reset=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tinfos = []
+        for _ in range(args.steps):
+            tinfos += g.timestep(T, 1, tol=args.tol, maxit=args.maxit, check=False)
+        torch.cuda.synchronize()
+        tdt = time.perf_counter() - t0
+        tit = sum(i.iterations for i in tinfos)
+        tk = {}
+        for k, name in enumerate(wfa.KERNEL_NAMES):
+            n, ms, by = g.kernel_stats(k)
+            if n:
+                tk[name] = {"us_avg": round(ms / n * 1e3, 2), "gbps": round(by / (ms / n * 1e-3) / 1e9, 1)}
+        line["textbook_bicgstab"] = {"value": prob.cells * tit / tdt, "ms_per_step": tdt / args.steps * 1e3,
+                                     "iterations_per_step": tit / args.steps, "kernels": tk,
+                                     "alg_bytes_per_cell_iter": STREAMS["bicgstab"] * w + 8}
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(prob, args.cpu_iters)
-    print(json.dumps(line))
+    return line
+
+
+def run_heat32(args, torch, inputs, wfa):
+    """32^3 heat diffusion, FP64, 10 steps to 1e-10: a latency-bound grid."""
+    prob = inputs.heat_32()
+    g = wfa.Grid.from_problem(prob, precision=wfa.F64)
+    g.set_option(wfa.OPT_METHOD, METHODS[args.method])
+    T = g.field(prob.T0)
+    g.timestep(T, 2, tol=1e-10, maxit=1000)
+    T = g.field(prob.T0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = g.timestep(T, 10, tol=1e-10, maxit=1000)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    iters = sum(i.iterations for i in infos)
+    out = {"workload": "heat_32^3_f64_10steps", "method": args.method, "seconds": dt,
+           "ms_per_step": dt / 10 * 1e3, "us_per_iteration": dt / iters * 1e6,
+           "iterations": iters, "cell_iters_per_s": prob.cells * iters / dt,
+           "rel_res_true_max": max(i.rel_res_true for i in infos)}
+    if not args.no_cpu:
+        import oracle
+        o = oracle.Oracle(prob)
+        c0 = time.perf_counter()
+        To, io = o.timestep(prob.T0, 10, 1e-10, 1000)
+        cdt = time.perf_counter() - c0
+        out["cpu_baseline"] = {"seconds": cdt, "iterations": sum(i.iterations for i in io),
+                               "cores": oracle.num_threads(), "kind": "oracle"}
+        Tg = T.cpu().numpy()
+        out["rel_err_vs_oracle"] = float(((Tg - To) ** 2).sum() ** 0.5 / (To ** 2).sum() ** 0.5)
+    return out
+
+
+def run_poisson_large(args, torch, inputs, wfa):
+    """512x512x1024 FP32 pure diffusion, exactly 500 BiCGStab iterations."""
+    prob = inputs.poisson_large()
+    g = wfa.Grid.from_problem(prob, precision=wfa.F32)
+    g.set_option(wfa.OPT_METHOD, METHODS[args.method])
+    T = g.field(prob.T0)
+    b = g.rhs(T)
+    x = g.field()
+    g.solve(b, x, tol=1e-300, maxit=20, method=args.method)
+    g.set_option(wfa.OPT_PROFILE, 1)
+    for k in range(wfa.K_COUNT):
+        g.kernel_stats(k, reset=True)
+    times = []
+    for _ in range(args.repeats):
+        x.copy_(T)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, info = g.solve(b, x, tol=1e-300, maxit=500, method=args.method)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    best = min(times)
+    kernels = {}
+    for k, name in enumerate(wfa.KERNEL_NAMES):
+        n, ms, by = g.kernel_stats(k)
+        if n:
+            kernels[name] = {"us_avg": round(ms / n * 1e3, 1), "gbps": round(by / (ms / n * 1e-3) / 1e9, 1)}
+    streams = STREAMS[args.method]
+    bytes_iter = (streams * 4 + 8) * prob.cells
+    return {"workload": "poisson_512x512x1024_f32_500it", "method": args.method,
+            "seconds_best": best, "seconds": times, "iterations": info.iterations,
+            "cell_iters_per_s": prob.cells * info.iterations / best,
+            "gbps": bytes_iter * info.iterations / best / 1e9,
+            "frac_8tbs": bytes_iter * info.iterations / best / 8e12,
+            "kernels": kernels, "rel_res_recursive": info.rel_res_recursive}
+
+
+def run_mixed384(args, torch, inputs, wfa):
+    """384^3 convection-diffusion (u x4): FP32 inside FP64 refinement vs
+    plain FP64 BiCGStab, to 1e-12 and to 1e-10."""
+    prob = inputs.convdiff_384(n=args.n if args.n != 256 else 384)
+    out = {"workload": f"mixed_{prob.nx}^3", "results": []}
+    Tref = None
+    for tol in (1e-10, 1e-12):
+        for name, prec in (("f64", wfa.F64), ("f32_ir64", wfa.F32_IR64)):
+            g = wfa.Grid.from_problem(prob, precision=prec)
+            T = g.field(prob.T0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = g.timestep(T, 1, tol=tol, maxit=100000)[0]
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            rec = {"precision": name, "tol": tol, "seconds": dt, "iterations": info.iterations,
+                   "refinements": info.refinements, "rel_res_true": info.rel_res_true,
+                   "status": info.status}
+            if name == "f64":
+                Tref = T.double().clone()
+            else:
+                rec["rel_diff_vs_f64"] = float((T - Tref).norm() / Tref.norm())
+            out["results"].append(rec)
+            del g
+    return out
+
+
+def run_serve(args, torch, inputs, wfa):
+    """Poisson request stream (200/s) of heat-step solves on grids with dims
+    in {32,...,192}, FP32 inside FP64 refinement to 1e-10."""
+    reqs = inputs.request_stream(count=args.requests)
+    fields = []
+    for rq in reqs:       # inputs resident in HBM before the clock starts
+        fields.append(torch.from_numpy(rq.problem().T0).to("cuda"))
+    torch.cuda.synchronize()
+    sv = wfa.Server(args.budget_gb << 30, max_slots=args.slots)
+    tickets = {}
+    t_start = time.perf_counter()
+    for q, rq in enumerate(reqs):
+        now = time.perf_counter() - t_start
+        if rq.arrival > now:
+            time.sleep(rq.arrival - now)
+        h = 1.0 / (max(rq.nx, rq.ny, rq.nz) + 1)
+        tickets[q] = (sv.submit(fields[q], h=h, dt=1e-3, alpha=1.0, precision=wfa.F32_IR64,
+                                tol=1e-10, maxit=20000), time.perf_counter() - t_start)
+    sv.drain()
+    t_end = time.perf_counter() - t_start
+    lat, cell_it, fails = [], 0, 0
+    for q, rq in enumerate(reqs):
+        code, info = sv.poll(tickets[q][0])
+        if code != wfa.OK:
+            fails += 1
+        lat.append((tickets[q][1] - rq.arrival) + info.seconds)
+        cell_it += rq.nx * rq.ny * rq.nz * info.iterations
+    sv.close()
+    return {"workload": f"serve_{args.requests}req_200rps", "requests": len(reqs),
+            "failed": fails, "makespan_s": t_end,
+            "latency_ms": {"p50": percentile(lat, 50) * 1e3, "p99": percentile(lat, 99) * 1e3,
+                           "mean": sum(lat) / len(lat) * 1e3},
+            "cell_iters_per_s": cell_it / t_end, "slots": args.slots,
+            "budget_gb": args.budget_gb}
+
+
+METHODS = {"bicgstab": 0, "cg": 1, "bicgstab2": 2}
+STREAMS = {"bicgstab": 17, "cg": 10, "bicgstab2": 14}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="convdiff",
+                    choices=["convdiff", "heat32", "poisson_large", "mixed384", "serve"])
+    ap.add_argument("--method", default="bicgstab2", choices=["bicgstab", "bicgstab2"])
+    ap.add_argument("--compare", type=int, default=1,
+                    help="also time the textbook three-pass BiCGStab on the same steps")
+    ap.add_argument("--n", type=int, default=256, help="grid cells per axis")
+    ap.add_argument("--precision", default="f64", choices=["f64", "f32", "f32_ir64"])
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--maxit", type=int, default=20000)
+    ap.add_argument("--repeats", type=int, default=3)
+    ap.add_argument("--requests", type=int, default=2000)
+    ap.add_argument("--slots", type=int, default=64)
+    ap.add_argument("--budget-gb", type=int, default=64)
+    ap.add_argument("--cpu-iters", type=int, default=120)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-profile", action="store_true",
+                    help="time without per-launch events (no roofline)")
+    ap.add_argument("--probe-copy", action="store_true",
+                    help="start with one 1 GiB device copy (a dispatch of known traffic that "
+                         "calibrates hardware byte counters)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; the solver has no "
+                          "multi-GPU path (see DESIGN.md for how it would shard)",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    from paper_2209_13768_amd import inputs, wfa
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    if args.probe_copy:
+        print(json.dumps({"copy_probe_gbps": wfa.stream_probe(1 << 30, 1)}), file=sys.stderr)
+    run = {"convdiff": run_convdiff, "heat32": run_heat32, "poisson_large": run_poisson_large,
+           "mixed384": run_mixed384, "serve": run_serve}[args.workload]
+    print(json.dumps(run(args, torch, inputs, wfa)))
 
 
 if __name__ == "__main__":

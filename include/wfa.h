@@ -68,7 +68,12 @@ enum {
 };
 enum { WFA_COEF_CONST = 0, WFA_COEF_CELL = 1 };
 enum { WFA_BC_DIRICHLET = 0, WFA_BC_ZEROFLUX = 1 };
-enum { WFA_METHOD_BICGSTAB = 0, WFA_METHOD_CG = 1 };
+enum {
+  WFA_METHOD_BICGSTAB = 0,   /* textbook BiCGStab: 3 reductions per iteration     */
+  WFA_METHOD_CG = 1,         /* classic CG (u == 0): 2 reductions per iteration   */
+  WFA_METHOD_BICGSTAB2 = 2   /* BiCGStab reorganised to 2 reductions and 2 passes
+                                per iteration (same iterates in exact arithmetic) */
+};
 
 /* ---- problem description --------------------------------------------------- */
 typedef struct {
@@ -140,6 +145,15 @@ int wfa_bicgstab_solve(wfa_grid* g, const void* b, void* x, double tol, int maxi
 int wfa_cg_solve(wfa_grid* g, const void* b, void* x, double tol, int maxit,
                  wfa_solve_info* info, void* stream);
 
+/* BiCGStab with two global reductions per iteration: the x and r update of
+ * each iteration is applied on the fly inside the next operator pass, and
+ * the next rho is predicted from (rh,s) - omega (rh,t) so that beta is
+ * known before that pass (the paper points to reduction-limited Krylov
+ * variants, sections 3.2.2 and 5).  Same contract as wfa_bicgstab_solve;
+ * WFA_F64 and WFA_F32 grids. */
+int wfa_bicgstab2_solve(wfa_grid* g, const void* b, void* x, double tol, int maxit,
+                        wfa_solve_info* info, void* stream);
+
 /* nsteps backward-Euler steps in place: T holds T^n on entry and T^{n+nsteps}
  * on exit.  Each step forms b = T + boundary terms and solves A T' = b from
  * the initial guess T with the grid's method (BiCGStab unless changed with
@@ -154,7 +168,9 @@ int wfa_true_residual(wfa_grid* g, const void* b, const void* x, double* rel, vo
 
 /* ---- options and instrumentation -------------------------------------------- */
 enum {
-  WFA_OPT_METHOD = 1,          /* WFA_METHOD_BICGSTAB (default) or _CG         */
+  WFA_OPT_METHOD = 1,          /* WFA_METHOD_BICGSTAB (default), _CG or
+                                  _BICGSTAB2 (used by wfa_timestep; the
+                                  *_solve entry points name their method)   */
   WFA_OPT_PERSISTENT = 2,      /* 0: one launch per phase (default),
                                   1: one persistent launch per solve chunk,
                                   -1: automatic by grid size                   */
@@ -175,7 +191,8 @@ int wfa_grid_set_option(wfa_grid* g, int option, int64_t value);
 enum {
   WFA_K_APPLY = 0, WFA_K_INIT = 1, WFA_K_PHASE_A = 2, WFA_K_PHASE_B = 3,
   WFA_K_PHASE_C = 4, WFA_K_RESIDUAL = 5, WFA_K_PROMOTE = 6, WFA_K_CG_A = 7,
-  WFA_K_CG_B = 8, WFA_K_PERSISTENT = 9, WFA_K_COUNT = 10
+  WFA_K_CG_B = 8, WFA_K_PERSISTENT = 9, WFA_K_PHASE_AC = 10, WFA_K_PHASE_B2 = 11,
+  WFA_K_COUNT = 12
 };
 /* With WFA_OPT_PROFILE on: launches and summed event time (ms) of one
  * kernel since the last reset; `bytes` = algorithmic HBM bytes per launch

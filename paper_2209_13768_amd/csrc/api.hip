@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdarg.h>
+#include <stdlib.h>
 #include <stdio.h>
 #include <string.h>
 
@@ -197,7 +198,7 @@ extern "C" int wfa_grid_set_option(wfa_grid* g, int option, int64_t value) {
   if (!g) return set_error(WFA_ERR_INVALID, "grid is NULL");
   switch (option) {
     case WFA_OPT_METHOD:
-      if (value != WFA_METHOD_BICGSTAB && value != WFA_METHOD_CG)
+      if (value != WFA_METHOD_BICGSTAB && value != WFA_METHOD_CG && value != WFA_METHOD_BICGSTAB2)
         return set_error(WFA_ERR_INVALID, "bad method %lld", (long long)value);
       g->method = (int)value;
       return WFA_OK;
@@ -326,6 +327,8 @@ static double bytes_per_cell(const wfa_grid* g, int kernel) {
     case WFA_K_CG_A: return 4 * wi + k;
     case WFA_K_CG_B: return 6 * wi;
     case WFA_K_PERSISTENT: return 17 * wi + 2 * k;
+    case WFA_K_PHASE_AC: return 10 * wi + k;
+    case WFA_K_PHASE_B2: return 4 * wi + k;
     default: return 0.0;
   }
 }
@@ -521,6 +524,46 @@ static int iterate_bicgstab(wfa_grid* g, const Launch<T>& L, T* x, T* r, T* rh, 
   return WFA_OK;
 }
 
+// Two-reduction BiCGStab: pass 1 reads r[par], p[par], v[par] and writes
+// the [par ^ 1] buffers (r too: neighbours read the old r on the halo).
+template <typename T>
+static int iterate_bicgstab2(wfa_grid* g, const Launch<T>& L, T* x, T** r, T* rh, T** p, T** v,
+                             T* t, const T* b, Scalars* h, int* restarts, int* par_io) {
+  int par = *par_io;
+  int rc = read_scalars(g, L.sc, h, L.stream);
+  if (rc) return rc;
+  while (h->status == ST_RUN) {
+    if (h->restart) {
+      if (++*restarts > WFA_MAX_RESTARTS) { h->status = -1; break; }
+      {
+        ProfScope ps(g, WFA_K_INIT, L.stream);
+        launch_init<T>(L, false, x, b, nullptr, r[par], rh);
+      }
+      if ((rc = check_launch("init"))) return rc;
+      if ((rc = read_scalars(g, L.sc, h, L.stream))) return rc;
+      continue;
+    }
+    // maxit iterations take maxit + 1 first passes (the last applies the update)
+    const int m = next_chunk(g, *h, h->maxit - h->iter + 1);
+    for (int q = 0; q < m; ++q) {
+      {
+        ProfScope ps(g, WFA_K_PHASE_AC, L.stream);
+        launch_phase_ac<T>(L, r[par], v[par], t, p[par], rh, x, r[par ^ 1], p[par ^ 1],
+                           v[par ^ 1]);
+      }
+      {
+        ProfScope ps(g, WFA_K_PHASE_B2, L.stream);
+        launch_phase_b2<T>(L, r[par ^ 1], v[par ^ 1], rh, t);
+      }
+      par ^= 1;
+    }
+    if ((rc = check_launch("bicgstab2"))) return rc;
+    if ((rc = read_scalars(g, L.sc, h, L.stream))) return rc;
+  }
+  *par_io = par;
+  return WFA_OK;
+}
+
 template <typename T>
 static int iterate_cg(wfa_grid* g, const Launch<T>& L, T* x, T* r, T** d, T* q, Scalars* h) {
   int par = 0;
@@ -597,8 +640,12 @@ static int solve_plain(wfa_grid* g, const T* b_user, T* x, bool form_b, double t
   }
   if ((rc = check_launch("init"))) return rc;
   int restarts = 0;
+  T* rbuf[2] = {r, vec[8]};
+  int rpar = 0;
   if (g->method == WFA_METHOD_CG)
     rc = iterate_cg<T>(g, L, x, r, p, t, &h);
+  else if (g->method == WFA_METHOD_BICGSTAB2)
+    rc = iterate_bicgstab2<T>(g, L, x, rbuf, rh, p, v, t, b, &h, &restarts, &rpar);
   else
     rc = iterate_bicgstab<T>(g, L, x, r, rh, p, v, t, b, &h, &restarts, true);
   if (rc) return rc;
@@ -733,8 +780,9 @@ int solve_any(wfa_grid* g, const void* b, void* x, bool form_b, double tol, int 
     case WFA_F64: return solve_plain<double>(g, (const double*)b, (double*)x, form_b, tol, maxit, info, s);
     case WFA_F32: return solve_plain<float>(g, (const float*)b, (float*)x, form_b, tol, maxit, info, s);
     default:
-      if (g->method == WFA_METHOD_CG)
-        return set_error(WFA_ERR_INVALID, "CG is available for WFA_F64 and WFA_F32 grids");
+      if (g->method != WFA_METHOD_BICGSTAB)
+        return set_error(WFA_ERR_INVALID,
+                         "WFA_F32_IR64 grids iterate with textbook BiCGStab only");
       return solve_ir(g, (const double*)b, (double*)x, form_b, tol, maxit, info, s);
   }
 }
@@ -746,6 +794,17 @@ extern "C" int wfa_bicgstab_solve(wfa_grid* g, const void* b, void* x, double to
   if (rc) return rc;
   const int saved = g->method;
   g->method = WFA_METHOD_BICGSTAB;
+  rc = solve_any(g, b, x, false, tol, maxit, info, (hipStream_t)stream);
+  g->method = saved;
+  return rc;
+}
+
+extern "C" int wfa_bicgstab2_solve(wfa_grid* g, const void* b, void* x, double tol, int maxit,
+                                   wfa_solve_info* info, void* stream) {
+  int rc = validate_solve(g, b, x, tol, maxit);
+  if (rc) return rc;
+  const int saved = g->method;
+  g->method = WFA_METHOD_BICGSTAB2;
   rc = solve_any(g, b, x, false, tol, maxit, info, (hipStream_t)stream);
   g->method = saved;
   return rc;

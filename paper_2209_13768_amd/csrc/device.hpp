@@ -42,7 +42,8 @@ struct alignas(64) Scalars {
   double scale, inv_scale;     // mixed precision: residual scaling by 2^-e
   int32_t status, iter, maxit, first, restart, szero, x_zero, force_bd;
   uint32_t counter;            // last-workgroup arrival counter (self-resetting)
-  int32_t pad[7];
+  int32_t restart_pending;     // two-reduction BiCGStab: restart after the update
+  int32_t pad[6];
 };
 
 // Grid-wide barrier state of a persistent launch (self-resetting count).
@@ -239,10 +240,11 @@ __device__ __forceinline__ void publish_and_finalize(double (&v)[NV], int slot, 
 // one plane of work hides each load's latency.
 //
 // Phase policy Ph provides:
-//   struct Raw;  Raw fetch(size_t idx);  T combine(const Raw&);   -- stage
+//   struct Raw;  Raw fetch(size_t idx);  St combine(const Raw&);  -- stage
+//   St;  static T val(const St&)        -- staged struct and its stencil value
 //   struct ERaw; ERaw efetch(size_t idx);                         -- epilogue loads
 //   static constexpr int NV;                                      -- dot partials
-//   void epilogue(size_t idx, T u, T Au, T kP, uint32_t inside,
+//   void epilogue(size_t idx, const St& u, T Au, T kP, uint32_t inside,
 //                 const ERaw&, double (&acc)[NV]);                -- stores + dots
 template <int RY>
 struct TileShape {
@@ -335,7 +337,9 @@ __device__ __forceinline__ void march_tile(const Geo& g, const Op<T>& op,
     }
   };
 
-  T up[RY], uc[RY];
+  using St = typename Ph::St;  // staged value (and what the epilogue needs of it)
+  T up[RY];
+  St uc[RY];
   T kpv[RY], kcv[RY];
   T hc = T(0), kh = T(0);
   ERaw ec[RY];
@@ -347,10 +351,10 @@ __device__ __forceinline__ void march_tile(const Geo& g, const Op<T>& op,
     kpv[r] = T(1);
     if (k0 > 0 && own[r]) {
       const size_t idx = (size_t)(k0 - 1) * plane + poff[r];
-      up[r] = ph.combine(ph.fetch(idx));
+      up[r] = Ph::val(ph.combine(ph.fetch(idx)));
       if (CELL) kpv[r] = (T)kappa[idx];
     }
-    uc[r] = T(0);
+    uc[r] = St{};
     kcv[r] = T(1);
     if (own[r]) {
       const size_t idx = (size_t)k0 * plane + poff[r];
@@ -361,7 +365,7 @@ __device__ __forceinline__ void march_tile(const Geo& g, const Op<T>& op,
   }
   if (hval) {
     const size_t idx = (size_t)k0 * plane + hoff;
-    hc = ph.combine(ph.fetch(idx));
+    hc = Ph::val(ph.combine(ph.fetch(idx)));
     if (CELL) kh = (T)kappa[idx];
   }
   PlaneLoads L0, L1;
@@ -376,7 +380,7 @@ __device__ __forceinline__ void march_tile(const Geo& g, const Op<T>& op,
     T* Lk = CELL ? sk + buf * (LH * LW) : nullptr;
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
-      Lu[lidx[r]] = uc[r];
+      Lu[lidx[r]] = Ph::val(uc[r]);
       if (CELL) Lk[lidx[r]] = kcv[r];
     }
     if (hl >= 0) {
@@ -387,11 +391,12 @@ __device__ __forceinline__ void march_tile(const Geo& g, const Op<T>& op,
 
     // stage plane k + 1 from its (now due) loads
     const bool has_n = (k + 1 <= k1) && (k + 1 < nz);
-    T un[RY], knv[RY];
+    St un[RY];
+    T knv[RY];
     ERaw en[RY];
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
-      un[r] = T(0);
+      un[r] = St{};
       knv[r] = T(1);
       if (has_n && own[r]) {
         un[r] = ph.combine(S.o[r]);
@@ -401,7 +406,7 @@ __device__ __forceinline__ void march_tile(const Geo& g, const Op<T>& op,
     }
     T hn = T(0), khn = T(1);
     if (hval && k + 1 < k1) {
-      hn = ph.combine(S.h);
+      hn = Ph::val(ph.combine(S.h));
       if (CELL) khn = (T)S.kh;
     }
     issue(S, k + 1 + PD);
@@ -412,7 +417,7 @@ __device__ __forceinline__ void march_tile(const Geo& g, const Op<T>& op,
     for (int r = 0; r < RY; ++r) {
       if (own[r]) {
         const int l = lidx[r];
-        T nb[6] = {Lu[l - 1], Lu[l + 1], Lu[l - LW], Lu[l + LW], up[r], un[r]};
+        T nb[6] = {Lu[l - 1], Lu[l + 1], Lu[l - LW], Lu[l + LW], up[r], Ph::val(un[r])};
         T kn6[6];
         if (CELL) {
           kn6[0] = Lk[l - 1]; kn6[1] = Lk[l + 1]; kn6[2] = Lk[l - LW];
@@ -422,14 +427,14 @@ __device__ __forceinline__ void march_tile(const Geo& g, const Op<T>& op,
           for (int f = 0; f < 6; ++f) kn6[f] = T(1);
         }
         const uint32_t ins = ins_xy[r] | ins_z;
-        const T Au = cell_apply<T, CELL>(op, uc[r], nb, kcv[r], kn6, ins);
+        const T Au = cell_apply<T, CELL>(op, Ph::val(uc[r]), nb, kcv[r], kn6, ins);
         ph.epilogue((size_t)k * plane + poff[r], uc[r], Au, kcv[r], ins, ec[r], acc);
       }
     }
     // rotate
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
-      up[r] = uc[r]; uc[r] = un[r];
+      up[r] = Ph::val(uc[r]); uc[r] = un[r];
       kpv[r] = kcv[r]; kcv[r] = knv[r];
       ec[r] = en[r];
     }

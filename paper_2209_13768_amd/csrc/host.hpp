@@ -12,7 +12,8 @@
 
 namespace wfa {
 
-constexpr int kVecs = 8;  // r, rh, t, p0, p1, v0, v1, b (b unused by IR inner)
+constexpr int kVecs = 9;  // r, rh, t, p0, p1, v0, v1, b, r1 (b unused by the IR inner
+                          // solve; r1 = second residual buffer of BiCGStab2)
 
 // Byte offsets of the workspace sub-buffers (each 256-byte aligned).
 struct Layout {

@@ -54,6 +54,15 @@ void launch_phase_b(const Launch<T>& L, const T* r, const T* v, T* t);
 template <typename T>
 void launch_phase_c(const Launch<T>& L, T* x, const T* p, T* r, const T* v, const T* t,
                     const T* rh);
+// Two-reduction BiCGStab, pass 1: apply the previous update (x, r -> r_out)
+// and stage p_out = r' + beta (p - omega v); v_out = A p_out; sigma,
+// (rh, r'), ||r'||^2
+template <typename T>
+void launch_phase_ac(const Launch<T>& L, const T* r, const T* v, const T* t, const T* p,
+                     const T* rh, T* x, T* r_out, T* p_out, T* v_out);
+// pass 2: s = r - alpha v; t = A s; (t,s), (t,t), (rh,s), (rh,t)
+template <typename T>
+void launch_phase_b2(const Launch<T>& L, const T* r, const T* v, const T* rh, T* t);
 // CG: d' = r + beta d (d' = r first); q = A d'; (d', q)
 template <typename T>
 void launch_cg_a(const Launch<T>& L, const T* r, const T* d, T* d_out, T* q);

@@ -115,6 +115,22 @@ void launch_phase_b(const Launch<T>& L, const T* r, const T* v, T* t) {
 }
 
 template <typename T>
+void launch_phase_ac(const Launch<T>& L, const T* r, const T* v, const T* t, const T* p,
+                     const T* rh, T* x, T* r_out, T* p_out, T* v_out) {
+  PhAC<T> ph{};
+  ph.r = r; ph.v = v; ph.t = t; ph.p = p; ph.rh = rh; ph.x = x;
+  ph.r_out = r_out; ph.p_out = p_out; ph.v_out = v_out;
+  dispatch_march(L, ph, FinAC{L.sc}, true, true);
+}
+
+template <typename T>
+void launch_phase_b2(const Launch<T>& L, const T* r, const T* v, const T* rh, T* t) {
+  PhB2<T> ph{};
+  ph.r = r; ph.v = v; ph.rh = rh; ph.t = t;
+  dispatch_march(L, ph, FinB2{L.sc}, true, true);
+}
+
+template <typename T>
 void launch_cg_a(const Launch<T>& L, const T* r, const T* d, T* d_out, T* q) {
   PhCgA<T> ph{};
   ph.r = r; ph.d = d; ph.d_out = d_out; ph.q = q;
@@ -282,6 +298,9 @@ Tiling make_tiling(int nx, int ny, int nz, int elem_bytes, int zc_override, int 
   template void launch_phase_c<T>(const Launch<T>&, T*, const T*, T*, const T*, const T*,    \
                                   const T*);                                                 \
   template void launch_cg_a<T>(const Launch<T>&, const T*, const T*, T*, T*);                \
+  template void launch_phase_ac<T>(const Launch<T>&, const T*, const T*, const T*, const T*, \
+                                   const T*, T*, T*, T*, T*);                                \
+  template void launch_phase_b2<T>(const Launch<T>&, const T*, const T*, const T*, T*);      \
   template void launch_cg_b<T>(const Launch<T>&, T*, const T*, T*, const T*);                \
   template void launch_fill<T>(size_t, T*, T, hipStream_t);
 WFA_INST(double)

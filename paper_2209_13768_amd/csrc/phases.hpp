@@ -20,7 +20,7 @@ struct FinInit {
     const double bb = s[0], rr = s[1];
     sc->bb = bb; sc->rr = rr; sc->rr0 = rr;
     sc->rho = rr; sc->rho_prev = 1.0; sc->alpha = 1.0; sc->omega = 1.0; sc->beta = 0.0;
-    sc->first = 1; sc->restart = 0; sc->szero = 0;
+    sc->first = 1; sc->restart = 0; sc->szero = 0; sc->restart_pending = 0;
     if (!fin_ok(bb) || !fin_ok(rr)) sc->status = ST_NONFINITE;
     else if (bb == 0.0) sc->status = ST_BZERO;
     else if (sqrt(rr) <= sc->tol * sqrt(bb)) sc->status = ST_CONV;
@@ -138,6 +138,8 @@ template <typename T>
 struct PhApply {
   static constexpr int NV = 1;
   static constexpr int PD = 1;
+  using St = T;
+  static __device__ __forceinline__ T val(T u) { return u; }
   const T* __restrict__ x;
   T* __restrict__ y;
   struct Raw { T x; };
@@ -155,6 +157,8 @@ template <typename T, bool CELL>
 struct PhRhs {
   static constexpr int NV = 1;
   static constexpr int PD = 1;
+  using St = T;
+  static __device__ __forceinline__ T val(T u) { return u; }
   Op<T> op;
   const T* __restrict__ x;
   T* __restrict__ b;
@@ -174,6 +178,8 @@ template <typename T, bool CELL, bool FORM_B>
 struct PhInit {
   static constexpr int NV = 2;
   static constexpr int PD = 1;
+  using St = T;
+  static __device__ __forceinline__ T val(T u) { return u; }
   Op<T> op;
   const T* __restrict__ x;
   const T* __restrict__ b_in;
@@ -205,6 +211,8 @@ template <typename T>
 struct PhA {
   static constexpr int NV = 1;
   static constexpr int PD = 1;
+  using St = T;
+  static __device__ __forceinline__ T val(T u) { return u; }
   const T* __restrict__ r;
   const T* __restrict__ p;
   const T* __restrict__ v;
@@ -240,6 +248,8 @@ template <typename T>
 struct PhB {
   static constexpr int NV = 2;
   static constexpr int PD = 2;
+  using St = T;
+  static __device__ __forceinline__ T val(T u) { return u; }
   const T* __restrict__ r;
   const T* __restrict__ v;
   T* __restrict__ t;
@@ -262,6 +272,8 @@ template <typename T>
 struct PhCgA {
   static constexpr int NV = 1;
   static constexpr int PD = 1;
+  using St = T;
+  static __device__ __forceinline__ T val(T u) { return u; }
   const T* __restrict__ r;
   const T* __restrict__ d;
   T* __restrict__ d_out;
@@ -294,6 +306,8 @@ template <typename Tin>
 struct PhResid {
   static constexpr int NV = 3;
   static constexpr int PD = 1;
+  using St = double;
+  static __device__ __forceinline__ double val(double u) { return u; }
   const Tin* __restrict__ x;
   const Tin* __restrict__ b;
   float* __restrict__ r32;
@@ -317,6 +331,152 @@ struct PhResid {
       rh32[i] = r32v;
       acc[2] += (double)r32v * (double)r32v;
     }
+  }
+};
+
+// ============================================================================
+// BiCGStab with two reductions per iteration
+// ============================================================================
+// Pass 1 applies the previous iteration's update on the fly,
+//   s = r - alpha v,  r' = s - omega t,  x' = x + alpha p + omega s,
+// and stages p' = r' + beta (p - omega v) (with halo) for v' = A p';
+// reduces sigma = (rh, v'), (rh, r'), ||r'||^2.  On the first pass of a
+// (re)start p' = r (and r is copied through so the r buffers alternate).
+template <typename T>
+struct StageAC {
+  T p_new, r_new, s, p_old;
+};
+
+template <typename T>
+struct PhAC {
+  static constexpr int NV = 3;
+  static constexpr int PD = 1;
+  using St = StageAC<T>;
+  static __device__ __forceinline__ T val(const St& u) { return u.p_new; }
+  const T* __restrict__ r;
+  const T* __restrict__ v;
+  const T* __restrict__ t;
+  const T* __restrict__ p;
+  const T* __restrict__ rh;
+  T* __restrict__ x;
+  T* __restrict__ r_out;
+  T* __restrict__ p_out;
+  T* __restrict__ v_out;
+  T alpha, omega, beta;
+  int first;
+  struct Raw { T r, v, t, p; };
+  struct ERaw { T x, rh; };
+  __device__ void bind(const Scalars* sc) {
+    alpha = (T)sc->alpha;
+    omega = (T)sc->omega;
+    beta = (T)sc->beta;
+    first = sc->first;
+  }
+  __device__ Raw fetch(size_t i) const {
+    if (first) return {r[i], T(0), T(0), T(0)};
+    return {r[i], v[i], t[i], p[i]};
+  }
+  __device__ St combine(const Raw& q) const {
+    if (first) return {q.r, q.r, T(0), T(0)};
+    const T s = q.r - alpha * q.v;
+    const T rn = s - omega * q.t;
+    return {rn + beta * (q.p - omega * q.v), rn, s, q.p};
+  }
+  __device__ ERaw efetch(size_t i) const {
+    if (first) return {T(0), rh[i]};
+    return {x[i], rh[i]};
+  }
+  __device__ void epilogue(size_t i, const St& u, T Au, T, uint32_t, const ERaw& e,
+                           double (&acc)[NV]) const {
+    if (!first) x[i] = e.x + alpha * u.p_old + omega * u.s;
+    r_out[i] = u.r_new;
+    p_out[i] = u.p_new;
+    v_out[i] = Au;
+    acc[0] += (double)e.rh * (double)Au;
+    acc[1] += (double)e.rh * (double)u.r_new;
+    acc[2] += (double)u.r_new * (double)u.r_new;
+  }
+};
+
+// Pass 2: s = r - alpha v staged, t = A s; (t,s), (t,t), (rh,s), (rh,t).
+template <typename T>
+struct PhB2 {
+  static constexpr int NV = 4;
+  static constexpr int PD = 2;
+  using St = T;
+  static __device__ __forceinline__ T val(T u) { return u; }
+  const T* __restrict__ r;
+  const T* __restrict__ v;
+  const T* __restrict__ rh;
+  T* __restrict__ t;
+  T alpha;
+  struct Raw { T r, v; };
+  struct ERaw { T rh; };
+  __device__ void bind(const Scalars* sc) { alpha = (T)sc->alpha; }
+  __device__ Raw fetch(size_t i) const { return {r[i], v[i]}; }
+  __device__ T combine(const Raw& q) const { return q.r - alpha * q.v; }
+  __device__ ERaw efetch(size_t i) const { return {rh[i]}; }
+  __device__ void epilogue(size_t i, T s, T Au, T, uint32_t, const ERaw& e,
+                           double (&acc)[NV]) const {
+    t[i] = Au;
+    acc[0] += (double)Au * (double)s;
+    acc[1] += (double)Au * (double)Au;
+    acc[2] += (double)e.rh * (double)s;
+    acc[3] += (double)e.rh * (double)Au;
+  }
+};
+
+// After pass 1: the iteration whose update was just applied is checked
+// (convergence on the exact ||r||, limits, a pending restart), then alpha
+// from the exact rho.
+struct FinAC {
+  Scalars* sc;
+  __device__ void operator()(const double (&s)[3]) const {
+    const double sigma = s[0], rho_exact = s[1], rr = s[2];
+    sc->sigma = sigma;
+    if (!sc->first) {
+      sc->iter += 1;
+      sc->rr = rr;
+      sc->x_zero = 0;
+      if (!fin_ok(rr)) { sc->status = ST_NONFINITE; return; }
+      if (sc->szero || sqrt(rr) <= sc->tol * sqrt(sc->bb)) { sc->status = ST_CONV; return; }
+      if (sc->restart_pending) { sc->restart = 1; return; }
+      if (sc->iter >= sc->maxit) { sc->status = ST_NOCONV; return; }
+      if (!fin_ok(rho_exact)) { sc->status = ST_NONFINITE; return; }
+      if (rho_exact == 0.0) { sc->restart = 1; return; }
+      sc->rho = rho_exact;
+    }
+    if (sc->force_bd > 0 && sc->iter + 1 == sc->force_bd) { sc->sigma = 0.0; sc->force_bd = 0; }
+    if (!fin_ok(sc->sigma)) sc->status = ST_NONFINITE;
+    else if (sc->sigma == 0.0) sc->restart = 1;
+    else sc->alpha = sc->rho / sc->sigma;
+  }
+};
+
+// After pass 2: omega, and beta from the predicted next rho.
+struct FinB2 {
+  Scalars* sc;
+  __device__ void operator()(const double (&s)[4]) const {
+    const double ts = s[0], tt = s[1], rs = s[2], rt = s[3];
+    sc->ts = ts; sc->tt = tt;
+    if (!fin_ok(ts) || !fin_ok(tt) || !fin_ok(rs) || !fin_ok(rt)) {
+      sc->status = ST_NONFINITE;
+      return;
+    }
+    if (tt == 0.0) {
+      sc->omega = 0.0;
+      sc->szero = 1;
+    } else {
+      sc->omega = ts / tt;
+      if (sc->omega == 0.0) sc->restart_pending = 1;
+    }
+    if (!sc->szero && !sc->restart_pending) {
+      const double rho_pred = rs - sc->omega * rt;
+      sc->beta = (rho_pred / sc->rho) * (sc->alpha / sc->omega);
+    } else {
+      sc->beta = 0.0;
+    }
+    sc->first = 0;
   }
 };
 

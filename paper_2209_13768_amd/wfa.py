@@ -20,20 +20,20 @@ ERR_INVALID, ERR_NOMEM, ERR_HIP, ERR_BREAKDOWN, ERR_NOCONV, ERR_NONFINITE = -1, 
 F64, F32, F32_IR64 = 0, 1, 2
 COEF_CONST, COEF_CELL = 0, 1
 BC_DIRICHLET, BC_ZEROFLUX = 0, 1
-METHOD_BICGSTAB, METHOD_CG = 0, 1
+METHOD_BICGSTAB, METHOD_CG, METHOD_BICGSTAB2 = 0, 1, 2
 OPT_METHOD, OPT_PERSISTENT, OPT_PROFILE, OPT_FORCE_BREAKDOWN, OPT_CHECK_EVERY = 1, 2, 3, 4, 5
 OPT_IR_INNER_TOL, OPT_ZCHUNK, OPT_RY = 6, 7, 8
 K_APPLY, K_INIT, K_PHASE_A, K_PHASE_B, K_PHASE_C, K_RESIDUAL, K_PROMOTE = 0, 1, 2, 3, 4, 5, 6
-K_CG_A, K_CG_B, K_PERSISTENT, K_COUNT = 7, 8, 9, 10
+K_CG_A, K_CG_B, K_PERSISTENT, K_PHASE_AC, K_PHASE_B2, K_COUNT = 7, 8, 9, 10, 11, 12
 KERNEL_NAMES = ("apply", "init", "phase_a", "phase_b", "phase_c", "residual", "promote",
-                "cg_a", "cg_b", "persistent")
+                "cg_a", "cg_b", "persistent", "phase_ac", "phase_b2")
 
 PRECISIONS = {"f64": F64, "f32": F32, "f32_ir64": F32_IR64}
 
 # Every function the header declares; the library must export all of them.
 EXPORTS = (
     "wfa_workspace_bytes", "wfa_grid_create", "wfa_grid_destroy", "wfa_stencil_apply",
-    "wfa_rhs", "wfa_bicgstab_solve", "wfa_cg_solve", "wfa_timestep", "wfa_true_residual",
+    "wfa_rhs", "wfa_bicgstab_solve", "wfa_bicgstab2_solve", "wfa_cg_solve", "wfa_timestep", "wfa_true_residual",
     "wfa_grid_set_option", "wfa_kernel_stats", "wfa_grid_tiling", "wfa_stream_probe",
     "wfa_server_create", "wfa_submit", "wfa_poll", "wfa_server_drain", "wfa_server_destroy",
     "wfa_last_error", "wfa_version",
@@ -103,6 +103,7 @@ def lib() -> ctypes.CDLL:
     L.wfa_rhs.argtypes = [vp, vp, vp, vp]
     L.wfa_bicgstab_solve.argtypes = [vp, vp, vp, dbl, i32, ctypes.POINTER(_Info), vp]
     L.wfa_cg_solve.argtypes = [vp, vp, vp, dbl, i32, ctypes.POINTER(_Info), vp]
+    L.wfa_bicgstab2_solve.argtypes = [vp, vp, vp, dbl, i32, ctypes.POINTER(_Info), vp]
     L.wfa_timestep.argtypes = [vp, vp, i32, dbl, i32, ctypes.POINTER(_Info), vp]
     L.wfa_true_residual.argtypes = [vp, vp, vp, ctypes.POINTER(dbl), vp]
     L.wfa_grid_set_option.argtypes = [vp, i32, i64]
@@ -250,7 +251,8 @@ class Grid:
         """Solve A x = b in place on x (initial guess; zeros when None)."""
         x = self.field() if x is None else x
         info = _Info()
-        fn = lib().wfa_cg_solve if method == "cg" else lib().wfa_bicgstab_solve
+        fn = {"cg": lib().wfa_cg_solve, "bicgstab": lib().wfa_bicgstab_solve,
+              "bicgstab2": lib().wfa_bicgstab2_solve}[method]
         rc = fn(self._h, self._v(b, "b"), self._v(x, "x"), float(tol), int(maxit),
                 ctypes.byref(info), _stream_ptr(stream))
         if check:

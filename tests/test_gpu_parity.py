@@ -318,3 +318,59 @@ def test_persistent_heat_32_matches_oracle(wfa, oracle_mod):
     infos = g.timestep(T, 3, tol=1e-12, maxit=1000)
     assert all(i.status == wfa.OK for i in infos)
     assert rel_l2(to_np(T), To) <= 3 * 14 * 2e-12
+
+
+@pytest.mark.parametrize("k", [1, 2, 5, 10, 20])
+@pytest.mark.parametrize("name", ["cell_upwind_mixed", "const_dirichlet"])
+def test_bicgstab2_trajectory_fp64(wfa, oracle_mod, name, k):
+    """Two-reduction BiCGStab against the oracle's two-reduction BiCGStab."""
+    prob = inputs.random_problem(112, 37, 21, 18, **VARIANTS[name])
+    o = oracle_mod.Oracle(prob)
+    b = o.rhs(prob.T0)
+    x0 = np.zeros(prob.shape)
+    xo, io = o.bicgstab2(b, x0, 1e-300, k)
+    g = _grid(wfa, prob, wfa.F64)
+    x, info = g.solve(g.field(b), g.field(), tol=1e-300, maxit=k, method="bicgstab2")
+    assert info.status == wfa.ERR_NOCONV and info.iterations == k == io.iterations
+    sx, _ = trajectory_sensitivity(o, b, x0, k, 2.0**-52)
+    assert rel_l2(to_np(x), xo) <= max(FP64_TOL, 100 * sx)
+
+
+@pytest.mark.parametrize("name", sorted(VARIANTS))
+def test_bicgstab2_converged_matches_oracle(wfa, oracle_mod, name):
+    prob = inputs.random_problem(113, 24, 18, 14, **VARIANTS[name])
+    o = oracle_mod.Oracle(prob)
+    b = o.rhs(prob.T0)
+    xo, io = o.bicgstab2(b, prob.T0, 1e-14, 2000)
+    g = _grid(wfa, prob, wfa.F64)
+    x, info = g.solve(g.field(b), g.field(prob.T0), tol=1e-14, maxit=2000, method="bicgstab2")
+    assert info.status == wfa.OK
+    assert rel_l2(to_np(x), xo) <= FP64_TOL
+    assert o.true_relres(b, to_np(x)) <= 1e-13
+
+
+def test_bicgstab2_timestep_and_paths(wfa, oracle_mod):
+    prob = inputs.convdiff(n=40, seed=9)
+    o = oracle_mod.Oracle(prob)
+    b = o.rhs(prob.T0)
+    g = _grid(wfa, prob, wfa.F64)
+    g.set_option(wfa.OPT_METHOD, wfa.METHOD_BICGSTAB2)
+    T = g.field(prob.T0)
+    info = g.timestep(T, 1, tol=1e-10, maxit=5000)[0]
+    assert info.status == wfa.OK
+    assert o.true_relres(b, to_np(T)) <= 1e-10
+    # forced breakdown -> restart, same final accuracy
+    g.set_option(wfa.OPT_FORCE_BREAKDOWN, 5)
+    x, info = g.solve(g.field(b), g.field(prob.T0), tol=1e-10, maxit=5000, method="bicgstab2")
+    assert info.status == wfa.OK and info.restarts == 1
+    assert o.true_relres(b, to_np(x)) <= 1e-10
+    # b == 0 and maxit
+    x, info = g.solve(g.field(), g.field(prob.T0), tol=1e-10, maxit=50, method="bicgstab2")
+    assert info.status == wfa.OK and info.iterations == 0 and not to_np(x).any()
+    x, info = g.solve(g.field(b), g.field(prob.T0), tol=1e-14, maxit=3, method="bicgstab2")
+    assert info.status == wfa.ERR_NOCONV and info.iterations == 3
+    # FP32 grid
+    g32 = _grid(wfa, prob, wfa.F32)
+    b32 = g32.rhs(g32.field(prob.T0))
+    x, info = g32.solve(b32, g32.field(prob.T0), tol=1e-5, maxit=5000, method="bicgstab2")
+    assert info.status == wfa.OK and info.rel_res_true <= 2e-5
