@@ -183,7 +183,13 @@ enum {
   WFA_OPT_IR_INNER_TOL = 6,    /* (value / 1e12) = inner relative tolerance of
                                   WFA_F32_IR64; default 1e-4 * 1e12            */
   WFA_OPT_ZCHUNK = 7,          /* z planes per workgroup; 0 = default rule     */
-  WFA_OPT_RY = 8               /* rows per wave of a tile (1, 2 or 4); 0 = default */
+  WFA_OPT_RY = 8,              /* rows per wave of a tile (1, 2 or 4); 0 = default */
+  WFA_OPT_JACOBI = 9           /* 1: BiCGStab iterates on D^{-1} A x = D^{-1} b
+                                  with D = diag(A), computed in the kernels (the
+                                  paper's psi row scaling, section 1.1.2); the
+                                  stop test then uses the scaled residual, and
+                                  rel_res_true stays the unscaled one.  WFA_F64
+                                  and WFA_F32 grids, BiCGStab methods only     */
 };
 int wfa_grid_set_option(wfa_grid* g, int option, int64_t value);
 

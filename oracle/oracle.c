@@ -225,6 +225,51 @@ static void residual(const orc_problem* p, const double* b, const double* x,
   for (long c = 0; c < n; ++c) r[c] = b[c] - r[c];
 }
 
+/*
+ * The operator a Krylov solve iterates with: A itself, or D^{-1} A with D the
+ * diagonal of A (left Jacobi scaling; for the paper's constant-coefficient
+ * system this is its psi = (1 + 6 omega)^{-1} row scaling, section 1.1.2).
+ */
+static void krylov_apply(const orc_problem* p, int jacobi, const double* x, double* y)
+{
+  orc_apply(p, x, y);
+  if (!jacobi) return;
+  const int nx = p->nx, ny = p->ny, nz = p->nz;
+#pragma omp parallel for schedule(static)
+  for (int k = 0; k < nz; ++k)
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) {
+        double diag, off[6];
+        orc_row(p, i, j, k, &diag, off, NULL);
+        y[cell_index(p, i, j, k)] /= diag;
+      }
+}
+
+/* b' = D^{-1} b */
+static void jacobi_scale(const orc_problem* p, const double* b, double* out)
+{
+  const int nx = p->nx, ny = p->ny, nz = p->nz;
+#pragma omp parallel for schedule(static)
+  for (int k = 0; k < nz; ++k)
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) {
+        double diag, off[6];
+        orc_row(p, i, j, k, &diag, off, NULL);
+        const long c = cell_index(p, i, j, k);
+        out[c] = b[c] / diag;
+      }
+}
+
+/* r = b - M x for the Krylov operator M */
+static void krylov_residual(const orc_problem* p, int jacobi, const double* b, const double* x,
+                            double* r)
+{
+  const long n = cells(p);
+  krylov_apply(p, jacobi, x, r);
+#pragma omp parallel for schedule(static)
+  for (long c = 0; c < n; ++c) r[c] = b[c] - r[c];
+}
+
 /* ||b - A x|| / ||b|| (0 when b == 0 and x == 0) */
 double orc_true_relres(const orc_problem* p, const double* b, const double* x)
 {
@@ -248,11 +293,18 @@ double orc_true_relres(const orc_problem* p, const double* b, const double* x)
  * iteration count continues).  A non-finite Krylov scalar stops with
  * ORC_NONFINITE.  tt == 0 means s == 0: the half step is the solution.
  */
-int orc_bicgstab(const orc_problem* p, const double* b, double* x,
-                 double tol, int maxit, double* r_out, orc_info* info)
+static int bicgstab_core(const orc_problem* p, int jacobi, const double* b_in, double* x,
+                         double tol, int maxit, double* r_out, orc_info* info)
 {
   const long n = cells(p);
   const size_t bytes = sizeof(double) * (size_t)n;
+  double* bs = NULL;          /* D^{-1} b when scaling */
+  const double* b = b_in;
+  if (jacobi) {
+    bs = (double*)malloc(bytes);
+    jacobi_scale(p, b_in, bs);
+    b = bs;
+  }
   double* r = (double*)malloc(bytes);
   double* rh = (double*)malloc(bytes);
   double* pv = (double*)malloc(bytes);
@@ -276,7 +328,7 @@ int orc_bicgstab(const orc_problem* p, const double* b, double* x,
 
   double rho_prev, alpha, omega;
 restart:
-  residual(p, b, x, r);
+  krylov_residual(p, jacobi, b, x, r);
   memcpy(rh, r, bytes);
   memset(pv, 0, bytes);
   memset(v, 0, bytes);
@@ -293,14 +345,14 @@ restart:
     const double beta = (rho / rho_prev) * (alpha / omega);
 #pragma omp parallel for schedule(static)
     for (long c = 0; c < n; ++c) pv[c] = r[c] + beta * (pv[c] - omega * v[c]);
-    orc_apply(p, pv, v);
+    krylov_apply(p, jacobi, pv, v);
     const double sigma = dot(p, rh, v);
     if (!isfinite(sigma)) { status = ORC_NONFINITE; goto done; }
     if (sigma == 0.0) goto do_restart;
     alpha = rho / sigma;
 #pragma omp parallel for schedule(static)
     for (long c = 0; c < n; ++c) s[c] = r[c] - alpha * v[c];
-    orc_apply(p, s, t);
+    krylov_apply(p, jacobi, s, t);
     const double tt = dot(p, t, t);
     const double ts = dot(p, t, s);
     if (!isfinite(tt) || !isfinite(ts)) { status = ORC_NONFINITE; goto done; }
@@ -335,11 +387,28 @@ done:
     info->iterations = it;
     info->restarts = restarts;
     info->rel_res_recursive = bn > 0.0 ? rnorm / bn : 0.0;
-    info->rel_res_true = (status == ORC_NONFINITE) ? NAN : orc_true_relres(p, b, x);
+    info->rel_res_true = (status == ORC_NONFINITE) ? NAN : orc_true_relres(p, b_in, x);
   }
   if (r_out) memcpy(r_out, r, bytes);
-  free(r); free(rh); free(pv); free(v); free(s); free(t);
+  free(r); free(rh); free(pv); free(v); free(s); free(t); free(bs);
   return status;
+}
+
+int orc_bicgstab(const orc_problem* p, const double* b, double* x,
+                 double tol, int maxit, double* r_out, orc_info* info)
+{
+  return bicgstab_core(p, 0, b, x, tol, maxit, r_out, info);
+}
+
+/*
+ * BiCGStab on the left-Jacobi-scaled system D^{-1} A x = D^{-1} b.  The
+ * stop test and the recursive residual refer to the scaled system
+ * (||D^{-1} r|| <= tol ||D^{-1} b||); rel_res_true is the unscaled one.
+ */
+int orc_bicgstab_jacobi(const orc_problem* p, const double* b, double* x,
+                        double tol, int maxit, double* r_out, orc_info* info)
+{
+  return bicgstab_core(p, 1, b, x, tol, maxit, r_out, info);
 }
 
 /*

@@ -93,6 +93,7 @@ def load(path: str | None = None) -> ctypes.CDLL:
     lib.orc_bicgstab.argtypes = [P, D, D, ctypes.c_double, ctypes.c_int, D, I]
     lib.orc_cg.argtypes = [P, D, D, ctypes.c_double, ctypes.c_int, D, I]
     lib.orc_bicgstab2.argtypes = [P, D, D, ctypes.c_double, ctypes.c_int, D, I]
+    lib.orc_bicgstab_jacobi.argtypes = [P, D, D, ctypes.c_double, ctypes.c_int, D, I]
     lib.orc_timestep.argtypes = [P, D, ctypes.c_int, ctypes.c_double, ctypes.c_int, I]
     lib.orc_num_threads.restype = ctypes.c_int
     lib.orc_set_num_threads.argtypes = [ctypes.c_int]
@@ -183,6 +184,10 @@ class Oracle:
     def bicgstab2(self, b, x0, tol: float, maxit: int, want_r: bool = False):
         """BiCGStab with two reductions per iteration (oracle.c)."""
         return self._krylov(self.lib.orc_bicgstab2, b, x0, tol, maxit, want_r)
+
+    def bicgstab_jacobi(self, b, x0, tol: float, maxit: int, want_r: bool = False):
+        """BiCGStab on D^{-1} A x = D^{-1} b (oracle.c)."""
+        return self._krylov(self.lib.orc_bicgstab_jacobi, b, x0, tol, maxit, want_r)
 
     def cg(self, b, x0, tol: float, maxit: int, want_r: bool = False):
         return self._krylov(self.lib.orc_cg, b, x0, tol, maxit, want_r)

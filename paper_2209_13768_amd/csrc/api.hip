@@ -162,6 +162,7 @@ void grid_setup(wfa_grid* g, int nx, int ny, int nz, const wfa_coeffs* c, char* 
   g->ir_inner_tol = 1e-4;
   const int w = g->prec == WFA_F32 ? 4 : 8;
   g->ry = 0;
+  g->jacobi = 0;
   g->tl = make_tiling(nx, ny, nz, w, 0, 0);
   g->tl32 = make_tiling(nx, ny, nz, 4, 0, 0);
 }
@@ -220,6 +221,10 @@ extern "C" int wfa_grid_set_option(wfa_grid* g, int option, int64_t value) {
     case WFA_OPT_IR_INNER_TOL:
       if (value <= 0) return set_error(WFA_ERR_INVALID, "bad inner tolerance");
       g->ir_inner_tol = (double)value * 1e-12;
+      return WFA_OK;
+    case WFA_OPT_JACOBI:
+      if (value != 0 && value != 1) return set_error(WFA_ERR_INVALID, "Jacobi flag must be 0 or 1");
+      g->jacobi = (int)value;
       return WFA_OK;
     case WFA_OPT_ZCHUNK:
     case WFA_OPT_RY: {
@@ -361,6 +366,7 @@ Launch<double> ctx<double>(wfa_grid* g, Scalars* sc, hipStream_t s) {
   Launch<double> L{};
   L.tl = g->tl;
   L.op = g->op64;
+  L.op.jac = (uint32_t)g->jacobi;
   L.cell = g->c.mode == WFA_COEF_CELL;
   L.kappa = (const float*)g->c.kappa;
   L.partials = g->partials;
@@ -374,11 +380,21 @@ Launch<float> ctx<float>(wfa_grid* g, Scalars* sc, hipStream_t s) {
   Launch<float> L{};
   L.tl = g->prec == WFA_F32 ? g->tl : g->tl32;
   L.op = g->op32;
+  L.op.jac = (uint32_t)g->jacobi;
   L.cell = g->c.mode == WFA_COEF_CELL;
   L.kappa = (const float*)g->c.kappa;
   L.partials = g->partials;
   L.sc = sc;
   L.stream = s;
+  return L;
+}
+
+// Launch context of the operator itself (no Jacobi scaling): true
+// residuals, wfa_stencil_apply, wfa_rhs.
+template <typename T>
+static Launch<T> plain_ctx(wfa_grid* g, Scalars* sc, hipStream_t s) {
+  Launch<T> L = ctx<T>(g, sc, s);
+  L.op.jac = 0;
   return L;
 }
 
@@ -607,7 +623,7 @@ static int true_residual(wfa_grid* g, const Tin* b, const Tin* x, double* rel, h
   Scalars h = fresh_scalars(1.0, 1, 0);
   int rc = write_scalars(&h, g->sc_aux, s);
   if (rc) return rc;
-  Launch<double> L = ctx<double>(g, g->sc_aux, s);
+  Launch<double> L = plain_ctx<double>(g, g->sc_aux, s);
   {
     ProfScope ps(g, WFA_K_RESIDUAL, s);
     launch_residual<Tin>(L, x, b, nullptr, nullptr, nullptr, 0);
@@ -662,6 +678,10 @@ static int solve_plain(wfa_grid* g, const T* b_user, T* x, bool form_b, double t
   } else {
     rel_true = NAN;
   }
+  if (status != WFA_OK)
+    set_error(status, "solve ended with %s after %d iterations (%d restarts)",
+              status == WFA_ERR_NOCONV ? "NOCONV" : status == WFA_ERR_NONFINITE ? "NONFINITE"
+              : "BREAKDOWN", h.iter, restarts);
   if (info) {
     info->status = status;
     info->iterations = h.iter;
@@ -749,6 +769,11 @@ static int solve_ir(wfa_grid* g, const double* b_user, double* x, bool form_b, d
       break;
     }
   }
+  if (status != WFA_OK)
+    set_error(status, "refinement ended with %s after %d refinements, %d inner iterations "
+              "(outer status %d, inner status %d, inner rr %.3e, outer rr %.3e)",
+              status == WFA_ERR_NOCONV ? "NOCONV" : status == WFA_ERR_NONFINITE ? "NONFINITE"
+              : "BREAKDOWN", refinements, total_it, ho.status, hi.status, hi.rr, ho.rr);
   if (info) {
     info->status = status;
     info->iterations = total_it;
@@ -776,6 +801,9 @@ int solve_any(wfa_grid* g, const void* b, void* x, bool form_b, double tol, int 
               wfa_solve_info* info, hipStream_t s) {
   if (g->method == WFA_METHOD_CG && (g->c.u[0] != 0.0 || g->c.u[1] != 0.0 || g->c.u[2] != 0.0))
     return set_error(WFA_ERR_INVALID, "CG needs a symmetric operator (u == 0)");
+  if (g->jacobi && (g->method == WFA_METHOD_CG || g->prec == WFA_F32_IR64))
+    return set_error(WFA_ERR_INVALID,
+                     "Jacobi scaling is available for BiCGStab on WFA_F64 / WFA_F32 grids");
   switch (g->prec) {
     case WFA_F64: return solve_plain<double>(g, (const double*)b, (double*)x, form_b, tol, maxit, info, s);
     case WFA_F32: return solve_plain<float>(g, (const float*)b, (float*)x, form_b, tol, maxit, info, s);
@@ -844,10 +872,10 @@ extern "C" int wfa_stencil_apply(wfa_grid* g, const void* x, void* y, void* stre
   hipStream_t s = (hipStream_t)stream;
   if (g->prec == WFA_F32) {
     ProfScope ps(g, WFA_K_APPLY, s);
-    launch_apply<float>(ctx<float>(g, g->sc, s), (const float*)x, (float*)y);
+    launch_apply<float>(plain_ctx<float>(g, g->sc, s), (const float*)x, (float*)y);
   } else {
     ProfScope ps(g, WFA_K_APPLY, s);
-    launch_apply<double>(ctx<double>(g, g->sc, s), (const double*)x, (double*)y);
+    launch_apply<double>(plain_ctx<double>(g, g->sc, s), (const double*)x, (double*)y);
   }
   return check_launch("apply");
 }
@@ -857,9 +885,9 @@ extern "C" int wfa_rhs(wfa_grid* g, const void* T, void* b, void* stream) {
   if (!T || !b) return set_error(WFA_ERR_INVALID, "T and b must be non-NULL");
   hipStream_t s = (hipStream_t)stream;
   if (g->prec == WFA_F32)
-    launch_rhs<float>(ctx<float>(g, g->sc, s), (const float*)T, (float*)b);
+    launch_rhs<float>(plain_ctx<float>(g, g->sc, s), (const float*)T, (float*)b);
   else
-    launch_rhs<double>(ctx<double>(g, g->sc, s), (const double*)T, (double*)b);
+    launch_rhs<double>(plain_ctx<double>(g, g->sc, s), (const double*)T, (double*)b);
   return check_launch("rhs");
 }
 

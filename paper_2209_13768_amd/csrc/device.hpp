@@ -66,6 +66,7 @@ struct Op {
   T out[6];        // outflow diagonal per face: max( F_f, 0)
   T bval[6];       // Dirichlet ghost values
   uint32_t dir;    // bit f set: face f is Dirichlet
+  uint32_t jac;    // 1: the Krylov operator is D^{-1} A (left Jacobi scaling)
 };
 
 // Reciprocal of a positive normal number: the hardware estimate refined by
@@ -87,9 +88,10 @@ __device__ __forceinline__ float pos_rcp(float a) {
 
 // Faces: 0 x-, 1 x+, 2 y-, 3 y+, 4 z-, 5 z+.  `inside` bit f: the neighbour
 // across face f exists.
+// Returns (A x)_P, or (A x)_P / A[P,P] when op.jac; the diagonal in `dg`.
 template <typename T, bool CELL>
 __device__ __forceinline__ T cell_apply(const Op<T>& op, T c, const T nb[6], T kP,
-                                        const T kN[6], uint32_t inside) {
+                                        const T kN[6], uint32_t inside, T& dg) {
   T diag = T(1), acc = T(0);
 #pragma unroll
   for (int f = 0; f < 6; ++f) {
@@ -102,7 +104,9 @@ __device__ __forceinline__ T cell_apply(const Op<T>& op, T c, const T nb[6], T k
       diag += D + op.out[f];
     }
   }
-  return diag * c - acc;
+  dg = diag;
+  const T y = diag * c - acc;
+  return op.jac ? y * pos_rcp(diag) : y;
 }
 
 // Dirichlet contribution of cell P to the right-hand side.
@@ -427,8 +431,9 @@ __device__ __forceinline__ void march_tile(const Geo& g, const Op<T>& op,
           for (int f = 0; f < 6; ++f) kn6[f] = T(1);
         }
         const uint32_t ins = ins_xy[r] | ins_z;
-        const T Au = cell_apply<T, CELL>(op, Ph::val(uc[r]), nb, kcv[r], kn6, ins);
-        ph.epilogue((size_t)k * plane + poff[r], uc[r], Au, kcv[r], ins, ec[r], acc);
+        T dg;
+        const T Au = cell_apply<T, CELL>(op, Ph::val(uc[r]), nb, kcv[r], kn6, ins, dg);
+        ph.epilogue((size_t)k * plane + poff[r], uc[r], Au, kcv[r], ins, ec[r], dg, acc);
       }
     }
     // rotate

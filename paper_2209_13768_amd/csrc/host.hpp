@@ -64,7 +64,7 @@ struct wfa_grid {
   wfa::Op<float> op32;
   wfa::Tiling tl;        // tiling of the grid's vector type
   wfa::Tiling tl32;      // tiling of FP32 inner vectors
-  int method, persistent, profile, force_bd, check_every, zchunk, ry;
+  int method, persistent, profile, force_bd, check_every, zchunk, ry, jacobi;
   double ir_inner_tol;
   wfa::Profiler prof;
 };

@@ -148,7 +148,7 @@ struct PhApply {
   __device__ Raw fetch(size_t i) const { return {x[i]}; }
   __device__ T combine(const Raw& r) const { return r.x; }
   __device__ ERaw efetch(size_t) const { return {}; }
-  __device__ void epilogue(size_t i, T, T Au, T, uint32_t, const ERaw&, double (&)[NV]) const {
+  __device__ void epilogue(size_t i, T, T Au, T, uint32_t, const ERaw&, T dg, double (&)[NV]) const {
     y[i] = Au;
   }
 };
@@ -168,7 +168,7 @@ struct PhRhs {
   __device__ Raw fetch(size_t i) const { return {x[i]}; }
   __device__ T combine(const Raw& r) const { return r.x; }
   __device__ ERaw efetch(size_t) const { return {}; }
-  __device__ void epilogue(size_t i, T u, T, T kP, uint32_t ins, const ERaw&,
+  __device__ void epilogue(size_t i, T u, T, T kP, uint32_t ins, const ERaw&, T dg,
                            double (&)[NV]) const {
     b[i] = u + cell_bterm<T, CELL>(op, kP, ins);
   }
@@ -195,11 +195,12 @@ struct PhInit {
     if (FORM_B) return {T(0)};
     return {b_in[i]};
   }
-  __device__ void epilogue(size_t i, T u, T Au, T kP, uint32_t ins, const ERaw& e,
+  __device__ void epilogue(size_t i, T u, T Au, T kP, uint32_t ins, const ERaw& e, T dg,
                            double (&acc)[NV]) const {
-    const T bv = FORM_B ? u + cell_bterm<T, CELL>(op, kP, ins) : e.b;
+    const T b0 = FORM_B ? u + cell_bterm<T, CELL>(op, kP, ins) : e.b;
+    const T bv = op.jac ? b0 * pos_rcp(dg) : b0;   // D^{-1} b under Jacobi scaling
     const T rv = bv - Au;
-    if (FORM_B) b_out[i] = bv;
+    if (FORM_B) b_out[i] = b0;
     r[i] = rv;
     rh[i] = rv;
     acc[0] += (double)bv * (double)bv;
@@ -236,7 +237,7 @@ struct PhA {
     return first ? q.r : q.r + beta * (q.p - omega * q.v);
   }
   __device__ ERaw efetch(size_t i) const { return {rh[i]}; }
-  __device__ void epilogue(size_t i, T u, T Au, T, uint32_t, const ERaw& e,
+  __device__ void epilogue(size_t i, T u, T Au, T, uint32_t, const ERaw& e, T dg,
                            double (&acc)[NV]) const {
     p_out[i] = u;
     v_out[i] = Au;
@@ -260,7 +261,7 @@ struct PhB {
   __device__ Raw fetch(size_t i) const { return {r[i], v[i]}; }
   __device__ T combine(const Raw& q) const { return q.r - alpha * q.v; }
   __device__ ERaw efetch(size_t) const { return {}; }
-  __device__ void epilogue(size_t i, T s, T Au, T, uint32_t, const ERaw&,
+  __device__ void epilogue(size_t i, T s, T Au, T, uint32_t, const ERaw&, T dg,
                            double (&acc)[NV]) const {
     t[i] = Au;
     acc[0] += (double)Au * (double)s;
@@ -292,7 +293,7 @@ struct PhCgA {
   }
   __device__ T combine(const Raw& z) const { return first ? z.r : z.r + beta * z.d; }
   __device__ ERaw efetch(size_t) const { return {}; }
-  __device__ void epilogue(size_t i, T u, T Au, T, uint32_t, const ERaw&,
+  __device__ void epilogue(size_t i, T u, T Au, T, uint32_t, const ERaw&, T dg,
                            double (&acc)[NV]) const {
     d_out[i] = u;
     q[i] = Au;
@@ -320,7 +321,7 @@ struct PhResid {
   __device__ Raw fetch(size_t i) const { return {(double)x[i]}; }
   __device__ double combine(const Raw& q) const { return q.x; }
   __device__ ERaw efetch(size_t i) const { return {(double)b[i]}; }
-  __device__ void epilogue(size_t i, double, double Au, double, uint32_t, const ERaw& e,
+  __device__ void epilogue(size_t i, double, double Au, double, uint32_t, const ERaw& e, double dg,
                            double (&acc)[NV]) const {
     const double rv = e.b - Au;
     acc[0] += rv * rv;
@@ -386,7 +387,7 @@ struct PhAC {
     if (first) return {T(0), rh[i]};
     return {x[i], rh[i]};
   }
-  __device__ void epilogue(size_t i, const St& u, T Au, T, uint32_t, const ERaw& e,
+  __device__ void epilogue(size_t i, const St& u, T Au, T, uint32_t, const ERaw& e, T dg,
                            double (&acc)[NV]) const {
     if (!first) x[i] = e.x + alpha * u.p_old + omega * u.s;
     r_out[i] = u.r_new;
@@ -416,7 +417,7 @@ struct PhB2 {
   __device__ Raw fetch(size_t i) const { return {r[i], v[i]}; }
   __device__ T combine(const Raw& q) const { return q.r - alpha * q.v; }
   __device__ ERaw efetch(size_t i) const { return {rh[i]}; }
-  __device__ void epilogue(size_t i, T s, T Au, T, uint32_t, const ERaw& e,
+  __device__ void epilogue(size_t i, T s, T Au, T, uint32_t, const ERaw& e, T dg,
                            double (&acc)[NV]) const {
     t[i] = Au;
     acc[0] += (double)Au * (double)s;

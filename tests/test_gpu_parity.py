@@ -374,3 +374,32 @@ def test_bicgstab2_timestep_and_paths(wfa, oracle_mod):
     b32 = g32.rhs(g32.field(prob.T0))
     x, info = g32.solve(b32, g32.field(prob.T0), tol=1e-5, maxit=5000, method="bicgstab2")
     assert info.status == wfa.OK and info.rel_res_true <= 2e-5
+
+
+@pytest.mark.parametrize("method", ["bicgstab", "bicgstab2"])
+def test_jacobi_scaling_matches_oracle(wfa, oracle_mod, method):
+    """Left Jacobi scaling D^{-1} A x = D^{-1} b, D computed in the kernels:
+    trajectory against the oracle's scaled BiCGStab (textbook organisation),
+    and the converged solution against the unscaled oracle solve."""
+    prob = inputs.random_problem(114, 30, 22, 17, cell=True, u=(1.0, 0.5, 0.25),
+                                 bc_kind=inputs.MIXED_BC_KIND, sigma=2.0)
+    o = oracle_mod.Oracle(prob)
+    b = o.rhs(prob.T0)
+    g = _grid(wfa, prob, wfa.F64)
+    g.set_option(wfa.OPT_JACOBI, 1)
+    if method == "bicgstab":
+        for k in (1, 4):
+            xo, io = o.bicgstab_jacobi(b, prob.T0, 1e-300, k)
+            x, info = g.solve(g.field(b), g.field(prob.T0), tol=1e-300, maxit=k)
+            assert info.iterations == k
+            assert rel_l2(to_np(x), xo) <= 1e-12
+    xs, io = o.bicgstab(b, prob.T0, 1e-13, 5000)
+    xj, ij = o.bicgstab_jacobi(b, prob.T0, 1e-13, 5000)
+    x, info = g.solve(g.field(b), g.field(prob.T0), tol=1e-13, maxit=5000, method=method)
+    assert info.status == wfa.OK
+    assert info.iterations < 0.7 * io.iterations          # scaling pays at high contrast
+    assert abs(info.iterations - ij.iterations) <= 0.1 * ij.iterations + 2
+    assert o.true_relres(b, to_np(x)) <= 1e-12
+    assert rel_l2(to_np(x), xs) <= 1e-9
+    # the operator entry points stay unscaled
+    assert rel_l2(to_np(g.apply(g.field(prob.T0))), o.apply(prob.T0)) <= FP64_TOL

@@ -63,6 +63,9 @@ MUTANTS = [
     ("bicgstab2_r_update_sign", "r[c] = sc - omega * t[c];", "r[c] = sc + omega * t[c];"),
     ("bicgstab2_p_update", "pv[c] = r[c] + beta * (pv[c] - omega * v[c]);\n      }",
      "pv[c] = r[c] + beta * pv[c];\n      }"),
+    ("jacobi_multiplies", "y[cell_index(p, i, j, k)] /= diag;",
+     "y[cell_index(p, i, j, k)] *= diag;"),
+    ("jacobi_rhs_unscaled", "out[c] = b[c] / diag;", "out[c] = b[c];"),
     ("dot_drops_last_plane", "for (int k = 0; k < nz; ++k) total += part[k];",
      "for (int k = 0; k + 1 < nz; ++k) total += part[k];"),
 ]

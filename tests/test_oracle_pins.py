@@ -450,3 +450,32 @@ def test_bicgstab2_status_paths_and_stop_rule(oracle_mod):
     assert np.array_equal(x1 * s, x2)
     _, i0 = o.bicgstab2(b, p.T0, tol, i1.iterations - 1)
     assert i0.status == oracle_mod.NOCONV and i0.rel_res_recursive > tol
+
+
+# ------------------------------------------------------ left Jacobi scaling
+@pytest.mark.parametrize("name", sorted(P5_CASES))
+def test_bicgstab_jacobi_dense_direct_solve(oracle_mod, name):
+    """D^{-1} A x = D^{-1} b has the solution of A x = b (LAPACK on A)."""
+    p = inputs.random_problem(56, 4, 4, 4, sigma=2.0, **P5_CASES[name])
+    o = oracle_mod.Oracle(p)
+    A = dense_by_columns(o)
+    b = o.rhs(p.T0)
+    x_ref = np.linalg.solve(A, b.ravel()).reshape(p.shape)
+    x, info = o.bicgstab_jacobi(b, p.T0, 1e-14, 400)
+    assert info.status == oracle_mod.OK
+    assert rel_l2(x, x_ref) <= 1e-12
+
+
+def test_bicgstab_jacobi_recursive_residual_is_scaled(oracle_mod):
+    """The recursive residual is D^{-1} (b - A x), D = diag(A) read off the
+    dense operator."""
+    p = inputs.random_problem(57, 6, 5, 4, u=(2.0, 1.0, 0.0), sigma=2.0)
+    o = oracle_mod.Oracle(p)
+    A = dense_by_columns(o)
+    d = np.diag(A).reshape(p.shape)
+    b = o.rhs(p.T0)
+    for k in (1, 3, 6):
+        x, info, r = o.bicgstab_jacobi(b, np.zeros(p.shape), 0.0, k, want_r=True)
+        assert np.linalg.norm(r - (b - o.apply(x)) / d) <= 1e-13 * np.linalg.norm(b / d)
+        scaled = np.linalg.norm(r) / np.linalg.norm(b / d)
+        assert abs(info.rel_res_recursive - scaled) <= 1e-12 * scaled
