@@ -271,8 +271,10 @@ def run_mixed384(args, torch, inputs, wfa):
     out = {"workload": f"mixed_{prob.nx}^3", "results": []}
     Tref = None
     for tol in (1e-10, 1e-12):
-        for name, prec in (("f64", wfa.F64), ("f32_ir64", wfa.F32_IR64)):
+        for name, prec, jac in (("f64", wfa.F64, 0), ("f64_jacobi", wfa.F64, 1),
+                                ("f32_ir64", wfa.F32_IR64, 0)):
             g = wfa.Grid.from_problem(prob, precision=prec)
+            g.set_option(wfa.OPT_JACOBI, jac)
             T = g.field(prob.T0)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -329,6 +331,32 @@ def run_serve(args, torch, inputs, wfa):
             "budget_gb": args.budget_gb}
 
 
+def run_explicit(args, torch, inputs, wfa):
+    """Explicit forward-time heat steps (Eq. 2, omega = 1/10, constant
+    diffusivity, Dirichlet 0) on 512x512x1024 in FP32: the paper's explicit
+    benchmark kernel; its bound is R = w_m / (8 W) iterations per second."""
+    nx, ny, nz = 512, 512, 1024
+    h = inputs.grid_spacing(nx, ny, nz)
+    g = wfa.Grid(nx, ny, nz, h=h, dt=0.1 * h * h, alpha=1.0, precision=wfa.F32)
+    T = g.field(inputs.random_field(6, (nz, ny, nx), dtype="float32"))
+    g.explicit(T, 4)
+    torch.cuda.synchronize()
+    g.set_option(wfa.OPT_PROFILE, 1)
+    g.kernel_stats(wfa.K_EXPLICIT, reset=True)
+    steps = 100
+    t0 = time.perf_counter()
+    g.explicit(T, steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    n, ms, by = g.kernel_stats(wfa.K_EXPLICIT)
+    cells = nx * ny * nz
+    return {"workload": "explicit_heat_512x512x1024_f32", "steps": steps, "seconds": dt,
+            "steps_per_s": steps / dt, "cell_steps_per_s": cells * steps / dt,
+            "gbps": 8 * cells * steps / dt / 1e9, "frac_8tbs": 8 * cells * steps / dt / 8e12,
+            "kernel_us_avg": ms / n * 1e3, "kernel_gbps": by / (ms / n * 1e-3) / 1e9,
+            "bound_steps_per_s_8tbs": 8e12 / (8 * cells)}
+
+
 METHODS = {"bicgstab": 0, "cg": 1, "bicgstab2": 2}
 STREAMS = {"bicgstab": 17, "cg": 10, "bicgstab2": 14}
 
@@ -339,7 +367,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="convdiff",
-                    choices=["convdiff", "heat32", "poisson_large", "mixed384", "serve"])
+                    choices=["convdiff", "heat32", "poisson_large", "mixed384", "serve", "explicit"])
     ap.add_argument("--method", default="bicgstab2", choices=["bicgstab", "bicgstab2"])
     ap.add_argument("--compare", type=int, default=1,
                     help="also time the textbook three-pass BiCGStab on the same steps")
@@ -375,7 +403,7 @@ def main():
     if args.probe_copy:
         print(json.dumps({"copy_probe_gbps": wfa.stream_probe(1 << 30, 1)}), file=sys.stderr)
     run = {"convdiff": run_convdiff, "heat32": run_heat32, "poisson_large": run_poisson_large,
-           "mixed384": run_mixed384, "serve": run_serve}[args.workload]
+           "mixed384": run_mixed384, "serve": run_serve, "explicit": run_explicit}[args.workload]
     print(json.dumps(run(args, torch, inputs, wfa)))
 
 

@@ -162,6 +162,14 @@ int wfa_bicgstab2_solve(wfa_grid* g, const void* b, void* x, double tol, int max
 int wfa_timestep(wfa_grid* g, void* T, int nsteps, double tol, int maxit,
                  wfa_solve_info* info, void* stream);
 
+/* nsteps explicit forward-time steps in place (section 1.1.1, Eq. 2,
+ * generalised like the operator): T' = T - (A T - T) + boundary terms, i.e.
+ * each cell gains the net face flux of the old time level.  Stable only for
+ * small steps (Eq. 2: omega = alpha dt / h^2 < 1/6 for pure diffusion); the
+ * caller chooses dt.  Uses the grid's workspace as the second time level.
+ * WFA_F64 and WFA_F32 grids.  Asynchronous on `stream`. */
+int wfa_explicit_step(wfa_grid* g, void* T, int nsteps, void* stream);
+
 /* FP64 true relative residual ||b - A x|| / ||b|| (FP64 fields only, i.e.
  * WFA_F64 or WFA_F32_IR64 grids).  Synchronises `stream`. */
 int wfa_true_residual(wfa_grid* g, const void* b, const void* x, double* rel, void* stream);
@@ -198,7 +206,7 @@ enum {
   WFA_K_APPLY = 0, WFA_K_INIT = 1, WFA_K_PHASE_A = 2, WFA_K_PHASE_B = 3,
   WFA_K_PHASE_C = 4, WFA_K_RESIDUAL = 5, WFA_K_PROMOTE = 6, WFA_K_CG_A = 7,
   WFA_K_CG_B = 8, WFA_K_PERSISTENT = 9, WFA_K_PHASE_AC = 10, WFA_K_PHASE_B2 = 11,
-  WFA_K_COUNT = 12
+  WFA_K_EXPLICIT = 12, WFA_K_COUNT = 13
 };
 /* With WFA_OPT_PROFILE on: launches and summed event time (ms) of one
  * kernel since the last reset; `bytes` = algorithmic HBM bytes per launch

@@ -628,6 +628,42 @@ int orc_timestep(const orc_problem* p, double* T, int nsteps, double tol,
   return status;
 }
 
+/*
+ * Explicit forward-time step (section 1.1.1, Eq. 2), generalised like the
+ * implicit operator: each cell gains the net flux through its faces at the
+ * old time level,
+ *   T'_P = T_P - [ (A[P,P] - 1) T_P + sum_f A[P,N_f] T_N ] + bterm_P,
+ * which for a constant diffusivity and Dirichlet faces is Eq. 2 with the
+ * ghost cells as the boundary cells held at their value.  nsteps steps in
+ * place.
+ */
+void orc_explicit(const orc_problem* p, double* T, int nsteps)
+{
+  const int nx = p->nx, ny = p->ny, nz = p->nz;
+  const long n = cells(p);
+  double* Tn = (double*)malloc(sizeof(double) * (size_t)n);
+  for (int step = 0; step < nsteps; ++step) {
+    memcpy(Tn, T, sizeof(double) * (size_t)n);
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < nz; ++k)
+      for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+          double diag, off[6], bterm;
+          orc_row(p, i, j, k, &diag, off, &bterm);
+          const long c = cell_index(p, i, j, k);
+          double flux = (diag - 1.0) * Tn[c];
+          if (i > 0)      flux += off[0] * Tn[cell_index(p, i - 1, j, k)];
+          if (i < nx - 1) flux += off[1] * Tn[cell_index(p, i + 1, j, k)];
+          if (j > 0)      flux += off[2] * Tn[cell_index(p, i, j - 1, k)];
+          if (j < ny - 1) flux += off[3] * Tn[cell_index(p, i, j + 1, k)];
+          if (k > 0)      flux += off[4] * Tn[cell_index(p, i, j, k - 1)];
+          if (k < nz - 1) flux += off[5] * Tn[cell_index(p, i, j, k + 1)];
+          T[c] = Tn[c] - flux + bterm;
+        }
+  }
+  free(Tn);
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP

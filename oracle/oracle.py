@@ -95,6 +95,7 @@ def load(path: str | None = None) -> ctypes.CDLL:
     lib.orc_bicgstab2.argtypes = [P, D, D, ctypes.c_double, ctypes.c_int, D, I]
     lib.orc_bicgstab_jacobi.argtypes = [P, D, D, ctypes.c_double, ctypes.c_int, D, I]
     lib.orc_timestep.argtypes = [P, D, ctypes.c_int, ctypes.c_double, ctypes.c_int, I]
+    lib.orc_explicit.argtypes = [P, D, ctypes.c_int]
     lib.orc_num_threads.restype = ctypes.c_int
     lib.orc_set_num_threads.argtypes = [ctypes.c_int]
     _lib_cache[path] = lib
@@ -198,6 +199,16 @@ class Oracle:
         self.lib.orc_timestep(self._p, self._ptr(T), int(nsteps), float(tol), int(maxit), infos)
         return T, [SolveInfo(i.status, i.iterations, i.restarts, i.rel_res_recursive,
                              i.rel_res_true) for i in infos[:nsteps]]
+
+
+def _explicit(self, T, nsteps: int) -> np.ndarray:
+    """nsteps explicit forward-time steps (oracle.c orc_explicit)."""
+    T = self._vec(T).copy()
+    self.lib.orc_explicit(self._p, self._ptr(T), int(nsteps))
+    return T
+
+
+Oracle.explicit = _explicit
 
 
 def num_threads() -> int:

@@ -19,14 +19,15 @@ HIPCC_FLAGS = [
 ]
 
 
-def build(verbose: bool = False, jobs: int = 4) -> str:
+def build(verbose: bool = False, jobs: int = 4, out: str | None = None,
+          defines: tuple[str, ...] = ()) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    objdir = os.path.join(HERE, "_build")
+    objdir = os.path.join(HERE, "_build" + ("_" + "_".join(d.lower() for d in defines) if defines else ""))
     os.makedirs(objdir, exist_ok=True)
     objs, procs = [], []
     for src in SOURCES:
         obj = os.path.join(objdir, src.replace(".hip", ".o"))
-        cmd = [hipcc, *HIPCC_FLAGS, "-I", INCLUDE, "-I", CSRC, "-c",
+        cmd = [hipcc, *HIPCC_FLAGS, *[f"-D{d}" for d in defines], "-I", INCLUDE, "-I", CSRC, "-c",
                os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
@@ -37,18 +38,19 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
             procs[0][1].wait()
     failed = []
     for src, p in procs:
-        out, _ = p.communicate()
-        if out and (verbose or p.returncode):
-            print(out, file=sys.stderr)
+        log, _ = p.communicate()
+        if log and (verbose or p.returncode):
+            print(log, file=sys.stderr)
         if p.returncode:
             failed.append(src)
     if failed:
         raise RuntimeError(f"hipcc failed on {failed}")
-    tmp = LIB + ".tmp"
+    lib = out or LIB
+    tmp = lib + ".tmp"
     cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread"]
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

@@ -262,11 +262,11 @@ namespace wfa {
 
 void Profiler::clear() {
   for (auto& p : pending) {
-    hipEventDestroy(p.e0);
-    hipEventDestroy(p.e1);
+    (void)hipEventDestroy(p.e0);   // teardown: nothing to report a failure to
+    (void)hipEventDestroy(p.e1);
   }
   pending.clear();
-  for (auto e : pool) hipEventDestroy(e);
+  for (auto e : pool) (void)hipEventDestroy(e);
   pool.clear();
 }
 
@@ -296,23 +296,32 @@ void Profiler::drain() {
 
 }  // namespace wfa
 
-// Bracket one launch with events when profiling.
+// Bracket one launch with events when profiling.  A launch whose events
+// could not be created or recorded is simply not counted.
 struct ProfScope {
   wfa_grid* g;
   int kernel;
   hipStream_t s;
   hipEvent_t e0 = nullptr, e1 = nullptr;
+  bool armed = false;
   ProfScope(wfa_grid* g_, int k, hipStream_t s_) : g(g_), kernel(k), s(s_) {
     if (g->profile) {
       e0 = g->prof.get();
       e1 = g->prof.get();
-      if (e0 && e1) hipEventRecord(e0, s);
+      armed = e0 && e1 && hipEventRecord(e0, s) == hipSuccess;
+      if (!armed) {
+        if (e0) g->prof.pool.push_back(e0);
+        if (e1) g->prof.pool.push_back(e1);
+      }
     }
   }
   ~ProfScope() {
-    if (g->profile && e0 && e1) {
-      hipEventRecord(e1, s);
+    if (!armed) return;
+    if (hipEventRecord(e1, s) == hipSuccess) {
       g->prof.pending.push_back({kernel, e0, e1});
+    } else {
+      g->prof.pool.push_back(e0);
+      g->prof.pool.push_back(e1);
     }
   }
 };
@@ -333,6 +342,7 @@ static double bytes_per_cell(const wfa_grid* g, int kernel) {
     case WFA_K_CG_B: return 6 * wi;
     case WFA_K_PERSISTENT: return 17 * wi + 2 * k;
     case WFA_K_PHASE_AC: return 10 * wi + k;
+    case WFA_K_EXPLICIT: return 2 * w + k;
     case WFA_K_PHASE_B2: return 4 * wi + k;
     default: return 0.0;
   }
@@ -694,6 +704,14 @@ static int solve_plain(wfa_grid* g, const T* b_user, T* x, bool form_b, double t
   return status;
 }
 
+// Inner iterations allowed per refinement: the remaining budget, capped so
+// that a slowly converging FP32 solve still hands back a correction.
+int wfa::ir_inner_maxit(int maxit, int used) {
+  const int left = maxit - used;
+  const int cap = maxit / 4 > 500 ? maxit / 4 : 500;
+  return left < cap ? left : cap;
+}
+
 // FP32 BiCGStab inside FP64 iterative refinement.
 static int solve_ir(wfa_grid* g, const double* b_user, double* x, bool form_b, double tol,
                     int maxit, wfa_solve_info* info, hipStream_t s) {
@@ -704,8 +722,12 @@ static int solve_ir(wfa_grid* g, const double* b_user, double* x, bool form_b, d
   float* v[2] = {vec[5], vec[6]};
   float* d = g->d32;
   int rc;
-  Launch<double> L64 = ctx<double>(g, g->sc, s);
+  Launch<double> L64 = plain_ctx<double>(g, g->sc, s);
+  // the inner FP32 solve iterates on the Jacobi-scaled system D^{-1} A d =
+  // D^{-1} r: far better conditioned when the diffusivity varies by orders
+  // of magnitude, which FP32 BiCGStab needs to make progress at all there
   Launch<float> L32 = ctx<float>(g, g->sc_in, s);
+  L32.op.jac = 1;
   const double* b = b_user;
   if (form_b) {
     launch_rhs<double>(L64, x, g->b64);
@@ -723,14 +745,15 @@ static int solve_ir(wfa_grid* g, const double* b_user, double* x, bool form_b, d
     ho = fresh_scalars(tol, maxit, 0);
     ho.scale = scale;
     ho.inv_scale = 1.0 / scale;
-    hi = fresh_scalars(g->ir_inner_tol, maxit - total_it, ref == 0 ? force_bd : 0);
+    hi = fresh_scalars(g->ir_inner_tol, ir_inner_maxit(maxit, total_it), ref == 0 ? force_bd : 0);
     hi.scale = scale;
     hi.inv_scale = 1.0 / scale;
+    hi.guard = kIrGuard;
     if ((rc = write_scalars(&ho, g->sc, s))) return rc;
     if ((rc = write_scalars(&hi, g->sc_in, s))) return rc;
     {
       ProfScope ps(g, WFA_K_RESIDUAL, s);
-      launch_residual<double>(L64, x, b, r, rh, g->sc_in, 1);
+      launch_residual<double>(L64, x, b, r, rh, g->sc_in, 2);
     }
     if ((rc = check_launch("residual"))) return rc;
     if ((rc = read_scalars(g, g->sc, &ho, s))) return rc;
@@ -755,6 +778,7 @@ static int solve_ir(wfa_grid* g, const double* b_user, double* x, bool form_b, d
     total_it += hi.iter;
     rec = hi.bb > 0.0 ? sqrt(hi.rr / hi.bb) : 0.0;
     if (hi.status == ST_NONFINITE) { status = WFA_ERR_NONFINITE; break; }
+    if (hi.diverged) { status = WFA_ERR_NOCONV; break; }   // no usable correction
     if (hi.iter > 0) {
       ProfScope ps(g, WFA_K_PROMOTE, s);
       launch_promote(g->n, g->tl.pw_blocks, x, d, g->sc_in, s);
@@ -889,6 +913,29 @@ extern "C" int wfa_rhs(wfa_grid* g, const void* T, void* b, void* stream) {
   else
     launch_rhs<double>(plain_ctx<double>(g, g->sc, s), (const double*)T, (double*)b);
   return check_launch("rhs");
+}
+
+extern "C" int wfa_explicit_step(wfa_grid* g, void* T, int nsteps, void* stream) {
+  if (!g || !T) return set_error(WFA_ERR_INVALID, "NULL argument");
+  if (nsteps < 0) return set_error(WFA_ERR_INVALID, "nsteps must be >= 0");
+  if (g->prec == WFA_F32_IR64)
+    return set_error(WFA_ERR_INVALID, "explicit steps need a WFA_F64 or WFA_F32 grid");
+  hipStream_t s = (hipStream_t)stream;
+  const size_t w = g->prec == WFA_F32 ? 4 : 8;
+  void* bufs[2] = {T, g->vec[0]};
+  for (int k = 0; k < nsteps; ++k) {
+    ProfScope ps(g, WFA_K_EXPLICIT, s);
+    if (g->prec == WFA_F32)
+      launch_explicit<float>(plain_ctx<float>(g, g->sc, s), (const float*)bufs[k & 1],
+                             (float*)bufs[(k + 1) & 1]);
+    else
+      launch_explicit<double>(plain_ctx<double>(g, g->sc, s), (const double*)bufs[k & 1],
+                              (double*)bufs[(k + 1) & 1]);
+  }
+  int rc = check_launch("explicit");
+  if (rc) return rc;
+  if (nsteps & 1) HIP_TRY(hipMemcpyAsync(T, bufs[1], w * g->n, hipMemcpyDeviceToDevice, s));
+  return WFA_OK;
 }
 
 extern "C" int wfa_true_residual(wfa_grid* g, const void* b, const void* x, double* rel,

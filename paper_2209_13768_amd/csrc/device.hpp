@@ -40,10 +40,12 @@ struct alignas(64) Scalars {
   double bb, rr, tol;          // ||b||^2, last ||r||^2, relative tolerance
   double sigma, ts, tt, rr0;   // last reduced values (diagnostics / trace)
   double scale, inv_scale;     // mixed precision: residual scaling by 2^-e
+  double guard;                // > 0: stop (diverged) once ||r||^2 > guard * ||r0||^2
   int32_t status, iter, maxit, first, restart, szero, x_zero, force_bd;
   uint32_t counter;            // last-workgroup arrival counter (self-resetting)
   int32_t restart_pending;     // two-reduction BiCGStab: restart after the update
-  int32_t pad[6];
+  int32_t diverged;            // set with ST_NOCONV when the guard tripped
+  int32_t pad[5];
 };
 
 // Grid-wide barrier state of a persistent launch (self-resetting count).

@@ -42,6 +42,10 @@ struct Profiler {
 };
 
 int set_error(int code, const char* fmt, ...);
+int ir_inner_maxit(int maxit, int used);
+// The inner FP32 solve of iterative refinement stops as diverged once its
+// residual norm has grown 1000-fold (squared: 1e6).
+constexpr double kIrGuard = 1e6;
 int validate_coeffs(int nx, int ny, int nz, const wfa_coeffs* c);
 
 }  // namespace wfa

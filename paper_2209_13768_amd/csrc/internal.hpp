@@ -42,6 +42,9 @@ void launch_init(const Launch<T>& L, bool form_b, const T* x, const T* b_in, T* 
 // b = T + boundary terms only
 template <typename T>
 void launch_rhs(const Launch<T>& L, const T* x, T* b);
+// One explicit forward-time step: y = x - (A x - x) + boundary terms
+template <typename T>
+void launch_explicit(const Launch<T>& L, const T* x, T* y);
 // p' = r + beta (p - omega v) (p' = r on the first iteration); v' = A p';
 // sigma = (rh, v')
 template <typename T>

@@ -87,6 +87,17 @@ void launch_rhs(const Launch<T>& L, const T* x, T* b) {
 }
 
 template <typename T>
+void launch_explicit(const Launch<T>& L, const T* x, T* y) {
+  if (L.cell) {
+    PhExplicit<T, true> ph{L.op, x, y};
+    dispatch_march(L, ph, FinNone{}, false, false);
+  } else {
+    PhExplicit<T, false> ph{L.op, x, y};
+    dispatch_march(L, ph, FinNone{}, false, false);
+  }
+}
+
+template <typename T>
 void launch_init(const Launch<T>& L, bool form_b, const T* x, const T* b_in, T* b_out, T* r,
                  T* rh) {
   FinInit fin{L.sc};
@@ -291,6 +302,7 @@ Tiling make_tiling(int nx, int ny, int nz, int elem_bytes, int zc_override, int 
 #define WFA_INST(T)                                                                           \
   template void launch_apply<T>(const Launch<T>&, const T*, T*);                             \
   template void launch_rhs<T>(const Launch<T>&, const T*, T*);                               \
+  template void launch_explicit<T>(const Launch<T>&, const T*, T*);                          \
   template void launch_init<T>(const Launch<T>&, bool, const T*, const T*, T*, T*, T*);      \
   template void launch_phase_a<T>(const Launch<T>&, const T*, const T*, const T*, T*, T*,    \
                                   const T*);                                                 \

@@ -9,6 +9,17 @@
 
 namespace wfa {
 
+// Loads and stores of values no neighbouring tile reads back soon
+// (epilogue inputs, pass outputs) can carry a streaming hint so that they
+// do not displace the halo rows and planes the L2 is holding.
+#ifdef WFA_STREAM_HINTS
+template <typename T> __device__ __forceinline__ T ld_once(const T* p) { return __builtin_nontemporal_load(p); }
+template <typename T> __device__ __forceinline__ void st_once(T* p, T v) { __builtin_nontemporal_store(v, p); }
+#else
+template <typename T> __device__ __forceinline__ T ld_once(const T* p) { return *p; }
+template <typename T> __device__ __forceinline__ void st_once(T* p, T v) { *p = v; }
+#endif
+
 // ============================================================================
 // finalizers (thread 0 of the last workgroup)
 // ============================================================================
@@ -62,6 +73,7 @@ struct FinC {
     if (sc->szero) sc->status = ST_CONV;
     else if (!fin_ok(rr)) sc->status = ST_NONFINITE;
     else if (sqrt(rr) <= sc->tol * sqrt(sc->bb)) sc->status = ST_CONV;
+    else if (sc->guard > 0.0 && rr > sc->guard * sc->rr0) { sc->status = ST_NOCONV; sc->diverged = 1; }
     else if (sc->omega == 0.0) sc->restart = 1;
     else if (sc->iter >= sc->maxit) sc->status = ST_NOCONV;
     else if (!fin_ok(rho_new)) sc->status = ST_NONFINITE;
@@ -118,7 +130,7 @@ struct FinResid {
       inner->bb = rho; inner->rr = rho; inner->rr0 = rho;
       inner->rho = rho; inner->rho_prev = 1.0; inner->alpha = 1.0; inner->omega = 1.0;
       inner->beta = 0.0; inner->first = 1; inner->restart = 0; inner->szero = 0;
-      inner->x_zero = 1; inner->iter = 0;
+      inner->x_zero = 1; inner->iter = 0; inner->diverged = 0;
       if (sc->status != ST_RUN) inner->status = ST_CONV;
       else if (!fin_ok(rho)) inner->status = ST_NONFINITE;
       else if (rho == 0.0) inner->status = ST_CONV;
@@ -171,6 +183,29 @@ struct PhRhs {
   __device__ void epilogue(size_t i, T u, T, T kP, uint32_t ins, const ERaw&, T dg,
                            double (&)[NV]) const {
     b[i] = u + cell_bterm<T, CELL>(op, kP, ins);
+  }
+};
+
+// Explicit forward-time step (the paper's Eq. 2, generalised like the
+// operator): y = x - (A x - x) + boundary terms.
+template <typename T, bool CELL>
+struct PhExplicit {
+  static constexpr int NV = 1;
+  static constexpr int PD = 2;
+  using St = T;
+  static __device__ __forceinline__ T val(T u) { return u; }
+  Op<T> op;
+  const T* __restrict__ x;
+  T* __restrict__ y;
+  struct Raw { T x; };
+  struct ERaw {};
+  __device__ void bind(const Scalars*) {}
+  __device__ Raw fetch(size_t i) const { return {x[i]}; }
+  __device__ T combine(const Raw& r) const { return r.x; }
+  __device__ ERaw efetch(size_t) const { return {}; }
+  __device__ void epilogue(size_t i, T u, T Au, T kP, uint32_t ins, const ERaw&, T dg,
+                           double (&)[NV]) const {
+    st_once(y + i, u - (Au - u) + cell_bterm<T, CELL>(op, kP, ins));
   }
 };
 
@@ -236,11 +271,11 @@ struct PhA {
   __device__ T combine(const Raw& q) const {
     return first ? q.r : q.r + beta * (q.p - omega * q.v);
   }
-  __device__ ERaw efetch(size_t i) const { return {rh[i]}; }
+  __device__ ERaw efetch(size_t i) const { return {ld_once(rh + i)}; }
   __device__ void epilogue(size_t i, T u, T Au, T, uint32_t, const ERaw& e, T dg,
                            double (&acc)[NV]) const {
-    p_out[i] = u;
-    v_out[i] = Au;
+    st_once(p_out + i, u);
+    st_once(v_out + i, Au);
     acc[0] += (double)e.rh * (double)Au;
   }
 };
@@ -263,7 +298,7 @@ struct PhB {
   __device__ ERaw efetch(size_t) const { return {}; }
   __device__ void epilogue(size_t i, T s, T Au, T, uint32_t, const ERaw&, T dg,
                            double (&acc)[NV]) const {
-    t[i] = Au;
+    st_once(t + i, Au);
     acc[0] += (double)Au * (double)s;
     acc[1] += (double)Au * (double)Au;
   }
@@ -327,7 +362,9 @@ struct PhResid {
     acc[0] += rv * rv;
     acc[1] += e.b * e.b;
     if (emit) {
-      const float r32v = (float)(rv * scale);
+      // emit == 2: the inner solve iterates on D^{-1} A, so its right-hand
+      // side is D^{-1} r
+      const float r32v = (float)((emit == 2 ? rv / dg : rv) * scale);
       r32[i] = r32v;
       rh32[i] = r32v;
       acc[2] += (double)r32v * (double)r32v;
@@ -384,15 +421,15 @@ struct PhAC {
     return {rn + beta * (q.p - omega * q.v), rn, s, q.p};
   }
   __device__ ERaw efetch(size_t i) const {
-    if (first) return {T(0), rh[i]};
-    return {x[i], rh[i]};
+    if (first) return {T(0), ld_once(rh + i)};
+    return {ld_once(x + i), ld_once(rh + i)};
   }
   __device__ void epilogue(size_t i, const St& u, T Au, T, uint32_t, const ERaw& e, T dg,
                            double (&acc)[NV]) const {
-    if (!first) x[i] = e.x + alpha * u.p_old + omega * u.s;
-    r_out[i] = u.r_new;
-    p_out[i] = u.p_new;
-    v_out[i] = Au;
+    if (!first) st_once(x + i, e.x + alpha * u.p_old + omega * u.s);
+    st_once(r_out + i, u.r_new);
+    st_once(p_out + i, u.p_new);
+    st_once(v_out + i, Au);
     acc[0] += (double)e.rh * (double)Au;
     acc[1] += (double)e.rh * (double)u.r_new;
     acc[2] += (double)u.r_new * (double)u.r_new;
@@ -416,10 +453,10 @@ struct PhB2 {
   __device__ void bind(const Scalars* sc) { alpha = (T)sc->alpha; }
   __device__ Raw fetch(size_t i) const { return {r[i], v[i]}; }
   __device__ T combine(const Raw& q) const { return q.r - alpha * q.v; }
-  __device__ ERaw efetch(size_t i) const { return {rh[i]}; }
+  __device__ ERaw efetch(size_t i) const { return {ld_once(rh + i)}; }
   __device__ void epilogue(size_t i, T s, T Au, T, uint32_t, const ERaw& e, T dg,
                            double (&acc)[NV]) const {
-    t[i] = Au;
+    st_once(t + i, Au);
     acc[0] += (double)Au * (double)s;
     acc[1] += (double)Au * (double)Au;
     acc[2] += (double)e.rh * (double)s;

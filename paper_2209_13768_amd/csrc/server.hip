@@ -151,6 +151,12 @@ int fail(wfa_server* sv, const char* what, hipError_t e) {
   return WFA_ERR_HIP;
 }
 
+// Host-to-device copy of scalar blocks; remembers the first failure.
+int put(wfa_server* sv, void* dst, const void* src, size_t bytes) {
+  const hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, sv->stream);
+  return e == hipSuccess ? WFA_OK : fail(sv, "scalar upload", e);
+}
+
 Scalars fresh(double tol, int maxit) {
   Scalars h{};
   h.tol = tol;
@@ -168,6 +174,8 @@ SolveDesc<T> make_desc(Request* r, T* x) {
   const Tiling& tl = (sizeof(T) == 4 && g.prec == WFA_F32_IR64) ? g.tl32 : g.tl;
   d.geo = tl.geo;
   if constexpr (sizeof(T) == 4) d.op = g.op32; else d.op = g.op64;
+  // the inner FP32 solve of refinement iterates on D^{-1} A (as wfa_timestep)
+  d.op.jac = g.prec == WFA_F32_IR64 ? 1u : 0u;
   d.kappa = (const float*)g.c.kappa;
   T** v = (T**)g.vec;
   d.x = x;
@@ -186,21 +194,22 @@ int start_request(wfa_server* sv, Request* r) {
   wfa_grid& g = r->g;
   hipStream_t s = sv->stream;
   if (g.prec == WFA_F32_IR64) {
-    Scalars ho = fresh(r->tol, r->maxit), hi = fresh(1e-4, r->maxit);
+    Scalars ho = fresh(r->tol, r->maxit), hi = fresh(1e-4, ir_inner_maxit(r->maxit, 0));
+    hi.guard = kIrGuard;
     sv->h_sc[r->slot * kScalarsPerSlot + 0] = ho;
     sv->h_sc[r->slot * kScalarsPerSlot + 1] = hi;
-    hipMemcpyAsync(g.sc, &sv->h_sc[r->slot * kScalarsPerSlot], 2 * sizeof(Scalars),
-                   hipMemcpyHostToDevice, s);
+    if (int rc = put(sv, g.sc, &sv->h_sc[r->slot * kScalarsPerSlot], 2 * sizeof(Scalars)))
+      return rc;
     Launch<double> L{g.tl, g.op64, g.c.mode == WFA_COEF_CELL, (const float*)g.c.kappa,
                      g.partials, g.sc, s};
     launch_rhs<double>(L, (const double*)r->T, g.b64);
     float** v = (float**)g.vec;
-    launch_residual<double>(L, (const double*)r->T, g.b64, v[0], v[1], g.sc_in, 1);
+    launch_residual<double>(L, (const double*)r->T, g.b64, v[0], v[1], g.sc_in, 2);
   } else {
     Scalars h = fresh(r->tol, r->maxit);
     sv->h_sc[r->slot * kScalarsPerSlot] = h;
-    hipMemcpyAsync(g.sc, &sv->h_sc[r->slot * kScalarsPerSlot], sizeof(Scalars),
-                   hipMemcpyHostToDevice, s);
+    if (int rc = put(sv, g.sc, &sv->h_sc[r->slot * kScalarsPerSlot], sizeof(Scalars)))
+      return rc;
     if (g.prec == WFA_F64) {
       Launch<double> L{g.tl, g.op64, g.c.mode == WFA_COEF_CELL, (const float*)g.c.kappa,
                        g.partials, g.sc, s};
@@ -226,16 +235,17 @@ int refine_request(wfa_server* sv, Request* r, double scale_next) {
   launch_promote(g.n, g.tl.pw_blocks, (double*)r->T, g.d32, g.sc_in, s);
   Scalars ho = fresh(r->tol, r->maxit);
   ho.scale = scale_next; ho.inv_scale = 1.0 / scale_next;
-  Scalars hi = fresh(1e-4, r->maxit - r->total_it);
+  Scalars hi = fresh(1e-4, ir_inner_maxit(r->maxit, r->total_it));
   hi.scale = scale_next; hi.inv_scale = 1.0 / scale_next;
+  hi.guard = kIrGuard;
   sv->h_sc[r->slot * kScalarsPerSlot + 0] = ho;
   sv->h_sc[r->slot * kScalarsPerSlot + 1] = hi;
-  hipMemcpyAsync(g.sc, &sv->h_sc[r->slot * kScalarsPerSlot], 2 * sizeof(Scalars),
-                 hipMemcpyHostToDevice, s);
+  if (int rc = put(sv, g.sc, &sv->h_sc[r->slot * kScalarsPerSlot], 2 * sizeof(Scalars)))
+    return rc;
   Launch<double> L{g.tl, g.op64, g.c.mode == WFA_COEF_CELL, (const float*)g.c.kappa,
                    g.partials, g.sc, s};
   float** v = (float**)g.vec;
-  launch_residual<double>(L, (const double*)r->T, g.b64, v[0], v[1], g.sc_in, 1);
+  launch_residual<double>(L, (const double*)r->T, g.b64, v[0], v[1], g.sc_in, 2);
   r->scale = scale_next;
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(sv, "refine", e);
@@ -248,8 +258,8 @@ int final_residual(wfa_server* sv, Request* r) {
   wfa_grid& g = r->g;
   hipStream_t s = sv->stream;
   sv->h_sc[r->slot * kScalarsPerSlot + 2] = fresh(1.0, 1);
-  hipMemcpyAsync(g.sc_aux, &sv->h_sc[r->slot * kScalarsPerSlot + 2], sizeof(Scalars),
-                 hipMemcpyHostToDevice, s);
+  if (int rc = put(sv, g.sc_aux, &sv->h_sc[r->slot * kScalarsPerSlot + 2], sizeof(Scalars)))
+    return rc;
   Launch<double> L{g.tl, g.op64, g.c.mode == WFA_COEF_CELL, (const float*)g.c.kappa,
                    g.partials, g.sc_aux, s};
   void** v = g.vec;
@@ -318,6 +328,10 @@ int advance(wfa_server* sv, Request* r) {
     if (in.restart) ++r->restarts;
     if (in.status == ST_NONFINITE) {
       retire(sv, r, WFA_ERR_NONFINITE, NAN);
+      return WFA_OK;
+    }
+    if (in.diverged) {   // no usable correction
+      retire(sv, r, WFA_ERR_NOCONV, sqrt(o.rr / o.bb));
       return WFA_OK;
     }
     if (r->restarts > WFA_MAX_RESTARTS) {
@@ -451,12 +465,12 @@ void worker_main(wfa_server* sv) {
     }
     if (!rc) {
       const int S = sv->max_slots;
-      hipMemcpyAsync(sv->d32, sv->h_d32.data(), sizeof(SolveDesc<float>) * std::max(n32, 1),
-                     hipMemcpyHostToDevice, sv->stream);
-      hipMemcpyAsync(sv->d64, sv->h_d64.data(), sizeof(SolveDesc<double>) * std::max(n64, 1),
-                     hipMemcpyHostToDevice, sv->stream);
-      hipMemcpyAsync(sv->bases, sv->h_bases.data(), sizeof(int) * 4 * (S + 1),
-                     hipMemcpyHostToDevice, sv->stream);
+      rc = put(sv, sv->d32, sv->h_d32.data(), sizeof(SolveDesc<float>) * std::max(n32, 1));
+      if (!rc) rc = put(sv, sv->d64, sv->h_d64.data(), sizeof(SolveDesc<double>) * std::max(n64, 1));
+      if (!rc) rc = put(sv, sv->bases, sv->h_bases.data(), sizeof(int) * 4 * (S + 1));
+    }
+    if (!rc) {
+      const int S = sv->max_slots;
       for (int q = 0; q < sv->chunk; ++q) {
         if (n32) {
           launch_batch_iteration<float>(sv->d32, sv->bases, t32, sv->bases + (S + 1), p32, n32,

@@ -24,16 +24,16 @@ METHOD_BICGSTAB, METHOD_CG, METHOD_BICGSTAB2 = 0, 1, 2
 OPT_METHOD, OPT_PERSISTENT, OPT_PROFILE, OPT_FORCE_BREAKDOWN, OPT_CHECK_EVERY = 1, 2, 3, 4, 5
 OPT_IR_INNER_TOL, OPT_ZCHUNK, OPT_RY, OPT_JACOBI = 6, 7, 8, 9
 K_APPLY, K_INIT, K_PHASE_A, K_PHASE_B, K_PHASE_C, K_RESIDUAL, K_PROMOTE = 0, 1, 2, 3, 4, 5, 6
-K_CG_A, K_CG_B, K_PERSISTENT, K_PHASE_AC, K_PHASE_B2, K_COUNT = 7, 8, 9, 10, 11, 12
+K_CG_A, K_CG_B, K_PERSISTENT, K_PHASE_AC, K_PHASE_B2, K_EXPLICIT, K_COUNT = 7, 8, 9, 10, 11, 12, 13
 KERNEL_NAMES = ("apply", "init", "phase_a", "phase_b", "phase_c", "residual", "promote",
-                "cg_a", "cg_b", "persistent", "phase_ac", "phase_b2")
+                "cg_a", "cg_b", "persistent", "phase_ac", "phase_b2", "explicit")
 
 PRECISIONS = {"f64": F64, "f32": F32, "f32_ir64": F32_IR64}
 
 # Every function the header declares; the library must export all of them.
 EXPORTS = (
     "wfa_workspace_bytes", "wfa_grid_create", "wfa_grid_destroy", "wfa_stencil_apply",
-    "wfa_rhs", "wfa_bicgstab_solve", "wfa_bicgstab2_solve", "wfa_cg_solve", "wfa_timestep", "wfa_true_residual",
+    "wfa_rhs", "wfa_explicit_step", "wfa_bicgstab_solve", "wfa_bicgstab2_solve", "wfa_cg_solve", "wfa_timestep", "wfa_true_residual",
     "wfa_grid_set_option", "wfa_kernel_stats", "wfa_grid_tiling", "wfa_stream_probe",
     "wfa_server_create", "wfa_submit", "wfa_poll", "wfa_server_drain", "wfa_server_destroy",
     "wfa_last_error", "wfa_version",
@@ -101,6 +101,7 @@ def lib() -> ctypes.CDLL:
     L.wfa_grid_destroy.argtypes = [vp]
     L.wfa_stencil_apply.argtypes = [vp, vp, vp, vp]
     L.wfa_rhs.argtypes = [vp, vp, vp, vp]
+    L.wfa_explicit_step.argtypes = [vp, vp, i32, vp]
     L.wfa_bicgstab_solve.argtypes = [vp, vp, vp, dbl, i32, ctypes.POINTER(_Info), vp]
     L.wfa_cg_solve.argtypes = [vp, vp, vp, dbl, i32, ctypes.POINTER(_Info), vp]
     L.wfa_bicgstab2_solve.argtypes = [vp, vp, vp, dbl, i32, ctypes.POINTER(_Info), vp]
@@ -245,6 +246,11 @@ class Grid:
         b = self.field() if b is None else b
         _check(lib().wfa_rhs(self._h, self._v(T, "T"), self._v(b, "b"), _stream_ptr(stream)))
         return b
+
+    def explicit(self, T, nsteps=1, stream=None):
+        """nsteps explicit forward-time steps of T in place."""
+        _check(lib().wfa_explicit_step(self._h, self._v(T, "T"), int(nsteps), _stream_ptr(stream)))
+        return T
 
     def solve(self, b, x=None, *, tol=1e-10, maxit=1000, method="bicgstab", check=True,
               stream=None):

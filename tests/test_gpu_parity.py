@@ -403,3 +403,36 @@ def test_jacobi_scaling_matches_oracle(wfa, oracle_mod, method):
     assert rel_l2(to_np(x), xs) <= 1e-9
     # the operator entry points stay unscaled
     assert rel_l2(to_np(g.apply(g.field(prob.T0))), o.apply(prob.T0)) <= FP64_TOL
+
+
+@pytest.mark.parametrize("name", ["const_dirichlet", "cell_upwind_mixed", "const_upwind_zeroflux"])
+@pytest.mark.parametrize("nsteps", [1, 4, 5])
+def test_explicit_step_matches_oracle(wfa, oracle_mod, name, nsteps):
+    """Explicit forward-time steps (Eq. 2 generalised) at a stable dt."""
+    base = inputs.random_problem(115, 70, 33, 21, **VARIANTS[name])
+    prob = base.with_(dt=0.05 * base.h ** 2 / (1.0 if base.kappa is None else float(base.kappa.max())))
+    o = oracle_mod.Oracle(prob)
+    To = o.explicit(prob.T0, nsteps)
+    for precision, tol in ((wfa.F64, FP64_TOL), (wfa.F32, FP32_TOL)):
+        g = _grid(wfa, prob, precision)
+        T = g.field(prob.T0)
+        g.explicit(T, nsteps)
+        assert rel_l2(to_np(T), To) <= tol
+
+
+def test_explicit_step_is_eq2_on_gpu(wfa):
+    nx, ny, nz = 66, 20, 13
+    h = inputs.grid_spacing(nx, ny, nz)
+    omega, gamma = 0.1, 0.25
+    prob = inputs.Problem(nx, ny, nz, h=h, dt=omega * h * h, alpha=1.0, bc_value=(gamma,) * 6)
+    T0 = np.random.default_rng(64).random(prob.shape)
+    ref = T0.copy()
+    for _ in range(3):
+        P = np.pad(ref, 1, constant_values=gamma)
+        nb = (P[:-2, 1:-1, 1:-1] + P[2:, 1:-1, 1:-1] + P[1:-1, :-2, 1:-1] + P[1:-1, 2:, 1:-1]
+              + P[1:-1, 1:-1, :-2] + P[1:-1, 1:-1, 2:])
+        ref = omega * nb + (1 - 6 * omega) * ref
+    g = _grid(wfa, prob, wfa.F64)
+    T = g.field(T0)
+    g.explicit(T, 3)
+    assert np.max(np.abs(to_np(T) - ref)) <= 1e-14

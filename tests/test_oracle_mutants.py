@@ -66,6 +66,9 @@ MUTANTS = [
     ("jacobi_multiplies", "y[cell_index(p, i, j, k)] /= diag;",
      "y[cell_index(p, i, j, k)] *= diag;"),
     ("jacobi_rhs_unscaled", "out[c] = b[c] / diag;", "out[c] = b[c];"),
+    ("explicit_flux_sign", "T[c] = Tn[c] - flux + bterm;", "T[c] = Tn[c] + flux + bterm;"),
+    ("explicit_keeps_identity", "double flux = (diag - 1.0) * Tn[c];",
+     "double flux = diag * Tn[c];"),
     ("dot_drops_last_plane", "for (int k = 0; k < nz; ++k) total += part[k];",
      "for (int k = 0; k + 1 < nz; ++k) total += part[k];"),
 ]

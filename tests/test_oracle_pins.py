@@ -479,3 +479,49 @@ def test_bicgstab_jacobi_recursive_residual_is_scaled(oracle_mod):
         assert np.linalg.norm(r - (b - o.apply(x)) / d) <= 1e-13 * np.linalg.norm(b / d)
         scaled = np.linalg.norm(r) / np.linalg.norm(b / d)
         assert abs(info.rel_res_recursive - scaled) <= 1e-12 * scaled
+
+
+# ------------------------------------------------------ explicit forward step
+def _eq2_step(T, omega, gamma):
+    """Eq. 2 of the paper on a grid padded with boundary cells held at gamma:
+    T' = omega * (sum of the six neighbours) + (1 - 6 omega) T."""
+    P = np.pad(T, 1, constant_values=gamma)
+    nb = (P[:-2, 1:-1, 1:-1] + P[2:, 1:-1, 1:-1] + P[1:-1, :-2, 1:-1] + P[1:-1, 2:, 1:-1]
+          + P[1:-1, 1:-1, :-2] + P[1:-1, 1:-1, 2:])
+    return omega * nb + (1 - 6 * omega) * T
+
+
+def test_explicit_step_is_eq2(oracle_mod):
+    """Constant diffusivity, Dirichlet faces all at gamma, omega = 1/10 (the
+    paper's test value): the oracle's explicit step is Eq. 2 exactly."""
+    nx, ny, nz = 9, 7, 6
+    h = grid_spacing(nx, ny, nz)
+    omega = 0.1
+    gamma = 0.35
+    p = inputs.Problem(nx, ny, nz, h=h, dt=omega * h * h, alpha=1.0, bc_value=(gamma,) * 6)
+    o = oracle_mod.Oracle(p)
+    T = np.random.default_rng(61).random(p.shape)
+    ref = T.copy()
+    for _ in range(4):
+        ref = _eq2_step(ref, omega, gamma)
+    assert np.max(np.abs(o.explicit(T, 4) - ref)) <= 1e-14
+
+
+def test_explicit_eigenmode_and_max_principle(oracle_mod):
+    nx, ny, nz = 8, 6, 5
+    p = const_problem(nx, ny, nz, alpha=1.0, dt=0.1 * grid_spacing(nx, ny, nz) ** 2)
+    o = oracle_mod.Oracle(p)
+    v = sine_mode(nx, ny, nz, 2, 1, 3)
+    lam = 1.0 / p.h**2 * sum(4 * np.sin(np.pi * m / (2 * (n + 1)))**2
+                             for m, n in zip((2, 1, 3), (nx, ny, nz)))
+    assert np.max(np.abs(o.explicit(v, 3) - (1 - p.dt * lam) ** 3 * v)) <= 1e-13
+    T = np.random.default_rng(62).random(p.shape)       # omega < 1/6: no new extrema
+    T5 = o.explicit(T, 5)
+    assert T5.min() >= min(T.min(), 0.0) - 1e-15 and T5.max() <= T.max() + 1e-15
+
+
+def test_explicit_conserves_with_zero_flux(oracle_mod):
+    p = inputs.random_problem(63, 9, 7, 6, u=(3.0, -2.0, 1.0), bc_kind=(ZEROFLUX,) * 6, dt=1e-4)
+    o = oracle_mod.Oracle(p)
+    T3 = o.explicit(p.T0, 3)
+    assert abs(T3.sum() - p.T0.sum()) <= 1e-12 * p.T0.sum()
