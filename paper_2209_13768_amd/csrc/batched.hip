@@ -26,7 +26,7 @@ k_batch_march(const SolveDesc<T>* __restrict__ descs, const int* __restrict__ ba
               int nsolves, int parity) {
   using TS = TileShape<RY>;
   __shared__ T su[2 * TS::LH * TS::LW];
-  __shared__ T sk[2 * TS::LH * TS::LW];
+  __shared__ float sk[2 * TS::LH * TS::LW];
   __shared__ double red[kWaves * 2];
   const int s = find_solve(bases, nsolves, blockIdx.x);
   const SolveDesc<T> d = descs[s];

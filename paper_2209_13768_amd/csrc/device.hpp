@@ -246,7 +246,12 @@ __device__ __forceinline__ void publish_and_finalize(double (&v)[NV], int slot, 
 // one plane of work hides each load's latency.
 //
 // Phase policy Ph provides:
-//   struct Raw;  Raw fetch(size_t idx);  St combine(const Raw&);  -- stage
+//   struct Raw;  Raw fetch(size_t idx);  T-like combine(const Raw&)  -- stage of
+//                                         halo cells and the z-halo plane k0-1
+//   struct ORaw; ORaw fetch_own(size_t idx);                        -- own cells
+//   St combine_own(const ORaw&, size_t idx, acc)  -- own cells of output planes;
+//                                         may store and accumulate (once per cell)
+//   T value_own(const ORaw&)              -- own cells of the z-halo plane k1
 //   St;  static T val(const St&)        -- staged struct and its stencil value
 //   struct ERaw; ERaw efetch(size_t idx);                         -- epilogue loads
 //   static constexpr int NV;                                      -- dot partials
@@ -265,7 +270,7 @@ template <typename T, bool CELL, int RY, class Ph>
 __device__ __forceinline__ void march_tile(const Geo& g, const Op<T>& op,
                                            const float* __restrict__ kappa, int tile,
                                            Ph& ph, double (&acc)[Ph::NV], T* su,
-                                           T* sk) {
+                                           float* sk) {
   using TS = TileShape<RY>;
   constexpr int TY = TS::TY, LW = TS::LW, LH = TS::LH;
   constexpr int PD = Ph::PD;  // planes of loads in flight ahead of the compute
@@ -313,11 +318,12 @@ __device__ __forceinline__ void march_tile(const Geo& g, const Op<T>& op,
   }
 
   using Raw = typename Ph::Raw;
+  using ORaw = typename Ph::ORaw;
   using ERaw = typename Ph::ERaw;
   // Loads of one plane that are in flight: own cells' stage inputs and
   // diffusivity, the halo cell's, and the epilogue's inputs.
   struct PlaneLoads {
-    Raw o[RY];
+    ORaw o[RY];
     float ko[RY];
     Raw h;
     float kh;
@@ -331,7 +337,7 @@ __device__ __forceinline__ void march_tile(const Geo& g, const Op<T>& op,
     for (int r = 0; r < RY; ++r) {
       if (stage && own[r]) {
         const size_t idx = (size_t)kp * plane + poff[r];
-        S.o[r] = ph.fetch(idx);
+        S.o[r] = ph.fetch_own(idx);
         if (CELL) S.ko[r] = kappa[idx];
       }
       if (kp < k1 && own[r]) S.e[r] = ph.efetch((size_t)kp * plane + poff[r]);
@@ -346,33 +352,34 @@ __device__ __forceinline__ void march_tile(const Geo& g, const Op<T>& op,
   using St = typename Ph::St;  // staged value (and what the epilogue needs of it)
   T up[RY];
   St uc[RY];
-  T kpv[RY], kcv[RY];
-  T hc = T(0), kh = T(0);
+  float kpv[RY], kcv[RY];   // diffusivity stays FP32 (as stored) until used
+  T hc = T(0);
+  float kh = 1.f;
   ERaw ec[RY];
 
   // plane k0 - 1 (own cells only) and plane k0 (own + halo), staged directly
 #pragma unroll
   for (int r = 0; r < RY; ++r) {
     up[r] = T(0);
-    kpv[r] = T(1);
+    kpv[r] = 1.f;
     if (k0 > 0 && own[r]) {
       const size_t idx = (size_t)(k0 - 1) * plane + poff[r];
       up[r] = Ph::val(ph.combine(ph.fetch(idx)));
-      if (CELL) kpv[r] = (T)kappa[idx];
+      if (CELL) kpv[r] = kappa[idx];
     }
     uc[r] = St{};
-    kcv[r] = T(1);
+    kcv[r] = 1.f;
     if (own[r]) {
       const size_t idx = (size_t)k0 * plane + poff[r];
-      uc[r] = ph.combine(ph.fetch(idx));
-      if (CELL) kcv[r] = (T)kappa[idx];
+      uc[r] = ph.combine_own(ph.fetch_own(idx), idx, acc);
+      if (CELL) kcv[r] = kappa[idx];
       ec[r] = ph.efetch(idx);
     }
   }
   if (hval) {
     const size_t idx = (size_t)k0 * plane + hoff;
     hc = Ph::val(ph.combine(ph.fetch(idx)));
-    if (CELL) kh = (T)kappa[idx];
+    if (CELL) kh = kappa[idx];
   }
   PlaneLoads L0, L1;
   issue(L0, k0 + 1);
@@ -383,7 +390,7 @@ __device__ __forceinline__ void march_tile(const Geo& g, const Op<T>& op,
   // with plane k+1+PD.
   auto step = [&](int k, PlaneLoads& S) {
     T* Lu = su + buf * (LH * LW);
-    T* Lk = CELL ? sk + buf * (LH * LW) : nullptr;
+    float* Lk = CELL ? sk + buf * (LH * LW) : nullptr;
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
       Lu[lidx[r]] = Ph::val(uc[r]);
@@ -391,29 +398,40 @@ __device__ __forceinline__ void march_tile(const Geo& g, const Op<T>& op,
     }
     if (hl >= 0) {
       Lu[hl] = hval ? hc : T(0);
-      if (CELL) Lk[hl] = hval ? kh : T(1);
+      if (CELL) Lk[hl] = hval ? kh : 1.f;
     }
     __syncthreads();
 
-    // stage plane k + 1 from its (now due) loads
+    // stage plane k + 1 from its (now due) loads; an output plane's own
+    // cells go through combine_own (which may store and accumulate), the
+    // z-halo plane k1 only yields the stencil value
     const bool has_n = (k + 1 <= k1) && (k + 1 < nz);
+    const bool out_n = k + 1 < k1;
     St un[RY];
-    T knv[RY];
+    T unv[RY];
+    float knv[RY];
     ERaw en[RY];
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
       un[r] = St{};
-      knv[r] = T(1);
+      unv[r] = T(0);
+      knv[r] = 1.f;
       if (has_n && own[r]) {
-        un[r] = ph.combine(S.o[r]);
-        if (CELL) knv[r] = (T)S.ko[r];
+        if (out_n) {
+          un[r] = ph.combine_own(S.o[r], (size_t)(k + 1) * plane + poff[r], acc);
+          unv[r] = Ph::val(un[r]);
+        } else {
+          unv[r] = ph.value_own(S.o[r]);
+        }
+        if (CELL) knv[r] = S.ko[r];
       }
       en[r] = S.e[r];
     }
-    T hn = T(0), khn = T(1);
+    T hn = T(0);
+    float khn = 1.f;
     if (hval && k + 1 < k1) {
       hn = Ph::val(ph.combine(S.h));
-      if (CELL) khn = (T)S.kh;
+      if (CELL) khn = S.kh;
     }
     issue(S, k + 1 + PD);
 
@@ -423,19 +441,19 @@ __device__ __forceinline__ void march_tile(const Geo& g, const Op<T>& op,
     for (int r = 0; r < RY; ++r) {
       if (own[r]) {
         const int l = lidx[r];
-        T nb[6] = {Lu[l - 1], Lu[l + 1], Lu[l - LW], Lu[l + LW], up[r], Ph::val(un[r])};
+        T nb[6] = {Lu[l - 1], Lu[l + 1], Lu[l - LW], Lu[l + LW], up[r], unv[r]};
         T kn6[6];
         if (CELL) {
-          kn6[0] = Lk[l - 1]; kn6[1] = Lk[l + 1]; kn6[2] = Lk[l - LW];
-          kn6[3] = Lk[l + LW]; kn6[4] = kpv[r]; kn6[5] = knv[r];
+          kn6[0] = (T)Lk[l - 1]; kn6[1] = (T)Lk[l + 1]; kn6[2] = (T)Lk[l - LW];
+          kn6[3] = (T)Lk[l + LW]; kn6[4] = (T)kpv[r]; kn6[5] = (T)knv[r];
         } else {
 #pragma unroll
           for (int f = 0; f < 6; ++f) kn6[f] = T(1);
         }
         const uint32_t ins = ins_xy[r] | ins_z;
         T dg;
-        const T Au = cell_apply<T, CELL>(op, Ph::val(uc[r]), nb, kcv[r], kn6, ins, dg);
-        ph.epilogue((size_t)k * plane + poff[r], uc[r], Au, kcv[r], ins, ec[r], dg, acc);
+        const T Au = cell_apply<T, CELL>(op, Ph::val(uc[r]), nb, (T)kcv[r], kn6, ins, dg);
+        ph.epilogue((size_t)k * plane + poff[r], uc[r], Au, (T)kcv[r], ins, ec[r], dg, acc);
       }
     }
     // rotate

@@ -33,7 +33,7 @@ k_march(Geo g, Op<T> op, const float* __restrict__ kappa, Ph ph, double* partial
         Scalars* sc, Fin fin, int gated, int publish) {
   using TS = TileShape<RY>;
   __shared__ T su[2 * TS::LH * TS::LW];
-  __shared__ T sk[CELL ? 2 * TS::LH * TS::LW : 1];
+  __shared__ float sk[CELL ? 2 * TS::LH * TS::LW : 1];
   __shared__ double red[kWaves * Ph::NV];
   if (gated && (sc->status != ST_RUN || sc->restart)) return;
   ph.bind(sc);
@@ -199,9 +199,17 @@ __global__ void __launch_bounds__(kThreads) k_fill(size_t n, T* __restrict__ y, 
 
 __global__ void __launch_bounds__(kThreads)
 k_copy(size_t n16, const uint4* __restrict__ src, uint4* __restrict__ dst) {
+  // four 16-byte loads in flight per thread before their stores
   const size_t stride = (size_t)gridDim.x * kThreads;
-  for (size_t e = (size_t)blockIdx.x * kThreads + threadIdx.x; e < n16; e += stride)
-    dst[e] = src[e];
+  size_t e = (size_t)blockIdx.x * kThreads + threadIdx.x;
+  for (; e + 3 * stride < n16; e += 4 * stride) {
+    const uint4 a = src[e], b = src[e + stride], c = src[e + 2 * stride], d = src[e + 3 * stride];
+    dst[e] = a;
+    dst[e + stride] = b;
+    dst[e + 2 * stride] = c;
+    dst[e + 3 * stride] = d;
+  }
+  for (; e < n16; e += stride) dst[e] = src[e];
 }
 
 static size_t cells_of(const Geo& g) { return (size_t)g.plane * (size_t)g.nz; }
@@ -238,7 +246,7 @@ double copy_probe(const void* src, void* dst, size_t bytes, int reps, hipStream_
   if (*err != hipSuccess) return 0.0;
   *err = hipEventCreate(&e1);
   if (*err != hipSuccess) { hipEventDestroy(e0); return 0.0; }
-  const int blocks = 256 * 16;
+  const int blocks = 256 * 8;
   hipLaunchKernelGGL(k_copy, dim3(blocks), dim3(kThreads), 0, s, n16, (const uint4*)src, (uint4*)dst);
   hipEventRecord(e0, s);
   for (int i = 0; i < reps; ++i)

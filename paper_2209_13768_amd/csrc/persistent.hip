@@ -87,7 +87,7 @@ template <typename T, bool CELL, int RY>
 __global__ void __launch_bounds__(kThreads) k_persistent_bicgstab(PersistArgs<T> a) {
   using TS = TileShape<RY>;
   __shared__ T su[2 * TS::LH * TS::LW];
-  __shared__ T sk[CELL ? 2 * TS::LH * TS::LW : 1];
+  __shared__ float sk[CELL ? 2 * TS::LH * TS::LW : 1];
   __shared__ double red[kWaves * 2];
   __shared__ Scalars ls;
   if (threadIdx.x == 0) ls = *a.sc;
