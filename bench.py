@@ -36,14 +36,18 @@ HBM_PEAK_GBPS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_convdiff256_f64.json")
 
 
+# The files that define the single-grid solver kernels and their launch
+# shapes: counter figures taken from other sources are stale.
+KERNEL_SOURCES = ("device.hpp", "phases.hpp", "kernels.hip", "internal.hpp")
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2209_13768_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".hpp")):
-            with open(os.path.join(csrc, name), "rb") as f:
-                h.update(name.encode())
-                h.update(f.read())
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode())
+            h.update(f.read())
     return h.hexdigest()[:16]
 
 
@@ -59,6 +63,91 @@ def load_traffic(kernel: str):
         return None
     k = t.get("kernels", {}).get(kernel)
     return None if k is None else k.get("hbm_bytes_per_launch")
+
+
+# rocprofv3 kernel names -> the names bench.py and the library's kernel
+# statistics use
+KERNEL_PATTERNS = (("PhAC<", "phase_ac"), ("PhB2<", "phase_b2"), ("PhA<", "phase_a"),
+                   ("PhB<", "phase_b"), ("k_phase_c<", "phase_c"), ("PhInit<", "init"),
+                   ("PhResid<", "residual"), ("PhCgA<", "cg_a"), ("k_cg_b<", "cg_b"),
+                   ("PhExplicit<", "explicit"), ("PhApply<", "apply"), ("k_copy", "copy"))
+COPY_PROBE_BYTES = 1 << 30   # --probe-copy: one copy of this many bytes (read and written)
+
+
+def kernel_label(name: str):
+    for pat, label in KERNEL_PATTERNS:
+        if pat in name:
+            return label
+    return None
+
+
+def counter_means(csv_path: str, counter: str):
+    """Mean value of `counter` per dispatch, by kernel label, from a
+    rocprofv3 --pmc counter_collection.csv."""
+    import csv
+    per = {}
+    with open(csv_path) as f:
+        for row in csv.DictReader(f):
+            if row["Counter_Name"] != counter:
+                continue
+            label = kernel_label(row["Kernel_Name"])
+            if label is None:
+                continue
+            d = per.setdefault(label, {})
+            did = row["Dispatch_Id"]
+            d[did] = d.get(did, 0.0) + float(row["Counter_Value"])
+    return {k: (sum(v.values()) / len(v), len(v)) for k, v in per.items()}
+
+
+def summarize_counters(fetch_csv: str, write_csv: str, workload: str, commands: list):
+    """HBM bytes per launch of each kernel from two counter runs (FETCH_SIZE,
+    WRITE_SIZE, KiB per dispatch), each scaled by what the same counter reads
+    for the --probe-copy dispatch of known size.  Writes the traffic file
+    the roofline line reads."""
+    fetch = counter_means(fetch_csv, "FETCH_SIZE")
+    write = counter_means(write_csv, "WRITE_SIZE")
+    if "copy" not in fetch or "copy" not in write:
+        raise SystemExit("the counter runs need the --probe-copy dispatch for calibration")
+    f_fetch = COPY_PROBE_BYTES / (fetch["copy"][0] * 1024.0)
+    f_write = COPY_PROBE_BYTES / (write["copy"][0] * 1024.0)
+    kernels = {}
+    for k in sorted(set(fetch) & set(write)):
+        if k == "copy":
+            continue
+        fk, n = fetch[k]
+        wk, _ = write[k]
+        kernels[k] = {"dispatches": n, "fetch_kib": round(fk, 1), "write_kib": round(wk, 1),
+                      "hbm_bytes_per_launch": round(fk * 1024.0 * f_fetch + wk * 1024.0 * f_write)}
+    out = {"source_hash": kernel_source_hash(), "workload": workload, "commands": commands,
+           "copy_calibration": {"bytes_each_way": COPY_PROBE_BYTES,
+                                "fetch_kib": round(fetch["copy"][0], 1),
+                                "write_kib": round(write["copy"][0], 1),
+                                "fetch_factor": round(f_fetch, 4), "write_factor": round(f_write, 4)},
+           "kernels": kernels}
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(out, f, indent=1)
+        f.write("\n")
+    return out
+
+
+def summarize_trace(stats_csv: str, title: str, command: str) -> str:
+    """Markdown table of a rocprofv3 --kernel-trace --stats kernel_stats.csv."""
+    import csv
+    import re
+    lines = [f"# {title}", "", "Command (run from the repository root on one MI355X):", "",
+             "```", command, "```", "",
+             f"Kernel sources hash (bench.kernel_source_hash): `{kernel_source_hash()}`", "",
+             "| kernel | calls | total (us) | average (us) | % |", "|---|---:|---:|---:|---:|"]
+    with open(stats_csv) as f:
+        for r in csv.DictReader(f):
+            if float(r["Percentage"]) < 0.01:
+                continue
+            name = re.sub(r"wfa::", "", r["Name"])
+            m = re.match(r"void (\w+)<([^(]*)>\(", name)
+            name = f"{m.group(1)}<{m.group(2)}>" if m else name.split("(")[0][:80]
+            lines.append(f"| `{name}` | {int(r['Calls'])} | {float(r['TotalDurationNs']) / 1e3:.1f} | "
+                         f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} |")
+    return "\n".join(lines) + "\n"
 
 
 def cpu_baseline(prob, iters: int):
@@ -386,7 +475,25 @@ def main():
     ap.add_argument("--probe-copy", action="store_true",
                     help="start with one 1 GiB device copy (a dispatch of known traffic that "
                          "calibrates hardware byte counters)")
+    ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="no GPU work: turn two rocprofv3 --pmc counter_collection.csv files "
+                         "(FETCH_SIZE, WRITE_SIZE; both runs with --probe-copy) into the traffic "
+                         "file the roofline line reads")
+    ap.add_argument("--counter-commands", nargs="*", default=[],
+                    help="with --summarize-counters: the commands that made the two files")
+    ap.add_argument("--summarize-trace", nargs=3, metavar=("STATS_CSV", "TITLE", "COMMAND"),
+                    help="no GPU work: print a markdown summary of a rocprofv3 --kernel-trace "
+                         "--stats kernel_stats.csv")
     args = ap.parse_args()
+
+    if args.summarize_trace:
+        print(summarize_trace(*args.summarize_trace), end="")
+        return
+    if args.summarize_counters:
+        out = summarize_counters(*args.summarize_counters, workload=f"{args.workload}",
+                                 commands=args.counter_commands)
+        print(json.dumps(out))
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -401,7 +508,7 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     if args.probe_copy:
-        print(json.dumps({"copy_probe_gbps": wfa.stream_probe(1 << 30, 1)}), file=sys.stderr)
+        print(json.dumps({"copy_probe_gbps": wfa.stream_probe(COPY_PROBE_BYTES, 1)}), file=sys.stderr)
     run = {"convdiff": run_convdiff, "heat32": run_heat32, "poisson_large": run_poisson_large,
            "mixed384": run_mixed384, "serve": run_serve, "explicit": run_explicit}[args.workload]
     print(json.dumps(run(args, torch, inputs, wfa)))

@@ -197,7 +197,12 @@ enum {
                                   paper's psi row scaling, section 1.1.2); the
                                   stop test then uses the scaled residual, and
                                   rel_res_true stays the unscaled one.  WFA_F64
-                                  and WFA_F32 grids, BiCGStab methods only     */
+                                  and WFA_F32 grids, BiCGStab methods only     */,
+  WFA_OPT_GRAPH = 10           /* 1: replay each chunk of iterations between
+                                  host checks from captured HIP graphs of 8
+                                  iterations (results are bitwise those of
+                                  plain launches); 0: plain launches (default);
+                                  -1: graphs for grids up to 2^23 cells        */
 };
 int wfa_grid_set_option(wfa_grid* g, int option, int64_t value);
 

@@ -41,6 +41,21 @@ struct Profiler {
   void clear();
 };
 
+// Executable graphs of fixed launch sequences (a chunk of iterations),
+// keyed by everything the captured launches depend on.
+struct GraphCache {
+  static constexpr int kKey = 16;
+  static constexpr size_t kMaxEntries = 32;
+  struct Entry {
+    uint64_t key[kKey];
+    hipGraphExec_t exec;
+  };
+  hipStream_t cap = nullptr;  // private stream the sequences are captured on
+  std::vector<Entry> entries;
+  uint64_t generation = 1;    // bumped whenever tiling or operator options change
+  void clear();
+};
+
 int set_error(int code, const char* fmt, ...);
 int ir_inner_maxit(int maxit, int used);
 // The inner FP32 solve of iterative refinement stops as diverged once its
@@ -68,9 +83,10 @@ struct wfa_grid {
   wfa::Op<float> op32;
   wfa::Tiling tl;        // tiling of the grid's vector type
   wfa::Tiling tl32;      // tiling of FP32 inner vectors
-  int method, persistent, profile, force_bd, check_every, zchunk, ry, jacobi;
+  int method, persistent, profile, force_bd, check_every, zchunk, ry, jacobi, graph;
   double ir_inner_tol;
   wfa::Profiler prof;
+  wfa::GraphCache graphs;
 };
 
 namespace wfa {

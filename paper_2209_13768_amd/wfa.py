@@ -22,7 +22,7 @@ COEF_CONST, COEF_CELL = 0, 1
 BC_DIRICHLET, BC_ZEROFLUX = 0, 1
 METHOD_BICGSTAB, METHOD_CG, METHOD_BICGSTAB2 = 0, 1, 2
 OPT_METHOD, OPT_PERSISTENT, OPT_PROFILE, OPT_FORCE_BREAKDOWN, OPT_CHECK_EVERY = 1, 2, 3, 4, 5
-OPT_IR_INNER_TOL, OPT_ZCHUNK, OPT_RY, OPT_JACOBI = 6, 7, 8, 9
+OPT_IR_INNER_TOL, OPT_ZCHUNK, OPT_RY, OPT_JACOBI, OPT_GRAPH = 6, 7, 8, 9, 10
 K_APPLY, K_INIT, K_PHASE_A, K_PHASE_B, K_PHASE_C, K_RESIDUAL, K_PROMOTE = 0, 1, 2, 3, 4, 5, 6
 K_CG_A, K_CG_B, K_PERSISTENT, K_PHASE_AC, K_PHASE_B2, K_EXPLICIT, K_COUNT = 7, 8, 9, 10, 11, 12, 13
 KERNEL_NAMES = ("apply", "init", "phase_a", "phase_b", "phase_c", "residual", "promote",
