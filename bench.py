@@ -11,9 +11,10 @@ on the same steps for comparison).  Inputs are synthetic and seeded
 
 Prints one JSON line.  `value` = cells x BiCGStab iterations / seconds over
 the K timed steps (inputs resident in HBM, HIP-event timing on the solve
-stream).  `roofline` is for the kernel with the largest share of GPU time;
-its average duration comes from HIP events around every launch of that
-kernel in the timed region; `traffic` is the HBM bytes per launch measured
+stream, plain launches).  `roofline` is for the kernel with the largest
+share of GPU time; its average duration comes from HIP events around every
+launch of that kernel while the same K steps run again from the same
+initial field; `traffic` is the HBM bytes per launch measured
 with rocprofv3 counters (profiles/) when they were taken from the current
 kernel sources, else null.  `cpu_baseline` times the FP64 CPU oracle on a
 bounded sample of the same workload on this host.
@@ -38,7 +39,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_convdiff256_f64.json")
 
 # The files that define the single-grid solver kernels and their launch
 # shapes: counter figures taken from other sources are stale.
-KERNEL_SOURCES = ("device.hpp", "phases.hpp", "kernels.hip", "internal.hpp")
+KERNEL_SOURCES = ("device.hpp", "phases.hpp", "kernels.hip")
 
 
 def kernel_source_hash() -> str:
@@ -48,6 +49,18 @@ def kernel_source_hash() -> str:
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(name.encode())
             h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def library_source_hash() -> str:
+    """Hash of every HIP source of the library (any kernel or launch change)."""
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2209_13768_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".hpp")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode())
+                h.update(f.read())
     return h.hexdigest()[:16]
 
 
@@ -136,7 +149,8 @@ def summarize_trace(stats_csv: str, title: str, command: str) -> str:
     import re
     lines = [f"# {title}", "", "Command (run from the repository root on one MI355X):", "",
              "```", command, "```", "",
-             f"Kernel sources hash (bench.kernel_source_hash): `{kernel_source_hash()}`", "",
+             f"Kernel sources hash (bench.kernel_source_hash): `{kernel_source_hash()}`; "
+             f"library sources hash (bench.library_source_hash): `{library_source_hash()}`", "",
              "| kernel | calls | total (us) | average (us) | % |", "|---|---:|---:|---:|---:|"]
     with open(stats_csv) as f:
         for r in csv.DictReader(f):
@@ -193,10 +207,8 @@ def run_convdiff(args, torch, inputs, wfa):
     T.copy_(T0)
     torch.cuda.synchronize()
 
-    profile = not args.no_profile
-    g.set_option(wfa.OPT_PROFILE, 1 if profile else 0)
-    for k in range(wfa.K_COUNT):
-        g.kernel_stats(k, reset=True)
+    # the timed steps: plain launches, no per-launch events
+    g.set_option(wfa.OPT_PROFILE, 0)
     infos = []
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -213,9 +225,23 @@ def run_convdiff(args, torch, inputs, wfa):
     iters = sum(i.iterations for i in infos)
     value = prob.cells * iters / (total_ms * 1e-3)
 
+    # the same steps again with HIP events around every launch (on the
+    # solve stream) for the per-kernel durations of the roofline
+    profile = not args.no_profile
     roofline = None
     kernels = {}
     if profile:
+        T.copy_(T0)
+        for _ in range(args.warmup):
+            g.timestep(T, 1, tol=args.tol, maxit=args.maxit, check=False)
+        T.copy_(T0)
+        g.set_option(wfa.OPT_PROFILE, 1)
+        for k in range(wfa.K_COUNT):
+            g.kernel_stats(k, reset=True)
+        for _ in range(args.steps):
+            g.timestep(T, 1, tol=args.tol, maxit=args.maxit, check=False)
+        torch.cuda.synchronize()
+        g.set_option(wfa.OPT_PROFILE, 0)
         for k, name in enumerate(wfa.KERNEL_NAMES):
             n, ms, by = g.kernel_stats(k)
             if n:
@@ -228,7 +254,9 @@ def run_convdiff(args, torch, inputs, wfa):
         roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                     "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                    "traffic": load_traffic(dom)}
+                    "traffic": load_traffic(dom),
+                    "measured": "HIP events around every launch on the solve stream, over "
+                                "the timed steps repeated from the same initial field"}
     w = 4 if prec == wfa.F32 else 8
     streams = STREAMS[args.method]
     alg_bytes_iter = (streams * w + 2 * 4) * prob.cells   # vector streams + 2 kappa reads
@@ -423,27 +451,41 @@ def run_serve(args, torch, inputs, wfa):
 def run_explicit(args, torch, inputs, wfa):
     """Explicit forward-time heat steps (Eq. 2, omega = 1/10, constant
     diffusivity, Dirichlet 0) on 512x512x1024 in FP32: the paper's explicit
-    benchmark kernel; its bound is R = w_m / (8 W) iterations per second."""
+    benchmark kernel.  One step per pass is bounded by 2w bytes per
+    cell-step; the fused form (temporal blocking, up to 4 steps per pass)
+    moves 2w bytes per pass."""
     nx, ny, nz = 512, 512, 1024
     h = inputs.grid_spacing(nx, ny, nz)
-    g = wfa.Grid(nx, ny, nz, h=h, dt=0.1 * h * h, alpha=1.0, precision=wfa.F32)
-    T = g.field(inputs.random_field(6, (nz, ny, nx), dtype="float32"))
-    g.explicit(T, 4)
-    torch.cuda.synchronize()
-    g.set_option(wfa.OPT_PROFILE, 1)
-    g.kernel_stats(wfa.K_EXPLICIT, reset=True)
-    steps = 100
-    t0 = time.perf_counter()
-    g.explicit(T, steps)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    n, ms, by = g.kernel_stats(wfa.K_EXPLICIT)
     cells = nx * ny * nz
-    return {"workload": "explicit_heat_512x512x1024_f32", "steps": steps, "seconds": dt,
-            "steps_per_s": steps / dt, "cell_steps_per_s": cells * steps / dt,
-            "gbps": 8 * cells * steps / dt / 1e9, "frac_8tbs": 8 * cells * steps / dt / 8e12,
-            "kernel_us_avg": ms / n * 1e3, "kernel_gbps": by / (ms / n * 1e-3) / 1e9,
-            "bound_steps_per_s_8tbs": 8e12 / (8 * cells)}
+    steps = 96
+    out = {"workload": "explicit_heat_512x512x1024_f32", "steps": steps,
+           "bound_cell_steps_per_s_one_pass_per_step_8tbs": 8e12 / 8}
+    for label, fuse in (("one_step_per_pass", 1), ("fused", 0)):
+        g = wfa.Grid(nx, ny, nz, h=h, dt=0.1 * h * h, alpha=1.0, precision=wfa.F32)
+        g.set_option(wfa.OPT_EXPLICIT_FUSE, fuse)
+        T = g.field(inputs.random_field(6, (nz, ny, nx), dtype="float32"))
+        g.explicit(T, 8)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.explicit(T, steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        g.set_option(wfa.OPT_PROFILE, 1)
+        for k in range(wfa.K_COUNT):
+            g.kernel_stats(k, reset=True)
+        g.explicit(T, steps)
+        torch.cuda.synchronize()
+        kid = wfa.K_EXPLICIT if fuse == 1 else wfa.K_EXPLICIT_FUSED
+        n, ms, by = g.kernel_stats(kid)
+        per_pass = steps / n
+        out[label] = {"seconds": dt, "cell_steps_per_s": cells * steps / dt,
+                      "steps_per_pass": per_pass,
+                      "kernel_us_avg": ms / n * 1e3,
+                      "kernel_alg_gbps": by / (ms / n * 1e-3) / 1e9,
+                      "equivalent_gbps_one_pass_per_step": 8 * cells * steps / dt / 1e9}
+        del g
+    out["speedup_fused"] = out["fused"]["cell_steps_per_s"] / out["one_step_per_pass"]["cell_steps_per_s"]
+    return out
 
 
 METHODS = {"bicgstab": 0, "cg": 1, "bicgstab2": 2}

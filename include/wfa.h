@@ -167,7 +167,10 @@ int wfa_timestep(wfa_grid* g, void* T, int nsteps, double tol, int maxit,
  * each cell gains the net face flux of the old time level.  Stable only for
  * small steps (Eq. 2: omega = alpha dt / h^2 < 1/6 for pure diffusion); the
  * caller chooses dt.  Uses the grid's workspace as the second time level.
- * WFA_F64 and WFA_F32 grids.  Asynchronous on `stream`. */
+ * With a constant diffusivity (WFA_COEF_CONST) 2 to 4 steps are fused into
+ * one pass over memory (temporal blocking, WFA_OPT_EXPLICIT_FUSE); the
+ * result is bitwise that of one pass per step.  WFA_F64 and WFA_F32 grids.
+ * Asynchronous on `stream`. */
 int wfa_explicit_step(wfa_grid* g, void* T, int nsteps, void* stream);
 
 /* FP64 true relative residual ||b - A x|| / ||b|| (FP64 fields only, i.e.
@@ -202,7 +205,12 @@ enum {
                                   host checks from captured HIP graphs of 8
                                   iterations (results are bitwise those of
                                   plain launches); 0: plain launches (default);
-                                  -1: graphs for grids up to 2^23 cells        */
+                                  -1: graphs for grids up to 2^23 cells        */,
+  WFA_OPT_EXPLICIT_FUSE = 11   /* explicit steps per pass over memory in
+                                  wfa_explicit_step: 1 to 4; 0 = automatic
+                                  (with a constant diffusivity 3 in FP32 and
+                                  2 in FP64, else 1).  More than 1 needs
+                                  WFA_COEF_CONST                               */
 };
 int wfa_grid_set_option(wfa_grid* g, int option, int64_t value);
 
@@ -211,7 +219,7 @@ enum {
   WFA_K_APPLY = 0, WFA_K_INIT = 1, WFA_K_PHASE_A = 2, WFA_K_PHASE_B = 3,
   WFA_K_PHASE_C = 4, WFA_K_RESIDUAL = 5, WFA_K_PROMOTE = 6, WFA_K_CG_A = 7,
   WFA_K_CG_B = 8, WFA_K_PERSISTENT = 9, WFA_K_PHASE_AC = 10, WFA_K_PHASE_B2 = 11,
-  WFA_K_EXPLICIT = 12, WFA_K_COUNT = 13
+  WFA_K_EXPLICIT = 12, WFA_K_EXPLICIT_FUSED = 13, WFA_K_COUNT = 14
 };
 /* With WFA_OPT_PROFILE on: launches and summed event time (ms) of one
  * kernel since the last reset; `bytes` = algorithmic HBM bytes per launch
@@ -222,6 +230,34 @@ int wfa_kernel_stats(wfa_grid* g, int kernel, int64_t* launches, double* ms,
 /* Tile shape the grid uses: x cells, y cells, z planes per workgroup, and
  * the number of workgroups of one phase launch. */
 int wfa_grid_tiling(wfa_grid* g, int* tx, int* ty, int* zc, int* blocks);
+
+/* ---- tile-shape autotuner ------------------------------------------------------
+ * The stencil passes march 64-cell-wide tiles of 4 x (rows per wave) rows
+ * along z, zc planes per workgroup.  wfa_autotune times `iters` iterations
+ * of `method` (WFA_METHOD_*) on this grid for the default rule and for every
+ * (rows per wave in {1, 2, 4}) x (zc in {1, 2, 4, ..., 64}, zc <= nz), keeps
+ * the fastest, applies it to the grid, and records it in a process-wide
+ * table under (nx, ny, nz, precision, coefficient mode).  Grids created
+ * afterwards with that key start with the recorded tiling, so a grid's
+ * tiling -- and with it the order of its reductions -- depends on its key
+ * only.  x and b are caller-owned device fields of the grid's vector type
+ * (FP64 for WFA_F32_IR64) and are overwritten.  Synchronises `stream`.
+ * The solver options of the grid are left as they were. */
+typedef struct {
+  int32_t ry, zc;              /* chosen rows per wave and z planes per workgroup */
+  int32_t candidates, pad;     /* distinct tile shapes timed                      */
+  double us_per_iter;          /* chosen shape, microseconds per iteration        */
+  double us_per_iter_default;  /* the default rule's shape                        */
+} wfa_tune_result;
+int wfa_autotune(wfa_grid* g, int method, void* x, void* b, int iters, wfa_tune_result* out,
+                 void* stream);
+/* The table as text, one entry per line:
+ *   nx ny nz precision mode rows_per_wave z_planes us_per_iter
+ * wfa_tune_load merges a file into the table (its entries win) and rejects
+ * a malformed file as a whole (WFA_ERR_INVALID).  No GPU work. */
+int wfa_tune_save(const char* path);
+int wfa_tune_load(const char* path);
+int wfa_tune_clear(void);
 
 /* Achievable HBM bandwidth probe: copies `bytes` (multiple of 16) from src
  * to dst `reps` times on `stream` and returns GB/s (read + write bytes). */

@@ -10,7 +10,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libwfa.so")
-SOURCES = ["kernels.hip", "persistent.hip", "batched.hip", "api.hip", "server.hip"]
+SOURCES = ["kernels.hip", "explicit_tb.hip", "persistent.hip", "batched.hip", "api.hip", "tune.hip",
+           "server.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

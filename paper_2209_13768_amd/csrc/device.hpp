@@ -21,6 +21,8 @@ namespace wfa {
 constexpr int kThreads = 256;      // 4 wave64 per workgroup
 constexpr int kWaves = kThreads / 64;
 constexpr int kTX = 64;            // tile width in x: one wave spans one row
+constexpr int kMaxReduce = 4;      // most global sums one pass reduces (per-tile
+                                   // partial slots the workspace holds per tile)
 
 // ---- device status of a solve ---------------------------------------------
 enum DevStatus : int32_t {
@@ -88,41 +90,99 @@ __device__ __forceinline__ float pos_rcp(float a) {
   return __builtin_fmaf(y, e, y);
 }
 
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
 // Faces: 0 x-, 1 x+, 2 y-, 3 y+, 4 z-, 5 z+.  `inside` bit f: the neighbour
 // across face f exists.
 // Returns (A x)_P, or (A x)_P / A[P,P] when op.jac; the diagonal in `dg`.
+// The operation sequence is pinned (explicit fused multiply-adds, no other
+// contraction), so every kernel that applies the operator -- one pass per
+// phase, persistent, batched, several explicit steps per pass -- rounds
+// identically.
 template <typename T, bool CELL>
 __device__ __forceinline__ T cell_apply(const Op<T>& op, T c, const T nb[6], T kP,
                                         const T kN[6], uint32_t inside, T& dg) {
+#pragma clang fp contract(off)
   T diag = T(1), acc = T(0);
 #pragma unroll
   for (int f = 0; f < 6; ++f) {
     if (inside & (1u << f)) {
-      const T D = CELL ? op.cD * (T(2) * kP * kN[f] * pos_rcp(kP + kN[f])) : op.cD;
-      diag += D + op.out[f];
-      acc += (D + op.in[f]) * nb[f];
+      T d_out, d_in;  // D + max(F,0), D + max(-F,0)
+      if (CELL) {
+        const T kf = T(2) * kP * kN[f] * pos_rcp(kP + kN[f]);  // harmonic mean
+        d_out = fma_t(op.cD, kf, op.out[f]);
+        d_in = fma_t(op.cD, kf, op.in[f]);
+      } else {
+        d_out = op.cD + op.out[f];
+        d_in = op.cD + op.in[f];
+      }
+      diag += d_out;
+      acc = fma_t(d_in, nb[f], acc);
     } else if (op.dir & (1u << f)) {
-      const T D = CELL ? op.cD * kP : op.cD;
-      diag += D + op.out[f];
+      diag += CELL ? fma_t(op.cD, kP, op.out[f]) : op.cD + op.out[f];
     }
   }
   dg = diag;
-  const T y = diag * c - acc;
+  const T y = fma_t(diag, c, -acc);
   return op.jac ? y * pos_rcp(diag) : y;
 }
 
 // Dirichlet contribution of cell P to the right-hand side.
 template <typename T, bool CELL>
 __device__ __forceinline__ T cell_bterm(const Op<T>& op, T kP, uint32_t inside) {
+#pragma clang fp contract(off)
   T s = T(0);
 #pragma unroll
   for (int f = 0; f < 6; ++f) {
     if (!(inside & (1u << f)) && (op.dir & (1u << f))) {
-      const T D = CELL ? op.cD * kP : op.cD;
-      s += (D + op.in[f]) * op.bval[f];
+      const T d_in = CELL ? fma_t(op.cD, kP, op.in[f]) : op.cD + op.in[f];
+      s = fma_t(d_in, op.bval[f], s);
     }
   }
   return s;
+}
+
+// Coefficients of a constant-diffusivity operator at a cell whose six
+// neighbours all exist, formed in the order cell_apply forms them, so that
+// cell_apply_interior returns cell_apply's value bit for bit.
+template <typename T>
+struct InteriorCoef {
+  T coef[6];  // D + in[f]
+  T diag;     // 1 + sum_f (D + out[f]), summed in face order
+};
+
+template <typename T>
+__device__ __forceinline__ InteriorCoef<T> interior_coef(const Op<T>& op) {
+#pragma clang fp contract(off)
+  InteriorCoef<T> k;
+  T diag = T(1);
+#pragma unroll
+  for (int f = 0; f < 6; ++f) {
+    diag += op.cD + op.out[f];
+    k.coef[f] = op.cD + op.in[f];
+  }
+  k.diag = diag;
+  return k;
+}
+
+// (A x)_P of a constant-diffusivity operator at a cell with all six
+// neighbours inside and no Jacobi scaling: cell_apply's operation sequence
+// with the face tests resolved.
+template <typename T>
+__device__ __forceinline__ T cell_apply_interior(const InteriorCoef<T>& k, T c, const T nb[6]) {
+#pragma clang fp contract(off)
+  T acc = T(0);
+#pragma unroll
+  for (int f = 0; f < 6; ++f) acc = fma_t(k.coef[f], nb[f], acc);
+  return fma_t(k.diag, c, -acc);
+}
+
+// One explicit forward-time step of cell P from its old value c and (A x)_P.
+template <typename T>
+__device__ __forceinline__ T explicit_update(T c, T Au, T bterm) {
+#pragma clang fp contract(off)
+  return c - (Au - c) + bterm;
 }
 
 __device__ __forceinline__ uint32_t inside_mask(const Geo& g, int i, int j, int k) {

@@ -83,7 +83,7 @@ struct wfa_grid {
   wfa::Op<float> op32;
   wfa::Tiling tl;        // tiling of the grid's vector type
   wfa::Tiling tl32;      // tiling of FP32 inner vectors
-  int method, persistent, profile, force_bd, check_every, zchunk, ry, jacobi, graph;
+  int method, persistent, profile, force_bd, check_every, zchunk, ry, jacobi, graph, fuse;
   double ir_inner_tol;
   wfa::Profiler prof;
   wfa::GraphCache graphs;
@@ -91,6 +91,9 @@ struct wfa_grid {
 
 namespace wfa {
 void grid_setup(wfa_grid* g, int nx, int ny, int nz, const wfa_coeffs* c, char* ws);
+void apply_tiling(wfa_grid* g, int ry, int zc);
+// Tile shape the tuning table holds for this grid key, if any.
+bool tuned_tiling(int nx, int ny, int nz, int precision, int mode, int* ry, int* zc);
 int solve_any(wfa_grid* g, const void* b, void* x, bool form_b, double tol, int maxit,
               wfa_solve_info* info, hipStream_t s);
 }  // namespace wfa

@@ -45,6 +45,10 @@ void launch_rhs(const Launch<T>& L, const T* x, T* b);
 // One explicit forward-time step: y = x - (A x - x) + boundary terms
 template <typename T>
 void launch_explicit(const Launch<T>& L, const T* x, T* y);
+// `steps` (2 to 4) explicit steps in one pass, constant diffusivity only;
+// zc_override > 0 sets the output planes per workgroup
+template <typename T>
+void launch_explicit_fused(const Launch<T>& L, const T* x, T* y, int steps, int zc_override);
 // p' = r + beta (p - omega v) (p' = r on the first iteration); v' = A p';
 // sigma = (rh, v')
 template <typename T>

@@ -31,6 +31,7 @@ template <typename T, bool CELL, int RY, class Ph, class Fin>
 __global__ void __launch_bounds__(kThreads)
 k_march(Geo g, Op<T> op, const float* __restrict__ kappa, Ph ph, double* partials,
         Scalars* sc, Fin fin, int gated, int publish) {
+  static_assert(Ph::NV <= kMaxReduce, "the workspace holds kMaxReduce partials per tile");
   using TS = TileShape<RY>;
   __shared__ T su[2 * TS::LH * TS::LW];
   __shared__ float sk[CELL ? 2 * TS::LH * TS::LW : 1];
@@ -288,7 +289,8 @@ Tiling make_tiling(int nx, int ny, int nz, int elem_bytes, int zc_override, int 
   if (zc > nz) zc = nz;
   if (zc < 1) zc = 1;
   // small grids: thinner tiles until there are >= 128 of them (measured on
-  // 32^3 and 64^3, where a pass is a few microseconds and parallelism wins)
+  // 32^3 and 64^3, where a pass is a few microseconds and parallelism wins;
+  // more tiles per grid cost the batched server more than they gain)
   if (zc_override <= 0)
     while (zc > 2 && txy * ((nz + zc - 1) / zc) < 128) zc /= 2;
   g.zc = zc;

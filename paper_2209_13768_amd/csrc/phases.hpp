@@ -219,7 +219,7 @@ struct PhExplicit {
   __device__ ERaw efetch(size_t) const { return {}; }
   __device__ void epilogue(size_t i, T u, T Au, T kP, uint32_t ins, const ERaw&, T dg,
                            double (&)[NV]) const {
-    st_once(y + i, u - (Au - u) + cell_bterm<T, CELL>(op, kP, ins));
+    st_once(y + i, explicit_update(u, Au, cell_bterm<T, CELL>(op, kP, ins)));
   }
 };
 

@@ -451,11 +451,18 @@ void worker_main(wfa_server* sv) {
     for (Request* r : admitted) {
       char* ws = sv->arena + sv->heap_base + r->off;
       grid_setup(&r->g, r->nx, r->ny, r->nz, &r->c, ws);
+      // a tuned plane depth for this grid key, where the tuned row count is
+      // the one every resident solve shares (one launch covers them all)
+      int t_ry = 0, t_zc = 0;
+      const int shared_ry = r->g.prec == WFA_F32_IR64 ? r->g.tl32.ry : r->g.tl.ry;
+      if (tuned_tiling(r->nx, r->ny, r->nz, r->c.precision, r->c.mode, &t_ry, &t_zc) &&
+          t_ry == shared_ry)
+        apply_tiling(&r->g, t_ry, t_zc);
       // the slot's scalar blocks live in the server's contiguous region
       r->g.sc = sv->slot_sc + r->slot * kScalarsPerSlot;
       r->g.sc_in = r->g.sc + 1;
       r->g.sc_aux = r->g.sc + 2;
-      // every grid gets the default tiling rule, so all share one row count
+      // every grid keeps the default rule's row count, so all share it
       sv->ry = r->g.prec == WFA_F32_IR64 ? r->g.tl32.ry : r->g.tl.ry;
       if ((rc = start_request(sv, r))) break;
     }

@@ -23,10 +23,12 @@ BC_DIRICHLET, BC_ZEROFLUX = 0, 1
 METHOD_BICGSTAB, METHOD_CG, METHOD_BICGSTAB2 = 0, 1, 2
 OPT_METHOD, OPT_PERSISTENT, OPT_PROFILE, OPT_FORCE_BREAKDOWN, OPT_CHECK_EVERY = 1, 2, 3, 4, 5
 OPT_IR_INNER_TOL, OPT_ZCHUNK, OPT_RY, OPT_JACOBI, OPT_GRAPH = 6, 7, 8, 9, 10
+OPT_EXPLICIT_FUSE = 11
 K_APPLY, K_INIT, K_PHASE_A, K_PHASE_B, K_PHASE_C, K_RESIDUAL, K_PROMOTE = 0, 1, 2, 3, 4, 5, 6
-K_CG_A, K_CG_B, K_PERSISTENT, K_PHASE_AC, K_PHASE_B2, K_EXPLICIT, K_COUNT = 7, 8, 9, 10, 11, 12, 13
+K_CG_A, K_CG_B, K_PERSISTENT, K_PHASE_AC, K_PHASE_B2, K_EXPLICIT = 7, 8, 9, 10, 11, 12
+K_EXPLICIT_FUSED, K_COUNT = 13, 14
 KERNEL_NAMES = ("apply", "init", "phase_a", "phase_b", "phase_c", "residual", "promote",
-                "cg_a", "cg_b", "persistent", "phase_ac", "phase_b2", "explicit")
+                "cg_a", "cg_b", "persistent", "phase_ac", "phase_b2", "explicit", "explicit_fused")
 
 PRECISIONS = {"f64": F64, "f32": F32, "f32_ir64": F32_IR64}
 
@@ -36,7 +38,8 @@ EXPORTS = (
     "wfa_rhs", "wfa_explicit_step", "wfa_bicgstab_solve", "wfa_bicgstab2_solve", "wfa_cg_solve", "wfa_timestep", "wfa_true_residual",
     "wfa_grid_set_option", "wfa_kernel_stats", "wfa_grid_tiling", "wfa_stream_probe",
     "wfa_server_create", "wfa_submit", "wfa_poll", "wfa_server_drain", "wfa_server_destroy",
-    "wfa_last_error", "wfa_version",
+    "wfa_last_error", "wfa_version", "wfa_autotune", "wfa_tune_save", "wfa_tune_load",
+    "wfa_tune_clear",
 )
 
 
@@ -63,6 +66,14 @@ class _Info(ctypes.Structure):
         ("refinements", ctypes.c_int32), ("restarts", ctypes.c_int32),
         ("rel_res_recursive", ctypes.c_double), ("rel_res_true", ctypes.c_double),
         ("seconds", ctypes.c_double),
+    ]
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [
+        ("ry", ctypes.c_int32), ("zc", ctypes.c_int32),
+        ("candidates", ctypes.c_int32), ("pad", ctypes.c_int32),
+        ("us_per_iter", ctypes.c_double), ("us_per_iter_default", ctypes.c_double),
     ]
 
 
@@ -118,6 +129,10 @@ def lib() -> ctypes.CDLL:
     L.wfa_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(_Info)]
     L.wfa_server_drain.argtypes = [vp]
     L.wfa_server_destroy.argtypes = [vp]
+    L.wfa_autotune.argtypes = [vp, i32, vp, vp, i32, ctypes.POINTER(TuneResult), vp]
+    L.wfa_tune_save.argtypes = [ctypes.c_char_p]
+    L.wfa_tune_load.argtypes = [ctypes.c_char_p]
+    L.wfa_tune_clear.argtypes = []
     L.wfa_last_error.restype = ctypes.c_char_p
     L.wfa_version.restype = ctypes.c_char_p
     _lib = L
@@ -279,6 +294,17 @@ class Grid:
                                        ctypes.byref(rel), _stream_ptr(stream)))
         return rel.value
 
+    def autotune(self, method="bicgstab2", iters=20, stream=None) -> dict:
+        """Time the candidate tile shapes on this grid, keep the fastest and
+        record it for grids of the same key (wfa_autotune)."""
+        x, b = self.field(), self.field()
+        r = TuneResult()
+        m = {"bicgstab": METHOD_BICGSTAB, "cg": METHOD_CG, "bicgstab2": METHOD_BICGSTAB2}[method]
+        _check(lib().wfa_autotune(self._h, m, self._v(x, "x"), self._v(b, "b"), int(iters),
+                                  ctypes.byref(r), _stream_ptr(stream)))
+        return {"ry": r.ry, "zc": r.zc, "candidates": r.candidates, "us_per_iter": r.us_per_iter,
+                "us_per_iter_default": r.us_per_iter_default}
+
     def set_option(self, option: int, value: int):
         _check(lib().wfa_grid_set_option(self._h, int(option), int(value)))
 
@@ -294,6 +320,18 @@ class Grid:
         v = [ctypes.c_int() for _ in range(4)]
         _check(lib().wfa_grid_tiling(self._h, *[ctypes.byref(q) for q in v]))
         return tuple(q.value for q in v)
+
+
+def tune_save(path: str):
+    _check(lib().wfa_tune_save(os.fsencode(path)))
+
+
+def tune_load(path: str):
+    _check(lib().wfa_tune_load(os.fsencode(path)))
+
+
+def tune_clear():
+    _check(lib().wfa_tune_clear())
 
 
 def stream_probe(nbytes: int = 1 << 30, reps: int = 10, stream=None) -> float:

@@ -2,6 +2,8 @@
 and closed-form fields.  Nothing here restates the oracle's assembly."""
 from __future__ import annotations
 
+import os
+
 import numpy as np
 import scipy.sparse as sp
 
@@ -60,3 +62,28 @@ def rel_l2(a, b) -> float:
     b = np.asarray(b, dtype=np.float64)
     nb = np.linalg.norm(b)
     return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def worked_examples():
+    """Cases of tests/golden/worked_examples.txt: (scheme, Problem, T1) with
+    every face a boundary cell at gamma and omega = alpha dt / h^2 = given."""
+    from fractions import Fraction
+    cases = []
+    with open(os.path.join(GOLDEN, "worked_examples.txt")) as f:
+        for line in f:
+            if not line.strip() or line.startswith("#"):
+                continue
+            head, t0, t1 = (part.split() for part in line.split("|"))
+            scheme, nx, ny, nz, omega, gamma = head
+            nx, ny, nz = int(nx), int(ny), int(nz)
+            h = grid_spacing(nx, ny, nz)
+            shape = (nz, ny, nx)
+            T0 = np.array([float(Fraction(v)) for v in t0]).reshape(shape)
+            T1 = np.array([float(Fraction(v)) for v in t1]).reshape(shape)
+            prob = Problem(nx, ny, nz, h=h, dt=float(Fraction(omega)) * h * h, alpha=1.0,
+                                  bc_value=(float(Fraction(gamma)),) * 6, T0=T0)
+            cases.append((scheme, prob, T1))
+    return cases

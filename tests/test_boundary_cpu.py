@@ -78,3 +78,58 @@ def test_grid_descriptor_host_only(libwfa):
     assert libwfa.wfa_grid_tiling(out, *[ctypes.byref(q) for q in v]) == wfa.OK
     assert v[2].value == 32
     assert libwfa.wfa_grid_destroy(out) == wfa.OK
+
+
+def _tiling(libwfa, g):
+    v = [ctypes.c_int() for _ in range(4)]
+    assert libwfa.wfa_grid_tiling(g, *[ctypes.byref(q) for q in v]) == 0
+    return tuple(q.value for q in v)
+
+
+def test_tuning_table_file_and_grid_creation(libwfa, tmp_path):
+    """The tuning table is host-only: a loaded entry sets the tiling of every
+    grid created with its key (shape, precision, coefficient mode) and no
+    other; save writes what load reads; a malformed file is rejected whole."""
+    from paper_2209_13768_amd import wfa
+    wfa.tune_clear()
+    c = wfa.make_coeffs(h=1 / 97, dt=1e-2)
+    nbytes = wfa.workspace_bytes(96, 80, 48, wfa.F64)
+
+    def grid(nx=96, ny=80, nz=48):
+        out = ctypes.c_void_p()
+        assert libwfa.wfa_grid_create(nx, ny, nz, ctypes.byref(c), ctypes.c_void_p(1 << 20),
+                                      nbytes, ctypes.byref(out)) == wfa.OK
+        return out
+
+    g = grid()
+    default = _tiling(libwfa, g)
+    libwfa.wfa_grid_destroy(g)
+    table = tmp_path / "tune.txt"
+    table.write_text("# comment\n96 80 48 0 0 4 8 123.5\n96 80 48 1 0 1 2 50.0\n")
+    wfa.tune_load(str(table))
+    g = grid()
+    assert _tiling(libwfa, g) == (64, 16, 8, 2 * 5 * 6)   # 4 rows per wave, 8 planes
+    libwfa.wfa_grid_destroy(g)
+    g = grid(96, 80, 47)                                   # another key: default rule
+    assert _tiling(libwfa, g)[1] == default[1]
+    libwfa.wfa_grid_destroy(g)
+    saved = tmp_path / "saved.txt"
+    wfa.tune_save(str(saved))
+    rows = [ln.split() for ln in saved.read_text().splitlines() if not ln.startswith("#")]
+    assert sorted(r[:7] for r in rows) == sorted([["96", "80", "48", "0", "0", "4", "8"],
+                                                  ["96", "80", "48", "1", "0", "1", "2"]])
+    wfa.tune_clear()
+    g = grid()
+    assert _tiling(libwfa, g) == default
+    libwfa.wfa_grid_destroy(g)
+    for bad in ("96 80 48 0 0 3 8 1.0\n", "96 80 48 0 0 2 49 1.0\n", "96 80 48 0\n",
+                "96 80 48 9 0 2 8 1.0\n"):
+        table.write_text("96 80 40 0 0 2 4 1.0\n" + bad)
+        with pytest.raises(wfa.WfaError):
+            wfa.tune_load(str(table))
+    g = grid(96, 80, 40)                                   # nothing of a bad file is merged
+    assert _tiling(libwfa, g)[2] != 4 or default[2] == 4
+    libwfa.wfa_grid_destroy(g)
+    with pytest.raises(wfa.WfaError):
+        wfa.tune_load(str(tmp_path / "missing.txt"))
+    wfa.tune_clear()

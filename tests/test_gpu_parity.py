@@ -436,3 +436,110 @@ def test_explicit_step_is_eq2_on_gpu(wfa):
     T = g.field(T0)
     g.explicit(T, 3)
     assert np.max(np.abs(to_np(T) - ref)) <= 1e-14
+
+
+FUSED_SHAPES = [(70, 33, 21), (130, 70, 45), (61, 29, 9), (1, 1, 1), (5, 3, 40), (200, 9, 3)]
+
+
+@pytest.mark.parametrize("shape", FUSED_SHAPES, ids=lambda s: "x".join(map(str, s)))
+@pytest.mark.parametrize("name", ["const_dirichlet", "const_upwind_zeroflux", "const_upwind_mixed"])
+def test_fused_explicit_steps_are_bitwise_one_step_passes(wfa, oracle_mod, shape, name):
+    """Temporal blocking (2 to 4 explicit steps per pass over memory) applies
+    each step's arithmetic to the same values: bitwise equal to one pass per
+    step, over shapes with several tiles in x, y and z and ragged edges."""
+    variants = dict(VARIANTS, const_upwind_mixed=dict(cell=False, u=(-2.0, 1.0, 3.0),
+                                                      bc_kind=inputs.MIXED_BC_KIND))
+    base = inputs.random_problem(116, *shape, **variants[name])
+    prob = base.with_(dt=0.1 * base.h ** 2)
+    o = oracle_mod.Oracle(prob)
+    for precision in (wfa.F64, wfa.F32):
+        ref = {}
+        g = _grid(wfa, prob, precision)
+        g.set_option(wfa.OPT_EXPLICIT_FUSE, 1)
+        for nsteps in (1, 2, 3, 4, 7, 9):
+            T = g.field(prob.T0)
+            ref[nsteps] = to_np(g.explicit(T, nsteps))
+        for fuse in (2, 3, 4):
+            g.set_option(wfa.OPT_EXPLICIT_FUSE, fuse)
+            for nsteps in (1, 2, 3, 4, 7, 9):
+                T = g.field(prob.T0)
+                got = to_np(g.explicit(T, nsteps))
+                assert np.array_equal(got, ref[nsteps]), (precision, fuse, nsteps)
+        if precision == wfa.F64:
+            assert rel_l2(ref[9], o.explicit(prob.T0, 9)) <= FP64_TOL
+
+
+def test_fused_explicit_needs_constant_diffusivity(wfa):
+    prob = inputs.random_problem(117, 20, 10, 6, cell=True)
+    g = _grid(wfa, prob, wfa.F64)
+    with pytest.raises(wfa.WfaError) as e:
+        g.set_option(wfa.OPT_EXPLICIT_FUSE, 4)
+    assert e.value.code == wfa.ERR_INVALID
+    g.set_option(wfa.OPT_EXPLICIT_FUSE, 1)
+
+
+def test_worked_examples_of_eq2_and_eq3_gpu(wfa):
+    """The GPU path reproduces the hand-derived exact values of Eq. 2 and
+    Eq. 3 at omega = 1/10 (tests/golden), explicit steps fused or not."""
+    from tests.oracle_helpers import worked_examples
+    for scheme, prob, T1 in worked_examples():
+        g = _grid(wfa, prob, wfa.F64)
+        T = g.field(prob.T0)
+        if scheme == "explicit":
+            g.explicit(T, 1)
+        else:
+            info = g.timestep(T, 1, tol=1e-15, maxit=100)[0]
+            assert info.status == wfa.OK
+        assert np.max(np.abs(to_np(T) - T1)) <= 2e-15 * max(1.0, np.max(np.abs(T1)))
+
+
+TILINGS = [(ry, zc) for ry in (1, 2, 4) for zc in (1, 2, 4, 8, 16, 32, 64)]
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_every_tiling_the_tuner_may_pick(wfa, oracle_mod, precision):
+    """Every (rows per wave, z planes) candidate of the autotuner gives the
+    oracle's operator and the oracle's first BiCGStab iterates (both
+    organisations), on a grid with ragged tiles in every direction."""
+    prob = inputs.random_problem(118, 70, 45, 38, cell=True, u=(1.0, -0.5, 2.0),
+                                 bc_kind=inputs.MIXED_BC_KIND)
+    o = oracle_mod.Oracle(prob)
+    b = o.rhs(prob.T0)
+    ya = o.apply(prob.T0)
+    x1, _ = o.bicgstab(b, prob.T0, 1e-300, 3)
+    x2, _ = o.bicgstab2(b, prob.T0, 1e-300, 3)
+    tol = FP64_TOL if precision == "f64" else FP32_TOL
+    for ry, zc in TILINGS:
+        if zc > prob.nz:
+            continue
+        g = _grid(wfa, prob, wfa.PRECISIONS[precision])
+        g.set_option(wfa.OPT_RY, ry)
+        g.set_option(wfa.OPT_ZCHUNK, zc)
+        assert rel_l2(to_np(g.apply(g.field(prob.T0))), ya) <= tol, (ry, zc)
+        for method, xo in (("bicgstab", x1), ("bicgstab2", x2)):
+            x, info = g.solve(g.field(b), g.field(prob.T0), tol=1e-300, maxit=3, method=method,
+                              check=False)
+            assert info.status == wfa.ERR_NOCONV, (ry, zc, method, info)
+            assert rel_l2(to_np(x), xo) <= (tol if precision == "f64" else 1e-4), (ry, zc, method)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_finest_tiling_partials_fit_the_workspace(wfa, oracle_mod, precision):
+    """Regression: one-row-per-wave, one-plane tiles on a grid with more
+    than 4096 of them (200x100x60: 6000 tiles).  The second pass of the
+    two-reduction BiCGStab writes four partial sums per tile; the
+    workspace once held only three per tile plus 4096 spare, so these
+    partials ran into the Krylov vectors."""
+    prob = inputs.random_problem(119, 200, 100, 60, cell=True, u=(1.0, 0.5, -0.25),
+                                 bc_kind=inputs.MIXED_BC_KIND)
+    o = oracle_mod.Oracle(prob)
+    b = o.rhs(prob.T0)
+    xo, _ = o.bicgstab2(b, prob.T0, 1e-300, 4)
+    g = _grid(wfa, prob, wfa.PRECISIONS[precision])
+    g.set_option(wfa.OPT_RY, 1)
+    g.set_option(wfa.OPT_ZCHUNK, 1)
+    assert g.tiling()[3] == 4 * 25 * 60
+    x, info = g.solve(g.field(b), g.field(prob.T0), tol=1e-300, maxit=4, method="bicgstab2",
+                      check=False)
+    assert info.status == wfa.ERR_NOCONV and info.iterations == 4
+    assert rel_l2(to_np(x), xo) <= (FP64_TOL if precision == "f64" else 1e-4)

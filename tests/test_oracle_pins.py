@@ -11,7 +11,9 @@ Operator (section 1.1.2, Eq. 3, generalised as documented in the oracle):
   P6  Kronecker-sum assembly of the constant-coefficient operator;
   L   exact steady states of layered media (series conductances), which pin
       the harmonic-mean face diffusivity and the Dirichlet ghost treatment;
-  C   convection adds the same matrix whatever the diffusivity field.
+  C   convection adds the same matrix whatever the diffusivity field;
+  W   hand-derived exact values of Eq. 2 and Eq. 3 at omega = 1/10 on 1- to
+      3-cell grids (tests/golden/worked_examples.txt).
 Solver:
   P5  dense LU (numpy.linalg.solve) on small grids;
   P7  scipy's BiCGStab on the CSR form;
@@ -525,3 +527,21 @@ def test_explicit_conserves_with_zero_flux(oracle_mod):
     o = oracle_mod.Oracle(p)
     T3 = o.explicit(p.T0, 3)
     assert abs(T3.sum() - p.T0.sum()) <= 1e-12 * p.T0.sum()
+
+
+# --------------------------------------------------------------------------- worked examples
+def test_worked_examples_of_eq2_and_eq3(oracle_mod):
+    """The oracle reproduces, to rounding, hand-derived exact rationals of
+    Eq. 2 (one explicit step) and Eq. 3 (one implicit step) at omega = 1/10
+    with every face a boundary cell at gamma (tests/golden)."""
+    from tests.oracle_helpers import worked_examples
+    cases = worked_examples()
+    assert len(cases) >= 5
+    for scheme, prob, T1 in cases:
+        o = oracle_mod.Oracle(prob)
+        if scheme == "explicit":
+            got = o.explicit(prob.T0, 1)
+        else:
+            got, infos = o.timestep(prob.T0, 1, 1e-15, 100)
+            assert infos[0].status == 0
+        assert np.max(np.abs(got - T1)) <= 2e-15 * max(1.0, np.max(np.abs(T1))), (scheme, prob.shape)
