@@ -5,8 +5,10 @@ solve of the whole grid): 256^3 convection-diffusion, FP64, log-normal
 per-cell diffusivity (mu 0, sigma 1), velocity (1, 0.5, 0.25) with
 first-order upwind, dt 1e-2, x- Dirichlet 1 / x+ Dirichlet 0 / y, z
 zero-flux, BiCGStab to a relative residual of 1e-8, solved with the
-two-reduction organisation of BiCGStab (the textbook three-pass one is timed
-on the same steps for comparison).  Inputs are synthetic and seeded
+two-reduction organisation of BiCGStab and a shadow residual hashed from
+the cell index (--shadow r0 stores r^ = r0 instead); the r^ = r0 form and
+the textbook three-pass BiCGStab are timed on the same steps for
+comparison.  Inputs are synthetic and seeded
 (paper_2209_13768_amd.inputs.convdiff).
 
 Prints one JSON line.  `value` = cells x BiCGStab iterations / seconds over
@@ -197,6 +199,7 @@ def run_convdiff(args, torch, inputs, wfa):
     prec = wfa.PRECISIONS[args.precision]
     g = wfa.Grid.from_problem(prob, precision=prec)
     g.set_option(wfa.OPT_METHOD, METHODS[args.method])
+    g.set_option(wfa.OPT_SHADOW, 1 if args.shadow == "hashed" else 0)
     T0 = g.field(prob.T0)
     T = g.field(prob.T0)
     stream = torch.cuda.current_stream()
@@ -258,7 +261,7 @@ def run_convdiff(args, torch, inputs, wfa):
                     "measured": "HIP events around every launch on the solve stream, over "
                                 "the timed steps repeated from the same initial field"}
     w = 4 if prec == wfa.F32 else 8
-    streams = STREAMS[args.method]
+    streams = streams_of(args)
     alg_bytes_iter = (streams * w + 2 * 4) * prob.cells   # vector streams + 2 kappa reads
     whole = alg_bytes_iter * iters / (total_ms * 1e-3) / 1e9
     line = {
@@ -276,6 +279,7 @@ def run_convdiff(args, torch, inputs, wfa):
         "data": "synthetic",
         "config": {"workload": f"convdiff_{args.n}^3_{args.precision}", "grid": [args.n] * 3,
                    "precision": args.precision, "tol": args.tol, "method": args.method,
+                   "shadow": args.shadow if args.method == "bicgstab2" else "r0",
                    "physics": "lognormal kappa, u=(1,0.5,0.25) upwind, dt=1e-2, mixed BC"},
         "iterations_per_step": iters / args.steps,
         "solve_latency_ms": {"p50": percentile(step_ms, 50), "p99": percentile(step_ms, 99)},
@@ -287,28 +291,33 @@ def run_convdiff(args, torch, inputs, wfa):
         "rel_res_true_max": max(i.rel_res_true for i in infos),
         "kernel_source_hash": kernel_source_hash(),
     }
-    if args.compare and args.method != "bicgstab":
-        # the textbook three-pass BiCGStab on the same steps, for comparison
-        g.set_option(wfa.OPT_METHOD, METHODS["bicgstab"])
-        T.copy_(T0)
-        for k in range(wfa.K_COUNT):
-            g.kernel_stats(k, reset=True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        tinfos = []
-        for _ in range(args.steps):
-            tinfos += g.timestep(T, 1, tol=args.tol, maxit=args.maxit, check=False)
-        torch.cuda.synchronize()
-        tdt = time.perf_counter() - t0
-        tit = sum(i.iterations for i in tinfos)
-        tk = {}
-        for k, name in enumerate(wfa.KERNEL_NAMES):
-            n, ms, by = g.kernel_stats(k)
-            if n:
-                tk[name] = {"us_avg": round(ms / n * 1e3, 2), "gbps": round(by / (ms / n * 1e-3) / 1e9, 1)}
-        line["textbook_bicgstab"] = {"value": prob.cells * tit / tdt, "ms_per_step": tdt / args.steps * 1e3,
-                                     "iterations_per_step": tit / args.steps, "kernels": tk,
-                                     "alg_bytes_per_cell_iter": STREAMS["bicgstab"] * w + 8}
+    if args.compare:
+        # the other organisations on the same steps, for comparison (plain
+        # launches, wall clock around the synchronised steps)
+        others = [("bicgstab2", "r0"), ("bicgstab", "r0")]
+        line["compare"] = {}
+        for method, shadow in others:
+            if (method, shadow) == (args.method, args.shadow if args.method == "bicgstab2" else "r0"):
+                continue
+            g.set_option(wfa.OPT_METHOD, METHODS[method])
+            g.set_option(wfa.OPT_SHADOW, 1 if shadow == "hashed" else 0)
+            T.copy_(T0)
+            for _ in range(args.warmup):
+                g.timestep(T, 1, tol=args.tol, maxit=args.maxit, check=False)
+            T.copy_(T0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            tinfos = []
+            for _ in range(args.steps):
+                tinfos += g.timestep(T, 1, tol=args.tol, maxit=args.maxit, check=False)
+            torch.cuda.synchronize()
+            tdt = time.perf_counter() - t0
+            tit = sum(i.iterations for i in tinfos)
+            streams = STREAMS[method] - (2 if (method, shadow) == ("bicgstab2", "hashed") else 0)
+            line["compare"][f"{method}_{shadow}"] = {
+                "value": prob.cells * tit / tdt, "ms_per_step": tdt / args.steps * 1e3,
+                "iterations_per_step": tit / args.steps,
+                "alg_bytes_per_cell_iter": streams * w + 8}
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(prob, args.cpu_iters)
     return line
@@ -350,13 +359,13 @@ def run_poisson_large(args, torch, inputs, wfa):
     prob = inputs.poisson_large()
     g = wfa.Grid.from_problem(prob, precision=wfa.F32)
     g.set_option(wfa.OPT_METHOD, METHODS[args.method])
+    g.set_option(wfa.OPT_SHADOW, 1 if args.shadow == "hashed" else 0)
     T = g.field(prob.T0)
     b = g.rhs(T)
     x = g.field()
     g.solve(b, x, tol=1e-300, maxit=20, method=args.method)
-    g.set_option(wfa.OPT_PROFILE, 1)
-    for k in range(wfa.K_COUNT):
-        g.kernel_stats(k, reset=True)
+    # a fixed iteration count: one host check at the end
+    g.set_option(wfa.OPT_CHECK_EVERY, 500)
     times = []
     for _ in range(args.repeats):
         x.copy_(T)
@@ -366,14 +375,22 @@ def run_poisson_large(args, torch, inputs, wfa):
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t0)
     best = min(times)
+    # one more repeat with HIP events around every launch: per-kernel times
+    g.set_option(wfa.OPT_PROFILE, 1)
+    for k in range(wfa.K_COUNT):
+        g.kernel_stats(k, reset=True)
+    x.copy_(T)
+    g.solve(b, x, tol=1e-300, maxit=500, method=args.method)
+    torch.cuda.synchronize()
     kernels = {}
     for k, name in enumerate(wfa.KERNEL_NAMES):
         n, ms, by = g.kernel_stats(k)
         if n:
             kernels[name] = {"us_avg": round(ms / n * 1e3, 1), "gbps": round(by / (ms / n * 1e-3) / 1e9, 1)}
-    streams = STREAMS[args.method]
+    streams = streams_of(args)
     bytes_iter = (streams * 4 + 8) * prob.cells
     return {"workload": "poisson_512x512x1024_f32_500it", "method": args.method,
+            "shadow": args.shadow if args.method == "bicgstab2" else "r0",
             "seconds_best": best, "seconds": times, "iterations": info.iterations,
             "cell_iters_per_s": prob.cells * info.iterations / best,
             "gbps": bytes_iter * info.iterations / best / 1e9,
@@ -492,6 +509,13 @@ METHODS = {"bicgstab": 0, "cg": 1, "bicgstab2": 2}
 STREAMS = {"bicgstab": 17, "cg": 10, "bicgstab2": 14}
 
 
+def streams_of(args) -> int:
+    """Vector streams per iteration; the hashed shadow residual of the
+    two-reduction BiCGStab is computed, not read, in both passes."""
+    s = STREAMS[args.method]
+    return s - 2 if args.method == "bicgstab2" and args.shadow == "hashed" else s
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -500,6 +524,9 @@ def main():
     ap.add_argument("--workload", default="convdiff",
                     choices=["convdiff", "heat32", "poisson_large", "mixed384", "serve", "explicit"])
     ap.add_argument("--method", default="bicgstab2", choices=["bicgstab", "bicgstab2"])
+    ap.add_argument("--shadow", default="hashed", choices=["r0", "hashed"],
+                    help="shadow residual of the two-reduction BiCGStab: r0 (stored) or a "
+                         "field hashed from the cell index (computed, one stream less per pass)")
     ap.add_argument("--compare", type=int, default=1,
                     help="also time the textbook three-pass BiCGStab on the same steps")
     ap.add_argument("--n", type=int, default=256, help="grid cells per axis")

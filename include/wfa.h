@@ -210,7 +210,21 @@ enum {
                                   wfa_explicit_step: 1 to 4; 0 = automatic
                                   (with a constant diffusivity 3 in FP32 and
                                   2 in FP64, else 1).  More than 1 needs
-                                  WFA_COEF_CONST                               */
+                                  WFA_COEF_CONST                               */,
+  WFA_OPT_SHADOW = 12,         /* shadow residual of the two-reduction
+                                  BiCGStab: 0 = r0, stored (default); 1 = a
+                                  fixed field of the cell index (the 32-bit
+                                  PCG hash of the index, top 24 bits mapped to
+                                  [-1, 1)), computed where it is used, which
+                                  saves one vector stream per pass            */
+  WFA_OPT_FORCE_DIVERGE = 13   /* n > 0: the first inner FP32 solve of the
+                                  next WFA_F32_IR64 solve counts as diverged at
+                                  inner iteration n (once), to exercise the
+                                  recovery from the host.  (An inner solve
+                                  diverges when ||r|| grows 1000-fold; it is
+                                  then repeated once, stopped at the iteration
+                                  of its smallest residual, and that
+                                  correction is applied.)                      */
 };
 int wfa_grid_set_option(wfa_grid* g, int option, int64_t value);
 

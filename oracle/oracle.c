@@ -207,6 +207,29 @@ static long cells(const orc_problem* p)
   return (long)p->nx * p->ny * p->nz;
 }
 
+/*
+ * A shadow residual that needs no storage.  BiCGStab accepts any shadow
+ * vector r^ with (r^, r0) != 0 (van der Vorst 1992); r^ = r0 is the usual
+ * choice, this one is a fixed pseudo-random field computed from the cell
+ * index c alone:
+ *   h = PCG hash of c: one step of the 32-bit LCG of PCG
+ *       (state = c * 747796405 + 2891336453), then PCG's RXS-M-XS output
+ *       permutation (O'Neill 2014; as a hash, Jarzynski and Olano 2020);
+ *   r^_c = (h >> 8) * 2^-23 - 1, in [-1, 1), exact in float and double.
+ */
+static uint32_t pcg_hash32(uint32_t c)
+{
+  const uint32_t state = c * 747796405u + 2891336453u;
+  const uint32_t word = ((state >> ((state >> 28u) + 4u)) ^ state) * 277803737u;
+  return (word >> 22u) ^ word;
+}
+
+void orc_shadow(long n, double* rh)
+{
+  for (long c = 0; c < n; ++c)
+    rh[c] = (double)(pcg_hash32((uint32_t)c) >> 8) * (1.0 / 8388608.0) - 1.0;
+}
+
 static int all_finite(const double* a, long n)
 {
   int ok = 1;
@@ -430,8 +453,8 @@ int orc_bicgstab_jacobi(const orc_problem* p, const double* b, double* x,
  * orc_bicgstab; a zero omega is applied (x += alpha p, r = s) before the
  * restart; tt == 0 (s == 0) ends with x + alpha p.
  */
-int orc_bicgstab2(const orc_problem* p, const double* b, double* x, double tol,
-                  int maxit, double* r_out, orc_info* info)
+int orc_bicgstab2_shadow(const orc_problem* p, const double* b, double* x, double tol,
+                         int maxit, int hashed_shadow, double* r_out, orc_info* info)
 {
   const long n = cells(p);
   const size_t bytes = sizeof(double) * (size_t)n;
@@ -457,7 +480,8 @@ int orc_bicgstab2(const orc_problem* p, const double* b, double* x, double tol,
   int first, pending_restart, szero;
 restart:
   residual(p, b, x, r);
-  memcpy(rh, r, bytes);
+  if (hashed_shadow) orc_shadow(n, rh);
+  else memcpy(rh, r, bytes);
   rho = dot(p, rh, r);
   rnorm = sqrt(dot(p, r, r));
   if (!isfinite(rnorm)) { status = ORC_NONFINITE; goto done; }
@@ -541,6 +565,12 @@ done:
   if (r_out) memcpy(r_out, r, bytes);
   free(r); free(rh); free(pv); free(v); free(s); free(t);
   return status;
+}
+
+int orc_bicgstab2(const orc_problem* p, const double* b, double* x, double tol,
+                  int maxit, double* r_out, orc_info* info)
+{
+  return orc_bicgstab2_shadow(p, b, x, tol, maxit, 0, r_out, info);
 }
 
 /*

@@ -93,6 +93,9 @@ def load(path: str | None = None) -> ctypes.CDLL:
     lib.orc_bicgstab.argtypes = [P, D, D, ctypes.c_double, ctypes.c_int, D, I]
     lib.orc_cg.argtypes = [P, D, D, ctypes.c_double, ctypes.c_int, D, I]
     lib.orc_bicgstab2.argtypes = [P, D, D, ctypes.c_double, ctypes.c_int, D, I]
+    lib.orc_bicgstab2_shadow.argtypes = [P, D, D, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                         D, I]
+    lib.orc_shadow.argtypes = [ctypes.c_long, D]
     lib.orc_bicgstab_jacobi.argtypes = [P, D, D, ctypes.c_double, ctypes.c_int, D, I]
     lib.orc_timestep.argtypes = [P, D, ctypes.c_int, ctypes.c_double, ctypes.c_int, I]
     lib.orc_explicit.argtypes = [P, D, ctypes.c_int]
@@ -182,9 +185,24 @@ class Oracle:
     def bicgstab(self, b, x0, tol: float, maxit: int, want_r: bool = False):
         return self._krylov(self.lib.orc_bicgstab, b, x0, tol, maxit, want_r)
 
-    def bicgstab2(self, b, x0, tol: float, maxit: int, want_r: bool = False):
-        """BiCGStab with two reductions per iteration (oracle.c)."""
-        return self._krylov(self.lib.orc_bicgstab2, b, x0, tol, maxit, want_r)
+    def bicgstab2(self, b, x0, tol: float, maxit: int, want_r: bool = False,
+                  hashed_shadow: bool = False):
+        """BiCGStab with two reductions per iteration (oracle.c); with
+        hashed_shadow the shadow residual is the index-hashed field of
+        shadow() instead of r0."""
+        if not hashed_shadow:
+            return self._krylov(self.lib.orc_bicgstab2, b, x0, tol, maxit, want_r)
+        fn = self.lib.orc_bicgstab2_shadow
+
+        def with_shadow(p, bp, xp, tol_, maxit_, rp, ip):
+            return fn(p, bp, xp, tol_, maxit_, 1, rp, ip)
+        return self._krylov(with_shadow, b, x0, tol, maxit, want_r)
+
+    def shadow(self):
+        """The index-hashed shadow residual (oracle.c, orc_shadow)."""
+        rh = np.empty(self.shape)
+        self.lib.orc_shadow(int(rh.size), self._ptr(rh))
+        return rh
 
     def bicgstab_jacobi(self, b, x0, tol: float, maxit: int, want_r: bool = False):
         """BiCGStab on D^{-1} A x = D^{-1} b (oracle.c)."""

@@ -162,11 +162,13 @@ void grid_setup(wfa_grid* g, int nx, int ny, int nz, const wfa_coeffs* c, char* 
   g->check_every = 0;
   g->zchunk = 0;
   g->ir_inner_tol = 1e-4;
+  g->force_div = 0;
   const int w = g->prec == WFA_F32 ? 4 : 8;
   g->ry = 0;
   g->jacobi = 0;
   g->graph = 0;
   g->fuse = 0;
+  g->shadow = 0;
   g->tl = make_tiling(nx, ny, nz, w, 0, 0);
   g->tl32 = make_tiling(nx, ny, nz, 4, 0, 0);
 }
@@ -236,6 +238,10 @@ extern "C" int wfa_grid_set_option(wfa_grid* g, int option, int64_t value) {
       if (value < 0 || value > 100000) return set_error(WFA_ERR_INVALID, "bad check interval");
       g->check_every = (int)value;
       return WFA_OK;
+    case WFA_OPT_FORCE_DIVERGE:
+      if (value < 0) return set_error(WFA_ERR_INVALID, "bad divergence iteration");
+      g->force_div = (int)value;
+      return WFA_OK;
     case WFA_OPT_IR_INNER_TOL:
       if (value <= 0) return set_error(WFA_ERR_INVALID, "bad inner tolerance");
       g->ir_inner_tol = (double)value * 1e-12;
@@ -250,6 +256,10 @@ extern "C" int wfa_grid_set_option(wfa_grid* g, int option, int64_t value) {
       if (value > 1 && g->c.mode != WFA_COEF_CONST)
         return set_error(WFA_ERR_INVALID, "fused explicit steps need a constant diffusivity");
       g->fuse = (int)value;
+      return WFA_OK;
+    case WFA_OPT_SHADOW:
+      if (value != 0 && value != 1) return set_error(WFA_ERR_INVALID, "shadow mode must be 0 or 1");
+      g->shadow = (int)value;
       return WFA_OK;
     case WFA_OPT_GRAPH:
       if (value < -1 || value > 1) return set_error(WFA_ERR_INVALID, "graph mode must be -1, 0 or 1");
@@ -368,10 +378,10 @@ static double bytes_per_cell(const wfa_grid* g, int kernel) {
     case WFA_K_CG_A: return 4 * wi + k;
     case WFA_K_CG_B: return 6 * wi;
     case WFA_K_PERSISTENT: return 17 * wi + 2 * k;
-    case WFA_K_PHASE_AC: return 10 * wi + k;
+    case WFA_K_PHASE_AC: return (g->shadow ? 9 : 10) * wi + k;
     case WFA_K_EXPLICIT: return 2 * w + k;
     case WFA_K_EXPLICIT_FUSED: return 2 * w;  // one read, one write per pass
-    case WFA_K_PHASE_B2: return 4 * wi + k;
+    case WFA_K_PHASE_B2: return (g->shadow ? 3 : 4) * wi + k;
     default: return 0.0;
   }
 }
@@ -597,7 +607,7 @@ static void graph_key(uint64_t (&k)[GraphCache::kKey], const wfa_grid* g, const 
   k[2] = (uint64_t)par;
   k[3] = g->graphs.generation;
   k[4] = (uint64_t)(uintptr_t)L.sc;
-  k[5] = (uint64_t)L.op.jac;
+  k[5] = (uint64_t)L.op.jac | ((uint64_t)L.shadow << 1);
   int q = 6;
   for (const void* p : ptrs) k[q++] = (uint64_t)(uintptr_t)p;
 }
@@ -818,6 +828,7 @@ static int solve_plain(wfa_grid* g, const T* b_user, T* x, bool form_b, double t
   int rc = write_scalars(&h, g->sc, s);
   if (rc) return rc;
   Launch<T> L = ctx<T>(g, g->sc, s);
+  L.shadow = g->method == WFA_METHOD_BICGSTAB2 ? g->shadow : 0;
   const T* b = form_b ? bw : b_user;
   {
     ProfScope ps(g, WFA_K_INIT, s);
@@ -900,14 +911,22 @@ static int solve_ir(wfa_grid* g, const double* b_user, double* x, bool form_b, d
   int status = WFA_ERR_NOCONV;
   const int force_bd = g->force_bd;
   g->force_bd = 0;
+  const int force_div = g->force_div;
+  g->force_div = 0;
+  // > 0: this refinement repeats one whose inner solve diverged, stopping it
+  // at the iteration that had reached its smallest residual (the kernels are
+  // deterministic, so the repeat retraces the same iterates)
+  int inner_cap = 0;
   for (int ref = 0;; ++ref) {
     ho = fresh_scalars(tol, maxit, 0);
     ho.scale = scale;
     ho.inv_scale = 1.0 / scale;
-    hi = fresh_scalars(g->ir_inner_tol, ir_inner_maxit(maxit, total_it), ref == 0 ? force_bd : 0);
+    hi = fresh_scalars(g->ir_inner_tol, inner_cap > 0 ? inner_cap : ir_inner_maxit(maxit, total_it),
+                       ref == 0 ? force_bd : 0);
     hi.scale = scale;
     hi.inv_scale = 1.0 / scale;
-    hi.guard = kIrGuard;
+    hi.guard = inner_cap > 0 ? 0.0 : kIrGuard;
+    hi.force_div = ref == 0 ? force_div : 0;
     if ((rc = write_scalars(&ho, g->sc, s))) return rc;
     if ((rc = write_scalars(&hi, g->sc_in, s))) return rc;
     {
@@ -937,7 +956,15 @@ static int solve_ir(wfa_grid* g, const double* b_user, double* x, bool form_b, d
     total_it += hi.iter;
     rec = hi.bb > 0.0 ? sqrt(hi.rr / hi.bb) : 0.0;
     if (hi.status == ST_NONFINITE) { status = WFA_ERR_NONFINITE; break; }
-    if (hi.diverged) { status = WFA_ERR_NOCONV; break; }   // no usable correction
+    if (hi.diverged) {
+      if (inner_cap == 0 && hi.it_min > 0) {  // repeat it, stopped at its best iterate
+        inner_cap = hi.it_min;
+        continue;
+      }
+      status = WFA_ERR_NOCONV;  // no usable correction
+      break;
+    }
+    inner_cap = 0;
     if (hi.iter > 0) {
       ProfScope ps(g, WFA_K_PROMOTE, s);
       launch_promote(g->n, g->tl.pw_blocks, x, d, g->sc_in, s);

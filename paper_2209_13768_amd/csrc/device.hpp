@@ -43,12 +43,16 @@ struct alignas(64) Scalars {
   double sigma, ts, tt, rr0;   // last reduced values (diagnostics / trace)
   double scale, inv_scale;     // mixed precision: residual scaling by 2^-e
   double guard;                // > 0: stop (diverged) once ||r||^2 > guard * ||r0||^2
+  double rr_min;               // smallest ||r||^2 so far (textbook BiCGStab) ...
   int32_t status, iter, maxit, first, restart, szero, x_zero, force_bd;
   uint32_t counter;            // last-workgroup arrival counter (self-resetting)
   int32_t restart_pending;     // two-reduction BiCGStab: restart after the update
   int32_t diverged;            // set with ST_NOCONV when the guard tripped
-  int32_t pad[5];
+  int32_t it_min;              // ... and the iteration that reached it
+  int32_t force_div;           // n > 0: declare the solve diverged at iteration n (test hook)
+  int32_t pad[3];
 };
+static_assert(sizeof(Scalars) == 192, "the scalar block is three 64-byte lines");
 
 // Grid-wide barrier state of a persistent launch (self-resetting count).
 struct GridBarrier {
@@ -176,6 +180,22 @@ __device__ __forceinline__ T cell_apply_interior(const InteriorCoef<T>& k, T c, 
 #pragma unroll
   for (int f = 0; f < 6; ++f) acc = fma_t(k.coef[f], nb[f], acc);
   return fma_t(k.diag, c, -acc);
+}
+
+// Shadow residual computed from the cell index instead of stored: the
+// 32-bit PCG hash of the index (an LCG step, state = i * 747796405 +
+// 2891336453, then PCG's RXS-M-XS output permutation; O'Neill 2014), whose
+// top 24 bits give r^_i = (h >> 8) 2^-23 - 1 in [-1, 1), exact in FP32 and
+// FP64.  Any r^ with (r^, r0) != 0 serves BiCGStab; this one costs no HBM
+// traffic where r^ = r0 costs one stream per reduction pass.
+__device__ __forceinline__ uint32_t pcg_hash(uint32_t i) {
+  const uint32_t state = i * 747796405u + 2891336453u;
+  const uint32_t word = ((state >> ((state >> 28u) + 4u)) ^ state) * 277803737u;
+  return (word >> 22u) ^ word;
+}
+template <typename T>
+__device__ __forceinline__ T hashed_shadow(size_t i) {
+  return T(pcg_hash((uint32_t)i) >> 8) * T(1.0 / 8388608.0) - T(1);
 }
 
 // One explicit forward-time step of cell P from its old value c and (A x)_P.

@@ -84,7 +84,9 @@ struct wfa_grid {
   wfa::Tiling tl;        // tiling of the grid's vector type
   wfa::Tiling tl32;      // tiling of FP32 inner vectors
   int method, persistent, profile, force_bd, check_every, zchunk, ry, jacobi, graph, fuse;
+  int shadow;  // two-reduction BiCGStab: 0 r^ = r0 (stored), 1 index-hashed r^
   double ir_inner_tol;
+  int force_div;         // n > 0: the next IR solve's first inner solve diverges at n
   wfa::Profiler prof;
   wfa::GraphCache graphs;
 };

@@ -29,6 +29,7 @@ struct Launch {
   double* partials;
   Scalars* sc;
   hipStream_t stream;
+  int shadow;   // 1: the two-reduction BiCGStab's shadow residual is index-hashed
 };
 
 // y = A x

@@ -103,11 +103,11 @@ void launch_init(const Launch<T>& L, bool form_b, const T* x, const T* b_in, T* 
                  T* rh) {
   FinInit fin{L.sc};
   if (L.cell) {
-    if (form_b) dispatch_march(L, PhInit<T, true, true>{L.op, x, b_in, b_out, r, rh}, fin, false, true);
-    else dispatch_march(L, PhInit<T, true, false>{L.op, x, b_in, b_out, r, rh}, fin, false, true);
+    if (form_b) dispatch_march(L, PhInit<T, true, true>{L.op, x, b_in, b_out, r, rh, L.shadow}, fin, false, true);
+    else dispatch_march(L, PhInit<T, true, false>{L.op, x, b_in, b_out, r, rh, L.shadow}, fin, false, true);
   } else {
-    if (form_b) dispatch_march(L, PhInit<T, false, true>{L.op, x, b_in, b_out, r, rh}, fin, false, true);
-    else dispatch_march(L, PhInit<T, false, false>{L.op, x, b_in, b_out, r, rh}, fin, false, true);
+    if (form_b) dispatch_march(L, PhInit<T, false, true>{L.op, x, b_in, b_out, r, rh, L.shadow}, fin, false, true);
+    else dispatch_march(L, PhInit<T, false, false>{L.op, x, b_in, b_out, r, rh, L.shadow}, fin, false, true);
   }
 }
 
@@ -130,6 +130,7 @@ template <typename T>
 void launch_phase_ac(const Launch<T>& L, const T* r, const T* v, const T* t, const T* p,
                      const T* rh, T* x, T* r_out, T* p_out, T* v_out) {
   PhAC<T> ph{};
+  ph.hashed = L.shadow;
   ph.r = r; ph.v = v; ph.t = t; ph.p = p; ph.rh = rh; ph.x = x;
   ph.r_out = r_out; ph.p_out = p_out; ph.v_out = v_out;
   dispatch_march(L, ph, FinAC{L.sc}, true, true);
@@ -138,6 +139,7 @@ void launch_phase_ac(const Launch<T>& L, const T* r, const T* v, const T* t, con
 template <typename T>
 void launch_phase_b2(const Launch<T>& L, const T* r, const T* v, const T* rh, T* t) {
   PhB2<T> ph{};
+  ph.hashed = L.shadow;
   ph.r = r; ph.v = v; ph.rh = rh; ph.t = t;
   dispatch_march(L, ph, FinB2{L.sc}, true, true);
 }

@@ -38,12 +38,13 @@ __device__ __forceinline__ bool fin_ok(double v) { return isfinite(v); }
 
 struct FinInit {
   Scalars* sc;
-  __device__ void operator()(const double (&s)[2]) const {
-    const double bb = s[0], rr = s[1];
+  __device__ void operator()(const double (&s)[3]) const {
+    const double bb = s[0], rr = s[1], rho = s[2];
     sc->bb = bb; sc->rr = rr; sc->rr0 = rr;
-    sc->rho = rr; sc->rho_prev = 1.0; sc->alpha = 1.0; sc->omega = 1.0; sc->beta = 0.0;
+    sc->rho = rho; sc->rho_prev = 1.0; sc->alpha = 1.0; sc->omega = 1.0; sc->beta = 0.0;
     sc->first = 1; sc->restart = 0; sc->szero = 0; sc->restart_pending = 0;
-    if (!fin_ok(bb) || !fin_ok(rr)) sc->status = ST_NONFINITE;
+    sc->rr_min = rr; sc->it_min = 0;
+    if (!fin_ok(bb) || !fin_ok(rr) || !fin_ok(rho)) sc->status = ST_NONFINITE;
     else if (bb == 0.0) sc->status = ST_BZERO;
     else if (sqrt(rr) <= sc->tol * sqrt(bb)) sc->status = ST_CONV;
     else if (sc->iter >= sc->maxit) sc->status = ST_NOCONV;
@@ -81,10 +82,14 @@ struct FinC {
     sc->iter += 1;
     sc->rr = rr;
     sc->x_zero = 0;
+    if (rr < sc->rr_min) { sc->rr_min = rr; sc->it_min = sc->iter; }
     if (sc->szero) sc->status = ST_CONV;
     else if (!fin_ok(rr)) sc->status = ST_NONFINITE;
     else if (sqrt(rr) <= sc->tol * sqrt(sc->bb)) sc->status = ST_CONV;
-    else if (sc->guard > 0.0 && rr > sc->guard * sc->rr0) { sc->status = ST_NOCONV; sc->diverged = 1; }
+    else if ((sc->guard > 0.0 && rr > sc->guard * sc->rr0) || sc->iter == sc->force_div) {
+      sc->status = ST_NOCONV;
+      sc->diverged = 1;
+    }
     else if (sc->omega == 0.0) sc->restart = 1;
     else if (sc->iter >= sc->maxit) sc->status = ST_NOCONV;
     else if (!fin_ok(rho_new)) sc->status = ST_NONFINITE;
@@ -142,6 +147,7 @@ struct FinResid {
       inner->rho = rho; inner->rho_prev = 1.0; inner->alpha = 1.0; inner->omega = 1.0;
       inner->beta = 0.0; inner->first = 1; inner->restart = 0; inner->szero = 0;
       inner->x_zero = 1; inner->iter = 0; inner->diverged = 0;
+      inner->rr_min = rho; inner->it_min = 0;
       if (sc->status != ST_RUN) inner->status = ST_CONV;
       else if (!fin_ok(rho)) inner->status = ST_NONFINITE;
       else if (rho == 0.0) inner->status = ST_CONV;
@@ -225,7 +231,7 @@ struct PhExplicit {
 
 template <typename T, bool CELL, bool FORM_B>
 struct PhInit {
-  static constexpr int NV = 2;
+  static constexpr int NV = 3;
   static constexpr int PD = 1;
   using St = T;
   static __device__ __forceinline__ T val(T u) { return u; }
@@ -235,6 +241,7 @@ struct PhInit {
   T* __restrict__ b_out;
   T* __restrict__ r;
   T* __restrict__ rh;
+  int hashed;      // shadow residual from the cell index (not stored)
   struct Raw { T x; };
   struct ERaw { T b; };
   WFA_PLAIN_OWN_STAGE
@@ -252,9 +259,12 @@ struct PhInit {
     const T rv = bv - Au;
     if (FORM_B) b_out[i] = b0;
     r[i] = rv;
-    rh[i] = rv;
+    T sh = rv;
+    if (hashed) sh = hashed_shadow<T>(i);
+    else rh[i] = rv;
     acc[0] += (double)bv * (double)bv;
     acc[1] += (double)rv * (double)rv;
+    acc[2] += (double)sh * (double)rv;
   }
 };
 
@@ -438,6 +448,7 @@ struct PhAC {
   T* __restrict__ v_out;
   T alpha, omega, beta;
   int first;
+  int hashed;      // shadow residual from the cell index (not stored)
   struct Raw { T r, v, t, p; };
   struct ORaw { T r, v, t, p, x, rh; };
   struct ERaw {};
@@ -457,8 +468,9 @@ struct PhAC {
     return rn + beta * (q.p - omega * q.v);
   }
   __device__ ORaw fetch_own(size_t i) const {
-    if (first) return {r[i], T(0), T(0), T(0), T(0), ld_once(rh + i)};
-    return {r[i], v[i], t[i], p[i], ld_once(x + i), ld_once(rh + i)};
+    const T sh = hashed ? hashed_shadow<T>(i) : ld_once(rh + i);
+    if (first) return {r[i], T(0), T(0), T(0), T(0), sh};
+    return {r[i], v[i], t[i], p[i], ld_once(x + i), sh};
   }
   // The previous iteration's update of this cell, applied and stored as soon
   // as the cell is staged: x' = x + alpha p + omega s, r' = s - omega t,
@@ -503,13 +515,16 @@ struct PhB2 {
   const T* __restrict__ rh;
   T* __restrict__ t;
   T alpha;
+  int hashed;      // shadow residual from the cell index (not stored)
   struct Raw { T r, v; };
   struct ERaw { T rh; };
   WFA_PLAIN_OWN_STAGE
   __device__ void bind(const Scalars* sc) { alpha = (T)sc->alpha; }
   __device__ Raw fetch(size_t i) const { return {r[i], v[i]}; }
   __device__ T combine(const Raw& q) const { return q.r - alpha * q.v; }
-  __device__ ERaw efetch(size_t i) const { return {ld_once(rh + i)}; }
+  __device__ ERaw efetch(size_t i) const {
+    return {hashed ? hashed_shadow<T>(i) : ld_once(rh + i)};
+  }
   __device__ void epilogue(size_t i, T s, T Au, T, uint32_t, const ERaw& e, T dg,
                            double (&acc)[NV]) const {
     st_once(t + i, Au);

@@ -93,6 +93,7 @@ struct Request {
   size_t off = 0, bytes = 0;
   wfa_grid g{};
   int total_it = 0, refinements = 0, restarts = 0;
+  int inner_cap = 0;  // > 0: repeating a diverged inner solve up to its best iterate
   double scale = 1.0;
   double last_rec = 0.0;
   double t_submit = 0.0, t_done = 0.0;
@@ -229,15 +230,15 @@ int start_request(wfa_server* sv, Request* r) {
 }
 
 // IR: apply the inner correction and compute the next FP64 residual.
-int refine_request(wfa_server* sv, Request* r, double scale_next) {
+int refine_request(wfa_server* sv, Request* r, double scale_next, bool promote) {
   wfa_grid& g = r->g;
   hipStream_t s = sv->stream;
-  launch_promote(g.n, g.tl.pw_blocks, (double*)r->T, g.d32, g.sc_in, s);
+  if (promote) launch_promote(g.n, g.tl.pw_blocks, (double*)r->T, g.d32, g.sc_in, s);
   Scalars ho = fresh(r->tol, r->maxit);
   ho.scale = scale_next; ho.inv_scale = 1.0 / scale_next;
-  Scalars hi = fresh(1e-4, ir_inner_maxit(r->maxit, r->total_it));
+  Scalars hi = fresh(1e-4, r->inner_cap > 0 ? r->inner_cap : ir_inner_maxit(r->maxit, r->total_it));
   hi.scale = scale_next; hi.inv_scale = 1.0 / scale_next;
-  hi.guard = kIrGuard;
+  hi.guard = r->inner_cap > 0 ? 0.0 : kIrGuard;
   sv->h_sc[r->slot * kScalarsPerSlot + 0] = ho;
   sv->h_sc[r->slot * kScalarsPerSlot + 1] = hi;
   if (int rc = put(sv, g.sc, &sv->h_sc[r->slot * kScalarsPerSlot], 2 * sizeof(Scalars)))
@@ -330,10 +331,19 @@ int advance(wfa_server* sv, Request* r) {
       retire(sv, r, WFA_ERR_NONFINITE, NAN);
       return WFA_OK;
     }
-    if (in.diverged) {   // no usable correction
-      retire(sv, r, WFA_ERR_NOCONV, sqrt(o.rr / o.bb));
+    if (in.diverged) {
+      if (r->inner_cap == 0 && in.it_min > 0) {
+        // repeat this refinement, stopping the inner solve at the iteration
+        // that had reached its smallest residual (deterministic kernels
+        // retrace the same iterates); nothing is promoted
+        r->inner_cap = in.it_min;
+        r->phase = R_REFINE;
+        return refine_request(sv, r, r->scale, false);
+      }
+      retire(sv, r, WFA_ERR_NOCONV, sqrt(o.rr / o.bb));  // no usable correction
       return WFA_OK;
     }
+    r->inner_cap = 0;
     if (r->restarts > WFA_MAX_RESTARTS) {
       retire(sv, r, WFA_ERR_BREAKDOWN, sqrt(o.rr / o.bb));
       return WFA_OK;
@@ -346,7 +356,7 @@ int advance(wfa_server* sv, Request* r) {
     const double rms = sqrt(o.rr / (double)g.n);
     const double scale = (rms > 0.0 && isfinite(rms)) ? ldexp(1.0, -(int)lround(log2(rms))) : 1.0;
     r->phase = R_REFINE;
-    int rc = refine_request(sv, r, scale);
+    int rc = refine_request(sv, r, scale, true);
     if (rc) return rc;
     if (r->code == WFA_ERR_NOCONV) r->phase = R_FINAL;  // read the residual next round
     return WFA_OK;

@@ -233,6 +233,30 @@ def test_mixed_precision_reaches_fp64_accuracy(wfa, oracle_mod):
     assert rel_l2(to_np(x), xo) <= 1e-7
 
 
+def test_mixed_precision_recovers_from_a_diverged_inner_solve(wfa, oracle_mod):
+    """An inner FP32 solve that diverges (forced from the host at inner
+    iteration 7) is repeated once, stopped at its smallest residual, and
+    its correction applied: the solve still reaches the FP64 tolerance, with
+    one more residual pass than without the forced divergence."""
+    prob = inputs.convdiff(n=40, seed=4, u=(4.0, 2.0, 1.0))
+    o = oracle_mod.Oracle(prob)
+    b = o.rhs(prob.T0)
+    runs = []
+    for force in (0, 7):
+        g = _grid(wfa, prob, wfa.F32_IR64)
+        g.set_option(wfa.OPT_PROFILE, 1)
+        g.set_option(wfa.OPT_FORCE_DIVERGE, force)
+        x, info = g.solve(g.field(b), g.field(prob.T0), tol=1e-12, maxit=5000)
+        assert info.status == wfa.OK, (force, info)
+        assert o.true_relres(b, to_np(x)) <= 1e-12
+        n_resid = g.kernel_stats(wfa.K_RESIDUAL)[0]
+        runs.append((to_np(x), info, n_resid))
+    (x0, i0, n0), (x1, i1, n1) = runs
+    assert n0 == i0.refinements + 1
+    assert n1 == i1.refinements + 2          # the repeated refinement
+    assert rel_l2(x1, x0) <= 1e-9
+
+
 def test_status_paths(wfa, oracle_mod):
     prob = inputs.random_problem(107, 20, 12, 9, cell=True, u=(1.0, 0.0, 0.0))
     o = oracle_mod.Oracle(prob)

@@ -69,6 +69,8 @@ MUTANTS = [
     ("explicit_flux_sign", "T[c] = Tn[c] - flux + bterm;", "T[c] = Tn[c] + flux + bterm;"),
     ("explicit_keeps_identity", "double flux = (diag - 1.0) * Tn[c];",
      "double flux = diag * Tn[c];"),
+    ("bicgstab2_shadow_ignored", "if (hashed_shadow) orc_shadow(n, rh);\n  else memcpy(rh, r, bytes);",
+     "memcpy(rh, r, bytes);"),
     ("dot_drops_last_plane", "for (int k = 0; k < nz; ++k) total += part[k];",
      "for (int k = 0; k + 1 < nz; ++k) total += part[k];"),
 ]

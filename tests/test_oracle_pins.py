@@ -545,3 +545,69 @@ def test_worked_examples_of_eq2_and_eq3(oracle_mod):
             got, infos = o.timestep(prob.T0, 1, 1e-15, 100)
             assert infos[0].status == 0
         assert np.max(np.abs(got - T1)) <= 2e-15 * max(1.0, np.max(np.abs(T1))), (scheme, prob.shape)
+
+
+# ------------------------------------------------- hashed shadow residual
+def test_hashed_shadow_field(oracle_mod):
+    """The stored-nothing shadow residual: a fixed field of the cell index
+    alone, in [-1, 1), exact in FP32, with no structure a Krylov method
+    could lock onto (mean near 0, no repeats in small grids)."""
+    p1 = inputs.random_problem(56, 20, 20, 20)
+    p2 = inputs.random_problem(57, 40, 10, 20, cell=True, u=(1.0, 0.0, 0.0))
+    r1 = oracle_mod.Oracle(p1).shadow().ravel()
+    r2 = oracle_mod.Oracle(p2).shadow().ravel()
+    assert np.array_equal(r1, r2)                       # index only, not the problem
+    assert r1.min() >= -1.0 and r1.max() < 1.0
+    assert np.array_equal(r1.astype(np.float32).astype(np.float64), r1)
+    assert abs(r1.mean()) < 0.05 and 0.3 < r1.std() < 0.7
+    assert len(np.unique(r1)) > 0.99 * r1.size
+
+
+@pytest.mark.parametrize("name", sorted(P5_CASES))
+def test_bicgstab2_hashed_shadow_dense_direct_solve(oracle_mod, name):
+    p = inputs.random_problem(58, 4, 4, 4, **P5_CASES[name])
+    o = oracle_mod.Oracle(p)
+    A = dense_by_columns(o)
+    b = o.rhs(p.T0)
+    x_ref = np.linalg.solve(A, b.ravel()).reshape(p.shape)
+    x, info = o.bicgstab2(b, p.T0, 1e-14, 400, hashed_shadow=True)
+    assert info.status == oracle_mod.OK
+    assert rel_l2(x, x_ref) <= 1e-12
+
+
+def _textbook_bicgstab(apply, b, x, rh, k):
+    """van der Vorst's BiCGStab, k full iterations from x, shadow rh."""
+    r = b - apply(x)
+    rho_prev = alpha = omega = 1.0
+    p = np.zeros_like(r)
+    v = np.zeros_like(r)
+    for _ in range(k):
+        rho = np.vdot(rh, r)
+        beta = (rho / rho_prev) * (alpha / omega)
+        p = r + beta * (p - omega * v)
+        v = apply(p)
+        alpha = rho / np.vdot(rh, v)
+        s = r - alpha * v
+        t = apply(s)
+        omega = np.vdot(t, s) / np.vdot(t, t)
+        x = x + alpha * p + omega * s
+        r = s - omega * t
+        rho_prev = rho
+    return x
+
+
+@pytest.mark.parametrize("cell,u", [(False, (0.0, 0.0, 0.0)), (True, (1.0, 0.5, 0.25))])
+def test_bicgstab2_hashed_shadow_follows_textbook_iterates(oracle_mod, cell, u):
+    """With the hashed shadow, the two-reduction iterates are the textbook
+    iterates for that shadow vector (restated here independently)."""
+    p = inputs.random_problem(59, 20, 15, 12, cell=cell, u=u, bc_kind=inputs.MIXED_BC_KIND)
+    o = oracle_mod.Oracle(p)
+    b = o.rhs(p.T0)
+    rh = o.shadow()
+    for k in (1, 2, 3, 5):
+        xt = _textbook_bicgstab(o.apply, b, p.T0.copy(), rh, k)
+        x2, i2 = o.bicgstab2(b, p.T0, 1e-300, k, hashed_shadow=True)
+        assert i2.iterations == k
+        assert rel_l2(x2, xt) <= 1e-12
+        xr, _ = o.bicgstab2(b, p.T0, 1e-300, k)
+        assert rel_l2(xr, xt) > 1e-9                     # r^ = r0 gives other iterates
