@@ -63,8 +63,9 @@ extern "C" {
 enum {
   WFA_F64 = 0,      /* FP64 vectors and operator                              */
   WFA_F32 = 1,      /* FP32 vectors and operator, FP64 dot accumulation       */
-  WFA_F32_IR64 = 2  /* FP64 fields; FP32 inner BiCGStab inside FP64 iterative
-                       refinement (residual, update and norms in FP64)       */
+  WFA_F32_IR64 = 2  /* FP64 fields; FP32 inner two-reduction BiCGStab on the
+                       Jacobi-scaled system inside FP64 iterative refinement
+                       (residual, update and norms in FP64)                  */
 };
 enum { WFA_COEF_CONST = 0, WFA_COEF_CELL = 1 };
 enum { WFA_BC_DIRICHLET = 0, WFA_BC_ZEROFLUX = 1 };
@@ -135,7 +136,9 @@ int wfa_rhs(wfa_grid* g, const void* T, void* b, void* stream);
  * on WFA_ERR_NOCONV, the last iterate) on exit.  Stops at the first full
  * iteration with recursive ||r|| <= tol*||b||; b == 0 gives x = 0.  Exact
  * breakdown (rho, sigma or omega == 0) restarts from b - A x, at most
- * WFA_MAX_RESTARTS times.  `info` may be NULL.  Synchronises `stream`. */
+ * WFA_MAX_RESTARTS times.  `info` may be NULL.  Synchronises `stream`.
+ * On a WFA_F32_IR64 grid this is the refinement loop, stopping on the FP64
+ * true residual, whose inner FP32 solves use the two-reduction form. */
 int wfa_bicgstab_solve(wfa_grid* g, const void* b, void* x, double tol, int maxit,
                        wfa_solve_info* info, void* stream);
 
@@ -149,8 +152,8 @@ int wfa_cg_solve(wfa_grid* g, const void* b, void* x, double tol, int maxit,
  * each iteration is applied on the fly inside the next operator pass, and
  * the next rho is predicted from (rh,s) - omega (rh,t) so that beta is
  * known before that pass (the paper points to reduction-limited Krylov
- * variants, sections 3.2.2 and 5).  Same contract as wfa_bicgstab_solve;
- * WFA_F64 and WFA_F32 grids. */
+ * variants, sections 3.2.2 and 5).  Same contract as wfa_bicgstab_solve
+ * (on a WFA_F32_IR64 grid the two entry points are the same refinement). */
 int wfa_bicgstab2_solve(wfa_grid* g, const void* b, void* x, double tol, int maxit,
                         wfa_solve_info* info, void* stream);
 
@@ -285,8 +288,12 @@ int wfa_stream_probe(const void* src, void* dst, size_t bytes, int reps, double*
  * arrival order as arena space and slots free up; all resident solves
  * advance together in batched launches (continuous batching); a request
  * finishes independently of the others and its result does not depend on
- * which requests ran beside it.  A background host thread drives the GPU
- * on `stream`.  Precision of every request: c->precision. */
+ * which requests ran beside it.  Every request is solved with the
+ * two-reduction BiCGStab (r^ = r0), as wfa_timestep does with
+ * WFA_OPT_METHOD = WFA_METHOD_BICGSTAB2; WFA_F32_IR64 requests run it as the
+ * inner solve of refinement, as wfa_timestep does.  A background host
+ * thread drives the GPU on `stream`.  Precision of every request:
+ * c->precision. */
 int wfa_server_create(void* arena, size_t arena_bytes, int max_slots, void* stream,
                       wfa_server** out);
 

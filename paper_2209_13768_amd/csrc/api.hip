@@ -693,12 +693,14 @@ static int iterate_bicgstab(wfa_grid* g, const Launch<T>& L, T* x, T* r, T* rh, 
 // the [par ^ 1] buffers (r too: neighbours read the old r on the halo).
 template <typename T>
 static int iterate_bicgstab2(wfa_grid* g, const Launch<T>& L, T* x, T** r, T* rh, T** p, T** v,
-                             T* t, const T* b, Scalars* h, int* restarts, int* par_io) {
+                             T* t, const T* b, Scalars* h, int* restarts, int* par_io,
+                             bool restartable) {
   int par = *par_io;
   int rc = read_scalars(g, L.sc, h, L.stream);
   if (rc) return rc;
   while (h->status == ST_RUN) {
     if (h->restart) {
+      if (!restartable) break;
       if (++*restarts > WFA_MAX_RESTARTS) { h->status = -1; break; }
       {
         ProfScope ps(g, WFA_K_INIT, L.stream);
@@ -841,7 +843,7 @@ static int solve_plain(wfa_grid* g, const T* b_user, T* x, bool form_b, double t
   if (g->method == WFA_METHOD_CG)
     rc = iterate_cg<T>(g, L, x, r, p, t, &h);
   else if (g->method == WFA_METHOD_BICGSTAB2)
-    rc = iterate_bicgstab2<T>(g, L, x, rbuf, rh, p, v, t, b, &h, &restarts, &rpar);
+    rc = iterate_bicgstab2<T>(g, L, x, rbuf, rh, p, v, t, b, &h, &restarts, &rpar, true);
   else
     rc = iterate_bicgstab<T>(g, L, x, r, rh, p, v, t, b, &h, &restarts, true);
   if (rc) return rc;
@@ -888,6 +890,7 @@ static int solve_ir(wfa_grid* g, const double* b_user, double* x, bool form_b, d
   auto t0 = std::chrono::steady_clock::now();
   float** vec = (float**)g->vec;
   float *r = vec[0], *rh = vec[1], *t = vec[2];
+  float* rbuf[2] = {vec[0], vec[8]};
   float* p[2] = {vec[3], vec[4]};
   float* v[2] = {vec[5], vec[6]};
   float* d = g->d32;
@@ -944,12 +947,12 @@ static int solve_ir(wfa_grid* g, const double* b_user, double* x, bool form_b, d
       break;
     }
     if (ref >= max_ref || total_it >= maxit) { status = WFA_ERR_NOCONV; break; }
-    // inner FP32 solve of A d = r32 from d = 0
-    // (an inner breakdown ends the inner solve; the next refinement restarts
-    // it from the FP64 true residual)
-    int inner_restarts = 0;
-    if ((rc = iterate_bicgstab<float>(g, L32, d, r, rh, p, v, t, rh, &hi, &inner_restarts,
-                                      false)))
+    // inner FP32 solve of A d = r32 from d = 0 with the two-reduction
+    // BiCGStab (r32 sits in r[0]; an inner breakdown ends the inner solve and
+    // the next refinement restarts it from the FP64 true residual)
+    int inner_restarts = 0, inner_par = 0;
+    if ((rc = iterate_bicgstab2<float>(g, L32, d, rbuf, rh, p, v, t, nullptr, &hi,
+                                       &inner_restarts, &inner_par, false)))
       return rc;
     if (hi.status == ST_RUN && hi.restart) ++restarts;
     if (restarts > WFA_MAX_RESTARTS) { status = WFA_ERR_BREAKDOWN; break; }
@@ -1018,9 +1021,9 @@ int solve_any(wfa_grid* g, const void* b, void* x, bool form_b, double tol, int 
     case WFA_F64: return solve_plain<double>(g, (const double*)b, (double*)x, form_b, tol, maxit, info, s);
     case WFA_F32: return solve_plain<float>(g, (const float*)b, (float*)x, form_b, tol, maxit, info, s);
     default:
-      if (g->method != WFA_METHOD_BICGSTAB)
-        return set_error(WFA_ERR_INVALID,
-                         "WFA_F32_IR64 grids iterate with textbook BiCGStab only");
+      // the inner solve is always the two-reduction BiCGStab
+      if (g->method == WFA_METHOD_CG)
+        return set_error(WFA_ERR_INVALID, "WFA_F32_IR64 grids iterate with BiCGStab, not CG");
       return solve_ir(g, (const double*)b, (double*)x, form_b, tol, maxit, info, s);
   }
 }

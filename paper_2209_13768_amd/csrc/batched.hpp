@@ -13,6 +13,8 @@ struct SolveDesc {
   const float* kappa;
   T* x;                 // iterate of the Krylov solve (IR: the FP32 correction)
   T *r, *rh, *t, *p0, *p1, *v0, *v1;
+  T* r1;                // second residual buffer of the two-reduction BiCGStab
+  int par;              // buffer parity of the solve at the first iteration of the launch
   double* partials;
   Scalars* sc;
   size_t n;
@@ -20,13 +22,14 @@ struct SolveDesc {
   int pw_blocks;
 };
 
-// One BiCGStab iteration (phases A, B, C) of every solve in descs[0..nsolves).
-// tile_bases / pw_bases: prefix sums of the solves' tile and pointwise-block
-// counts (nsolves + 1 entries each, device memory).  Every solve's tiling
-// must use `ry` rows per wave.
+// One two-reduction BiCGStab iteration (passes AC and B2) of every solve in
+// descs[0..nsolves).  tile_bases: prefix sums of the solves' tile counts
+// (nsolves + 1 entries, device memory); every solve's tiling must use `ry`
+// rows per wave.  Solve s uses the buffers of parity descs[s].par ^ (q & 1),
+// q = the index of this iteration among the launches made since the
+// descriptors were written.
 template <typename T>
-void launch_batch_iteration(const SolveDesc<T>* descs, const int* tile_bases, int tiles_total,
-                            const int* pw_bases, int pw_total, int nsolves, int parity, int ry,
-                            hipStream_t s);
+void launch_batch_iteration2(const SolveDesc<T>* descs, const int* tile_bases, int tiles_total,
+                             int nsolves, int q, int ry, hipStream_t s);
 
 }  // namespace wfa

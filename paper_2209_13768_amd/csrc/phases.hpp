@@ -448,6 +448,7 @@ struct PhAC {
   T* __restrict__ v_out;
   T alpha, omega, beta;
   int first;
+  int x_zero;      // x is still the zero initial guess (refinement's correction)
   int hashed;      // shadow residual from the cell index (not stored)
   struct Raw { T r, v, t, p; };
   struct ORaw { T r, v, t, p, x, rh; };
@@ -457,6 +458,7 @@ struct PhAC {
     omega = (T)sc->omega;
     beta = (T)sc->beta;
     first = sc->first;
+    x_zero = sc->x_zero;
   }
   __device__ Raw fetch(size_t i) const {
     if (first) return {r[i], T(0), T(0), T(0)};
@@ -470,7 +472,7 @@ struct PhAC {
   __device__ ORaw fetch_own(size_t i) const {
     const T sh = hashed ? hashed_shadow<T>(i) : ld_once(rh + i);
     if (first) return {r[i], T(0), T(0), T(0), T(0), sh};
-    return {r[i], v[i], t[i], p[i], ld_once(x + i), sh};
+    return {r[i], v[i], t[i], p[i], x_zero ? T(0) : ld_once(x + i), sh};
   }
   // The previous iteration's update of this cell, applied and stored as soon
   // as the cell is staged: x' = x + alpha p + omega s, r' = s - omega t,
@@ -547,8 +549,14 @@ struct FinAC {
       sc->iter += 1;
       sc->rr = rr;
       sc->x_zero = 0;
+      if (rr < sc->rr_min) { sc->rr_min = rr; sc->it_min = sc->iter; }
       if (!fin_ok(rr)) { sc->status = ST_NONFINITE; return; }
       if (sc->szero || sqrt(rr) <= sc->tol * sqrt(sc->bb)) { sc->status = ST_CONV; return; }
+      if ((sc->guard > 0.0 && rr > sc->guard * sc->rr0) || sc->iter == sc->force_div) {
+        sc->status = ST_NOCONV;
+        sc->diverged = 1;
+        return;
+      }
       if (sc->restart_pending) { sc->restart = 1; return; }
       if (sc->iter >= sc->maxit) { sc->status = ST_NOCONV; return; }
       if (!fin_ok(rho_exact)) { sc->status = ST_NONFINITE; return; }

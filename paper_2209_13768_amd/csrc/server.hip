@@ -94,6 +94,7 @@ struct Request {
   wfa_grid g{};
   int total_it = 0, refinements = 0, restarts = 0;
   int inner_cap = 0;  // > 0: repeating a diverged inner solve up to its best iterate
+  int par = 0;        // buffer parity of the next iteration (0 after every (re)start)
   double scale = 1.0;
   double last_rec = 0.0;
   double t_submit = 0.0, t_done = 0.0;
@@ -131,7 +132,6 @@ struct wfa_server {
   bool stop = false;
   int worker_error = WFA_OK;
   char worker_msg[256] = "";
-  int parity32 = 0, parity64 = 0;
   int chunk = 4;
   int ry = 0;        // rows per wave of every resident solve's tiling
   std::thread worker;
@@ -181,6 +181,8 @@ SolveDesc<T> make_desc(Request* r, T* x) {
   T** v = (T**)g.vec;
   d.x = x;
   d.r = v[0]; d.rh = v[1]; d.t = v[2]; d.p0 = v[3]; d.p1 = v[4]; d.v0 = v[5]; d.v1 = v[6];
+  d.r1 = v[8];
+  d.par = r->par;
   d.partials = g.partials;
   d.sc = g.prec == WFA_F32_IR64 ? g.sc_in : g.sc;
   d.n = g.n;
@@ -194,6 +196,7 @@ SolveDesc<T> make_desc(Request* r, T* x) {
 int start_request(wfa_server* sv, Request* r) {
   wfa_grid& g = r->g;
   hipStream_t s = sv->stream;
+  r->par = 0;  // the first residual goes to the parity-0 buffer
   if (g.prec == WFA_F32_IR64) {
     Scalars ho = fresh(r->tol, r->maxit), hi = fresh(1e-4, ir_inner_maxit(r->maxit, 0));
     hi.guard = kIrGuard;
@@ -247,6 +250,7 @@ int refine_request(wfa_server* sv, Request* r, double scale_next, bool promote) 
                    g.partials, g.sc, s};
   float** v = (float**)g.vec;
   launch_residual<double>(L, (const double*)r->T, g.b64, v[0], v[1], g.sc_in, 2);
+  r->par = 0;
   r->scale = scale_next;
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(sv, "refine", e);
@@ -370,6 +374,7 @@ int advance(wfa_server* sv, Request* r) {
       r->code = WFA_ERR_BREAKDOWN;
       return final_residual(sv, r);
     }
+    r->par = 0;  // the restart's residual goes to the parity-0 buffer
     if (g.prec == WFA_F64) {
       Launch<double> L{g.tl, g.op64, g.c.mode == WFA_COEF_CELL, (const float*)g.c.kappa,
                        g.partials, g.sc, sv->stream};
@@ -488,19 +493,16 @@ void worker_main(wfa_server* sv) {
     }
     if (!rc) {
       const int S = sv->max_slots;
+      // two-reduction BiCGStab iterations of every resident solve
       for (int q = 0; q < sv->chunk; ++q) {
-        if (n32) {
-          launch_batch_iteration<float>(sv->d32, sv->bases, t32, sv->bases + (S + 1), p32, n32,
-                                        sv->parity32, sv->ry, sv->stream);
-          sv->parity32 ^= 1;
-        }
-        if (n64) {
-          launch_batch_iteration<double>(sv->d64, sv->bases + 2 * (S + 1), t64,
-                                         sv->bases + 3 * (S + 1), p64, n64, sv->parity64,
-                                         sv->ry, sv->stream);
-          sv->parity64 ^= 1;
-        }
+        if (n32)
+          launch_batch_iteration2<float>(sv->d32, sv->bases, t32, n32, q, sv->ry, sv->stream);
+        if (n64)
+          launch_batch_iteration2<double>(sv->d64, sv->bases + 2 * (S + 1), t64, n64, q, sv->ry,
+                                          sv->stream);
       }
+      for (Request* r : sv->slots)
+        if (r && (r->phase == R_ITER || r->phase == R_REFINE)) r->par ^= (sv->chunk & 1);
       hipError_t e = hipGetLastError();
       if (e != hipSuccess) rc = fail(sv, "batched iteration", e);
     }
