@@ -215,8 +215,9 @@ enum {
                                   2 in FP64, else 1).  More than 1 needs
                                   WFA_COEF_CONST                               */,
   WFA_OPT_SHADOW = 12,         /* shadow residual of the two-reduction
-                                  BiCGStab: 0 = r0, stored (default); 1 = a
-                                  fixed field of the cell index (the 32-bit
+                                  BiCGStab (also the inner solve of
+                                  WFA_F32_IR64): 0 = r0, stored (default); 1 =
+                                  a fixed field of the cell index (the 32-bit
                                   PCG hash of the index, top 24 bits mapped to
                                   [-1, 1)), computed where it is used, which
                                   saves one vector stream per pass            */
@@ -289,9 +290,10 @@ int wfa_stream_probe(const void* src, void* dst, size_t bytes, int reps, double*
  * advance together in batched launches (continuous batching); a request
  * finishes independently of the others and its result does not depend on
  * which requests ran beside it.  Every request is solved with the
- * two-reduction BiCGStab (r^ = r0), as wfa_timestep does with
- * WFA_OPT_METHOD = WFA_METHOD_BICGSTAB2; WFA_F32_IR64 requests run it as the
- * inner solve of refinement, as wfa_timestep does.  A background host
+ * two-reduction BiCGStab and the index-hashed shadow residual, as
+ * wfa_timestep does with WFA_OPT_METHOD = WFA_METHOD_BICGSTAB2 and
+ * WFA_OPT_SHADOW = 1; WFA_F32_IR64 requests run it as the inner solve of
+ * refinement, as wfa_timestep does.  A background host
  * thread drives the GPU on `stream`.  Precision of every request:
  * c->precision. */
 int wfa_server_create(void* arena, size_t arena_bytes, int max_slots, void* stream,

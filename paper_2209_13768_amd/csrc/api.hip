@@ -807,7 +807,7 @@ static int true_residual(wfa_grid* g, const Tin* b, const Tin* x, double* rel, h
   Launch<double> L = plain_ctx<double>(g, g->sc_aux, s);
   {
     ProfScope ps(g, WFA_K_RESIDUAL, s);
-    launch_residual<Tin>(L, x, b, nullptr, nullptr, nullptr, 0);
+    launch_residual<Tin>(L, x, b, nullptr, nullptr, nullptr, 0, 0);
   }
   if ((rc = check_launch("residual"))) return rc;
   if ((rc = read_scalars(g, g->sc_aux, &h, s))) return rc;
@@ -901,6 +901,7 @@ static int solve_ir(wfa_grid* g, const double* b_user, double* x, bool form_b, d
   // of magnitude, which FP32 BiCGStab needs to make progress at all there
   Launch<float> L32 = ctx<float>(g, g->sc_in, s);
   L32.op.jac = 1;
+  L32.shadow = g->shadow;  // the inner solve's shadow residual (as the residual pass wrote it)
   const double* b = b_user;
   if (form_b) {
     launch_rhs<double>(L64, x, g->b64);
@@ -934,7 +935,7 @@ static int solve_ir(wfa_grid* g, const double* b_user, double* x, bool form_b, d
     if ((rc = write_scalars(&hi, g->sc_in, s))) return rc;
     {
       ProfScope ps(g, WFA_K_RESIDUAL, s);
-      launch_residual<double>(L64, x, b, r, rh, g->sc_in, 2);
+      launch_residual<double>(L64, x, b, r, rh, g->sc_in, 2, g->shadow);
     }
     if ((rc = check_launch("residual"))) return rc;
     if ((rc = read_scalars(g, g->sc, &ho, s))) return rc;

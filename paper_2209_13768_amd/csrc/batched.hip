@@ -46,6 +46,7 @@ k_batch_march(const SolveDesc<T>* __restrict__ descs, const int* __restrict__ ba
     PhAC<T> ph{};
     ph.r = r_in; ph.v = v_in; ph.t = d.t; ph.p = p_in; ph.rh = d.rh; ph.x = d.x;
     ph.r_out = r_out; ph.p_out = p_out; ph.v_out = v_out;
+    ph.hashed = d.hashed;
     ph.bind(sc);
     double acc[3] = {0.0, 0.0, 0.0};
     if (d.cell) march_tile<T, true, RY>(d.geo, d.op, d.kappa, tile, ph, acc, su, sk);
@@ -54,6 +55,7 @@ k_batch_march(const SolveDesc<T>* __restrict__ descs, const int* __restrict__ ba
   } else {
     PhB2<T> ph{};
     ph.r = r_out; ph.v = v_out; ph.rh = d.rh; ph.t = d.t;
+    ph.hashed = d.hashed;
     ph.bind(sc);
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     if (d.cell) march_tile<T, true, RY>(d.geo, d.op, d.kappa, tile, ph, acc, su, sk);

@@ -15,6 +15,7 @@ struct SolveDesc {
   T *r, *rh, *t, *p0, *p1, *v0, *v1;
   T* r1;                // second residual buffer of the two-reduction BiCGStab
   int par;              // buffer parity of the solve at the first iteration of the launch
+  int hashed;           // shadow residual hashed from the cell index (not stored)
   double* partials;
   Scalars* sc;
   size_t n;

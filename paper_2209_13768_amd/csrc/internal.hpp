@@ -78,10 +78,12 @@ void launch_cg_a(const Launch<T>& L, const T* r, const T* d, T* d_out, T* q);
 template <typename T>
 void launch_cg_b(const Launch<T>& L, T* x, const T* d, T* r, const T* q);
 // FP64 residual of Tin-typed x, b: (r,r), (b,b); optionally r32 = fp32(r *
-// scale) into r32 and rh32 and (r32, r32) for the inner solve (sc_inner).
+// scale) into r32, the inner shadow residual (r32 itself into rh32, or the
+// index-hashed field when `hashed`), and (r32, r32), (rh, r32) for the inner
+// solve (sc_inner).
 template <typename Tin>
 void launch_residual(const Launch<double>& L, const Tin* x, const Tin* b, float* r32,
-                     float* rh32, Scalars* sc_inner, int mode);
+                     float* rh32, Scalars* sc_inner, int mode, int hashed);
 // x64 += inv_scale * d32 (scalars of the inner solve)
 void launch_promote(size_t n, int blocks, double* x, const float* d, const Scalars* sc_inner,
                     hipStream_t s);

@@ -153,9 +153,9 @@ void launch_cg_a(const Launch<T>& L, const T* r, const T* d, T* d_out, T* q) {
 
 template <typename Tin>
 void launch_residual(const Launch<double>& L, const Tin* x, const Tin* b, float* r32,
-                     float* rh32, Scalars* sc_inner, int mode) {
+                     float* rh32, Scalars* sc_inner, int mode, int hashed) {
   PhResid<Tin> ph{};
-  ph.x = x; ph.b = b; ph.r32 = r32; ph.rh32 = rh32; ph.emit = mode;
+  ph.x = x; ph.b = b; ph.r32 = r32; ph.rh32 = rh32; ph.emit = mode; ph.hashed = hashed;
   dispatch_march(L, ph, FinResid{L.sc, mode ? sc_inner : nullptr}, false, true);
 }
 
@@ -331,8 +331,8 @@ WFA_INST(double)
 WFA_INST(float)
 #undef WFA_INST
 template void launch_residual<double>(const Launch<double>&, const double*, const double*,
-                                      float*, float*, Scalars*, int);
+                                      float*, float*, Scalars*, int, int);
 template void launch_residual<float>(const Launch<double>&, const float*, const float*, float*,
-                                     float*, Scalars*, int);
+                                     float*, Scalars*, int, int);
 
 }  // namespace wfa

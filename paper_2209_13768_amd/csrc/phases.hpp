@@ -135,23 +135,26 @@ struct FinCgB {
 struct FinResid {
   Scalars* sc;
   Scalars* inner;  // may be null
-  __device__ void operator()(const double (&s)[3]) const {
-    const double rr = s[0], bb = s[1], rho = s[2];
+  __device__ void operator()(const double (&s)[4]) const {
+    const double rr = s[0], bb = s[1], r2 = s[2], rho = s[3];
     sc->rr = rr; sc->bb = bb;
     if (!fin_ok(rr) || !fin_ok(bb)) sc->status = ST_NONFINITE;
     else if (bb == 0.0) sc->status = ST_BZERO;
     else if (sqrt(rr) <= sc->tol * sqrt(bb)) sc->status = ST_CONV;
     else sc->status = ST_RUN;
     if (inner) {
-      inner->bb = rho; inner->rr = rho; inner->rr0 = rho;
+      inner->bb = r2; inner->rr = r2; inner->rr0 = r2;
       inner->rho = rho; inner->rho_prev = 1.0; inner->alpha = 1.0; inner->omega = 1.0;
       inner->beta = 0.0; inner->first = 1; inner->restart = 0; inner->szero = 0;
       inner->x_zero = 1; inner->iter = 0; inner->diverged = 0;
-      inner->rr_min = rho; inner->it_min = 0;
+      inner->rr_min = r2; inner->it_min = 0;
       if (sc->status != ST_RUN) inner->status = ST_CONV;
-      else if (!fin_ok(rho)) inner->status = ST_NONFINITE;
-      else if (rho == 0.0) inner->status = ST_CONV;
-      else inner->status = ST_RUN;
+      else if (!fin_ok(r2) || !fin_ok(rho)) inner->status = ST_NONFINITE;
+      else if (r2 == 0.0) inner->status = ST_CONV;
+      else {
+        inner->status = ST_RUN;
+        if (rho == 0.0) inner->restart = 1;  // (r^, r0) = 0: breakdown at the start
+      }
     }
   }
 };
@@ -389,7 +392,7 @@ struct PhCgA {
 // scaled FP32 residual for the inner solve of iterative refinement).
 template <typename Tin>
 struct PhResid {
-  static constexpr int NV = 3;
+  static constexpr int NV = 4;
   static constexpr int PD = 1;
   using St = double;
   static __device__ __forceinline__ double val(double u) { return u; }
@@ -399,6 +402,7 @@ struct PhResid {
   float* __restrict__ rh32;
   double scale;
   int emit;
+  int hashed;      // inner shadow residual from the cell index (not stored)
   struct Raw { double x; };
   struct ERaw { double b; };
   WFA_PLAIN_OWN_STAGE
@@ -416,8 +420,11 @@ struct PhResid {
       // side is D^{-1} r
       const float r32v = (float)((emit == 2 ? rv / dg : rv) * scale);
       r32[i] = r32v;
-      rh32[i] = r32v;
+      float sh = r32v;
+      if (hashed) sh = hashed_shadow<float>(i);
+      else rh32[i] = r32v;
       acc[2] += (double)r32v * (double)r32v;
+      acc[3] += (double)sh * (double)r32v;
     }
   }
 };

@@ -81,6 +81,10 @@ struct Heap {
 
 enum Phase { Q_QUEUED, R_START, R_ITER, R_REFINE, R_FINAL, R_DONE };
 
+// Every served solve uses the index-hashed shadow residual (one vector
+// stream less per pass than storing r0), as a grid does with WFA_OPT_SHADOW.
+constexpr int kServerShadow = 1;
+
 struct Request {
   uint64_t ticket;
   int nx, ny, nz;
@@ -183,6 +187,7 @@ SolveDesc<T> make_desc(Request* r, T* x) {
   d.r = v[0]; d.rh = v[1]; d.t = v[2]; d.p0 = v[3]; d.p1 = v[4]; d.v0 = v[5]; d.v1 = v[6];
   d.r1 = v[8];
   d.par = r->par;
+  d.hashed = kServerShadow;
   d.partials = g.partials;
   d.sc = g.prec == WFA_F32_IR64 ? g.sc_in : g.sc;
   d.n = g.n;
@@ -208,7 +213,8 @@ int start_request(wfa_server* sv, Request* r) {
                      g.partials, g.sc, s};
     launch_rhs<double>(L, (const double*)r->T, g.b64);
     float** v = (float**)g.vec;
-    launch_residual<double>(L, (const double*)r->T, g.b64, v[0], v[1], g.sc_in, 2);
+    launch_residual<double>(L, (const double*)r->T, g.b64, v[0], v[1], g.sc_in, 2,
+                            kServerShadow);
   } else {
     Scalars h = fresh(r->tol, r->maxit);
     sv->h_sc[r->slot * kScalarsPerSlot] = h;
@@ -218,11 +224,13 @@ int start_request(wfa_server* sv, Request* r) {
       Launch<double> L{g.tl, g.op64, g.c.mode == WFA_COEF_CELL, (const float*)g.c.kappa,
                        g.partials, g.sc, s};
       double** v = (double**)g.vec;
+      L.shadow = kServerShadow;
       launch_init<double>(L, true, (double*)r->T, nullptr, v[7], v[0], v[1]);
     } else {
       Launch<float> L{g.tl, g.op32, g.c.mode == WFA_COEF_CELL, (const float*)g.c.kappa,
                       g.partials, g.sc, s};
       float** v = (float**)g.vec;
+      L.shadow = kServerShadow;
       launch_init<float>(L, true, (float*)r->T, nullptr, v[7], v[0], v[1]);
     }
   }
@@ -249,7 +257,7 @@ int refine_request(wfa_server* sv, Request* r, double scale_next, bool promote) 
   Launch<double> L{g.tl, g.op64, g.c.mode == WFA_COEF_CELL, (const float*)g.c.kappa,
                    g.partials, g.sc, s};
   float** v = (float**)g.vec;
-  launch_residual<double>(L, (const double*)r->T, g.b64, v[0], v[1], g.sc_in, 2);
+  launch_residual<double>(L, (const double*)r->T, g.b64, v[0], v[1], g.sc_in, 2, kServerShadow);
   r->par = 0;
   r->scale = scale_next;
   hipError_t e = hipGetLastError();
@@ -269,9 +277,11 @@ int final_residual(wfa_server* sv, Request* r) {
                    g.partials, g.sc_aux, s};
   void** v = g.vec;
   if (g.prec == WFA_F64)
-    launch_residual<double>(L, (const double*)r->T, (const double*)v[7], nullptr, nullptr, nullptr, 0);
+    launch_residual<double>(L, (const double*)r->T, (const double*)v[7], nullptr, nullptr, nullptr,
+                            0, 0);
   else
-    launch_residual<float>(L, (const float*)r->T, (const float*)v[7], nullptr, nullptr, nullptr, 0);
+    launch_residual<float>(L, (const float*)r->T, (const float*)v[7], nullptr, nullptr, nullptr,
+                           0, 0);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(sv, "final residual", e);
   r->phase = R_FINAL;
@@ -379,11 +389,13 @@ int advance(wfa_server* sv, Request* r) {
       Launch<double> L{g.tl, g.op64, g.c.mode == WFA_COEF_CELL, (const float*)g.c.kappa,
                        g.partials, g.sc, sv->stream};
       double** v = (double**)g.vec;
+      L.shadow = kServerShadow;
       launch_init<double>(L, false, (double*)r->T, v[7], nullptr, v[0], v[1]);
     } else {
       Launch<float> L{g.tl, g.op32, g.c.mode == WFA_COEF_CELL, (const float*)g.c.kappa,
                       g.partials, g.sc, sv->stream};
       float** v = (float**)g.vec;
+      L.shadow = kServerShadow;
       launch_init<float>(L, false, (float*)r->T, v[7], nullptr, v[0], v[1]);
     }
     return WFA_OK;

@@ -70,6 +70,7 @@ def test_server_matches_single_grid_path(wfa):
     for rq, s, info in zip(reqs, served, infos):
         prob = rq.problem()
         g = wfa.Grid.from_problem(prob, precision=wfa.F32_IR64)
+        g.set_option(wfa.OPT_SHADOW, 1)    # the server's shadow residual
         T = g.field(prob.T0)
         gi = g.timestep(T, 1, tol=1e-10, maxit=20000)[0]
         assert np.array_equal(T.cpu().numpy(), s)

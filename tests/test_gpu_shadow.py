@@ -96,3 +96,21 @@ def test_hashed_shadow_timestep_restart_and_fp32(wfa, oracle_mod):
     x2, _ = g2.solve(g2.field(b2), g2.field(p2.T0), tol=1e-300, maxit=5, method="bicgstab2",
                      check=False)
     assert rel_l2(to_np(x2), xo) <= FP32_TOL
+
+
+def test_hashed_shadow_inside_refinement(wfa, oracle_mod):
+    """FP32-in-FP64 refinement whose inner two-reduction solves use the
+    hashed shadow: same FP64 accuracy as with r^ = r0."""
+    prob = inputs.convdiff(n=40, seed=4, u=(4.0, 2.0, 1.0))
+    o = oracle_mod.Oracle(prob)
+    b = o.rhs(prob.T0)
+    xs = []
+    for shadow in (0, 1):
+        g = wfa.Grid.from_problem(prob, precision=wfa.F32_IR64)
+        g.set_option(wfa.OPT_SHADOW, shadow)
+        x, info = g.solve(g.field(b), g.field(prob.T0), tol=1e-12, maxit=5000)
+        assert info.status == wfa.OK, info
+        assert o.true_relres(b, to_np(x)) <= 1e-12
+        xs.append(to_np(x))
+    assert rel_l2(xs[1], xs[0]) <= 1e-9
+    assert not np.array_equal(xs[0], xs[1])          # the option took effect

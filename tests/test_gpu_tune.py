@@ -64,12 +64,14 @@ def test_server_uses_tuned_plane_depth(wfa, tmp_path):
     prob = rq.problem()
     g0 = wfa.Grid.from_problem(prob, precision=wfa.F64)
     g0.set_option(wfa.OPT_METHOD, wfa.METHOD_BICGSTAB2)   # the server's method
+    g0.set_option(wfa.OPT_SHADOW, 1)                      # and shadow residual
     ry = g0.tiling()[1] // 4
     path = tmp_path / "t.txt"
     path.write_text(f"64 40 36 {wfa.F64} 0 {ry} 3 1.0\n")
     wfa.tune_load(str(path))
     g = wfa.Grid.from_problem(prob, precision=wfa.F64)
     g.set_option(wfa.OPT_METHOD, wfa.METHOD_BICGSTAB2)
+    g.set_option(wfa.OPT_SHADOW, 1)
     assert g.tiling()[2] == 3 and g0.tiling()[2] != 3
     T = g.field(prob.T0)
     gi = g.timestep(T, 1, tol=1e-10, maxit=20000)[0]
