@@ -26,6 +26,9 @@ def wfa():
 def _solve(wfa, prob, precision, graph, method, check_every=0, tol=1e-10, maxit=2000, ry=0):
     g = wfa.Grid.from_problem(prob, precision=precision)
     g.set_option(wfa.OPT_GRAPH, graph)
+    if method == "bicgstab2_hashed":
+        method = "bicgstab2"
+        g.set_option(wfa.OPT_SHADOW, 1)
     g.set_option(wfa.OPT_CHECK_EVERY, check_every)
     if ry:
         g.set_option(wfa.OPT_RY, ry)
@@ -36,7 +39,8 @@ def _solve(wfa, prob, precision, graph, method, check_every=0, tol=1e-10, maxit=
 
 CASES = [
     ("bicgstab", "f64"), ("bicgstab", "f32"), ("bicgstab", "f32_ir64"),
-    ("bicgstab2", "f64"), ("bicgstab2", "f32"), ("cg", "f64"), ("cg", "f32"),
+    ("bicgstab2", "f64"), ("bicgstab2", "f32"), ("bicgstab2_hashed", "f64"),
+    ("bicgstab2_hashed", "f32_ir64"), ("cg", "f64"), ("cg", "f32"),
 ]
 
 
