@@ -9,6 +9,7 @@
 #include <string.h>
 
 #include <chrono>
+#include <functional>
 #include <initializer_list>
 #include <new>
 #include <vector>
@@ -211,6 +212,7 @@ extern "C" int wfa_grid_destroy(wfa_grid* g) {
   if (!g) return set_error(WFA_ERR_INVALID, "grid is NULL");
   g->prof.clear();
   g->graphs.clear();
+  g->rb.clear();
   delete g;
   return WFA_OK;
 }
@@ -452,17 +454,78 @@ static int check_launch(const char* what) {
   return WFA_OK;
 }
 
-// Host copy of a device scalar block.
-static int read_scalars(wfa_grid* g, const Scalars* dev, Scalars* host, hipStream_t s) {
-  HIP_TRY(hipMemcpyAsync(host, dev, sizeof(Scalars), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
+namespace wfa {
+
+int Readback::init() {
+  if (host) return WFA_OK;
+  Scalars* h = nullptr;
+  HIP_TRY(hipHostMalloc((void**)&h, kSlots * sizeof(Scalars), hipHostMallocDefault));
+  hipEvent_t e = nullptr;
+  const hipError_t ee = hipEventCreateWithFlags(&e, hipEventDisableTiming);
+  if (ee != hipSuccess) {
+    (void)hipHostFree(h);
+    return set_error(WFA_ERR_HIP, "readback event: %s", hipGetErrorString(ee));
+  }
+  host = h;
+  done = e;
+  return WFA_OK;
+}
+
+void Readback::clear() {
+  if (done) (void)hipEventDestroy(done);   // teardown: nothing to report a failure to
+  if (host) (void)hipHostFree(host);
+  done = nullptr;
+  host = nullptr;
+}
+
+}  // namespace wfa
+
+namespace wfa {
+
+// Polls the event for up to 2 ms (the common wait on small grids is tens of
+// microseconds), then blocks on it.
+hipError_t wait_event(hipEvent_t e) {
+  const auto t0 = std::chrono::steady_clock::now();
+  hipError_t q;
+  while ((q = hipEventQuery(e)) == hipErrorNotReady) {
+    if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(2)) {
+      q = hipEventSynchronize(e);
+      break;
+    }
+  }
+  // "not ready" is an answer, not a failure: leave no trace of it for the
+  // calling thread's next hipGetLastError
+  (void)hipGetLastError();
+  return q;
+}
+
+}  // namespace wfa
+
+static int wait_readback(wfa_grid* g) {
+  const hipError_t e = wait_event(g->rb.done);
+  if (e != hipSuccess) return set_error(WFA_ERR_HIP, "readback: %s", hipGetErrorString(e));
   if (g->profile) g->prof.drain();
   return WFA_OK;
 }
 
-static int write_scalars(const Scalars* host, Scalars* dev, hipStream_t s) {
-  HIP_TRY(hipMemcpyAsync(dev, host, sizeof(Scalars), hipMemcpyHostToDevice, s));
+// Host copies of one or two device scalar blocks, read together.
+static int read_scalars(wfa_grid* g, const Scalars* dev, Scalars* host, hipStream_t s,
+                        const Scalars* dev2 = nullptr, Scalars* host2 = nullptr) {
+  int rc = g->rb.init();
+  if (rc) return rc;
+  HIP_TRY(hipMemcpyAsync(g->rb.host, dev, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+  if (dev2)
+    HIP_TRY(hipMemcpyAsync(g->rb.host + 1, dev2, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipEventRecord(g->rb.done, s));
+  if ((rc = wait_readback(g))) return rc;
+  *host = g->rb.host[0];
+  if (dev2) *host2 = g->rb.host[1];
   return WFA_OK;
+}
+
+static int write_scalars(const Scalars* host, Scalars* dev, hipStream_t s) {
+  launch_set_scalars(dev, *host, s);
+  return check_launch("set scalars");
 }
 
 static int status_code(int dev_status) {
@@ -618,13 +681,41 @@ static void graph_key(uint64_t (&k)[GraphCache::kKey], const wfa_grid* g, const 
 // Runs iterations until the device status leaves ST_RUN.  A breakdown
 // restarts from the true residual b - A x when `restartable`; otherwise the
 // loop returns with h->restart set (the caller restarts at a higher level).
+//
+// The caller has queued the pass that initialised the scalar block, and h
+// holds the values it wrote there; the first chunk is queued behind that
+// pass without reading it back (if it ended the solve, every pass of the
+// chunk exits at its first instruction).  The same holds after a restart.
+// Each chunk's scalars are read back once, together with the optional
+// `tail`: a second scalar block, and a pass queued behind every chunk.
+
+// Queued behind every chunk of iterations and read back with it.
+struct ChunkTail {
+  std::function<void()> launch;  // may be empty
+  const Scalars* dev = nullptr;  // block read back with the solve's own
+  Scalars* host = nullptr;
+};
+
+static int read_chunk(wfa_grid* g, const Scalars* dev, Scalars* h, hipStream_t s,
+                      ChunkTail* tail) {
+  if (tail && tail->launch) {
+    tail->launch();
+    int rc = check_launch("tail");
+    if (rc) return rc;
+  }
+  return read_scalars(g, dev, h, s, tail ? tail->dev : nullptr, tail ? tail->host : nullptr);
+}
+
 template <typename T>
 static int iterate_bicgstab(wfa_grid* g, const Launch<T>& L, T* x, T* r, T* rh, T** p, T** v,
-                            T* t, const T* b, Scalars* h, int* restarts, bool restartable) {
+                            T* t, const T* b, Scalars* h, int* restarts, bool restartable,
+                            ChunkTail* tail) {
   int par = 0;
-  int rc = use_persistent(g, L.tl) ? reset_barrier(g, L.stream) : WFA_OK;
-  if (rc) return rc;
-  if ((rc = read_scalars(g, L.sc, h, L.stream))) return rc;
+  int rc = WFA_OK;
+  if (use_persistent(g, L.tl)) {
+    if ((rc = reset_barrier(g, L.stream))) return rc;
+    if ((rc = read_chunk(g, L.sc, h, L.stream, tail))) return rc;
+  }
   while (h->status == ST_RUN) {
     if (h->restart) {
       if (!restartable) return WFA_OK;
@@ -634,7 +725,8 @@ static int iterate_bicgstab(wfa_grid* g, const Launch<T>& L, T* x, T* r, T* rh, 
         launch_init<T>(L, false, x, b, nullptr, r, rh);
       }
       if ((rc = check_launch("init"))) return rc;
-      if ((rc = read_scalars(g, L.sc, h, L.stream))) return rc;
+      h->restart = 0;
+      if (use_persistent(g, L.tl) && (rc = read_chunk(g, L.sc, h, L.stream, tail))) return rc;
       continue;
     }
     const int m = next_chunk(g, *h, h->maxit - h->iter);
@@ -648,7 +740,7 @@ static int iterate_bicgstab(wfa_grid* g, const Launch<T>& L, T* x, T* r, T* rh, 
       if (e != hipSuccess)
         return set_error(WFA_ERR_HIP, "persistent launch: %s", hipGetErrorString(e));
       par ^= (m & 1);
-      if ((rc = read_scalars(g, L.sc, h, L.stream))) return rc;
+      if ((rc = read_chunk(g, L.sc, h, L.stream, tail))) return rc;
       if ((rc = check_barrier(g, L.stream))) return rc;
       continue;
     }
@@ -684,7 +776,7 @@ static int iterate_bicgstab(wfa_grid* g, const Launch<T>& L, T* x, T* r, T* rh, 
       par ^= 1;
     }
     if ((rc = check_launch("phase"))) return rc;
-    if ((rc = read_scalars(g, L.sc, h, L.stream))) return rc;
+    if ((rc = read_chunk(g, L.sc, h, L.stream, tail))) return rc;
   }
   return WFA_OK;
 }
@@ -694,10 +786,9 @@ static int iterate_bicgstab(wfa_grid* g, const Launch<T>& L, T* x, T* r, T* rh, 
 template <typename T>
 static int iterate_bicgstab2(wfa_grid* g, const Launch<T>& L, T* x, T** r, T* rh, T** p, T** v,
                              T* t, const T* b, Scalars* h, int* restarts, int* par_io,
-                             bool restartable) {
+                             bool restartable, ChunkTail* tail) {
   int par = *par_io;
-  int rc = read_scalars(g, L.sc, h, L.stream);
-  if (rc) return rc;
+  int rc = WFA_OK;
   while (h->status == ST_RUN) {
     if (h->restart) {
       if (!restartable) break;
@@ -707,7 +798,7 @@ static int iterate_bicgstab2(wfa_grid* g, const Launch<T>& L, T* x, T** r, T* rh
         launch_init<T>(L, false, x, b, nullptr, r[par], rh);
       }
       if ((rc = check_launch("init"))) return rc;
-      if ((rc = read_scalars(g, L.sc, h, L.stream))) return rc;
+      h->restart = 0;
       continue;
     }
     // maxit iterations take maxit + 1 first passes (the last applies the update)
@@ -740,17 +831,17 @@ static int iterate_bicgstab2(wfa_grid* g, const Launch<T>& L, T* x, T** r, T* rh
       par ^= 1;
     }
     if ((rc = check_launch("bicgstab2"))) return rc;
-    if ((rc = read_scalars(g, L.sc, h, L.stream))) return rc;
+    if ((rc = read_chunk(g, L.sc, h, L.stream, tail))) return rc;
   }
   *par_io = par;
   return WFA_OK;
 }
 
 template <typename T>
-static int iterate_cg(wfa_grid* g, const Launch<T>& L, T* x, T* r, T** d, T* q, Scalars* h) {
+static int iterate_cg(wfa_grid* g, const Launch<T>& L, T* x, T* r, T** d, T* q, Scalars* h,
+                      ChunkTail* tail) {
   int par = 0;
-  int rc = read_scalars(g, L.sc, h, L.stream);
-  if (rc) return rc;
+  int rc = WFA_OK;
   while (h->status == ST_RUN) {
     const int m = next_chunk(g, *h, h->maxit - h->iter);
     int k = 0;
@@ -780,7 +871,7 @@ static int iterate_cg(wfa_grid* g, const Launch<T>& L, T* x, T* r, T** d, T* q, 
       par ^= 1;
     }
     if ((rc = check_launch("cg"))) return rc;
-    if ((rc = read_scalars(g, L.sc, h, L.stream))) return rc;
+    if ((rc = read_chunk(g, L.sc, h, L.stream, tail))) return rc;
   }
   return WFA_OK;
 }
@@ -837,15 +928,32 @@ static int solve_plain(wfa_grid* g, const T* b_user, T* x, bool form_b, double t
     launch_init<T>(L, form_b, x, b_user, bw, r, rh);
   }
   if ((rc = check_launch("init"))) return rc;
+  // The true residual pass is queued behind every chunk and runs once the
+  // solve has converged or used its iterations, so the chunk that ends the
+  // solve also brings its true residual back.  (Not when profiling: there
+  // every launch that is timed is one that does its work.)
+  ChunkTail tail;
+  Scalars ha = fresh_scalars(1.0, 1, 0);
+  const bool use_tail = !g->profile;
+  const Launch<double> La = plain_ctx<double>(g, g->sc_aux, s);
+  if (use_tail) {
+    if ((rc = write_scalars(&ha, g->sc_aux, s))) return rc;
+    tail.launch = [&]() {
+      launch_residual<T>(La, x, b, nullptr, nullptr, nullptr, 0, 0, g->sc);
+    };
+    tail.dev = g->sc_aux;
+    tail.host = &ha;
+  }
   int restarts = 0;
   T* rbuf[2] = {r, vec[8]};
   int rpar = 0;
+  ChunkTail* tp = use_tail ? &tail : nullptr;
   if (g->method == WFA_METHOD_CG)
-    rc = iterate_cg<T>(g, L, x, r, p, t, &h);
+    rc = iterate_cg<T>(g, L, x, r, p, t, &h, tp);
   else if (g->method == WFA_METHOD_BICGSTAB2)
-    rc = iterate_bicgstab2<T>(g, L, x, rbuf, rh, p, v, t, b, &h, &restarts, &rpar, true);
+    rc = iterate_bicgstab2<T>(g, L, x, rbuf, rh, p, v, t, b, &h, &restarts, &rpar, true, tp);
   else
-    rc = iterate_bicgstab<T>(g, L, x, r, rh, p, v, t, b, &h, &restarts, true);
+    rc = iterate_bicgstab<T>(g, L, x, r, rh, p, v, t, b, &h, &restarts, true, tp);
   if (rc) return rc;
   int status;
   if (h.status == -1) status = WFA_ERR_BREAKDOWN;
@@ -855,10 +963,13 @@ static int solve_plain(wfa_grid* g, const T* b_user, T* x, bool form_b, double t
     if ((rc = check_launch("fill"))) return rc;
   }
   double rel_true = 0.0;
-  if (status != WFA_ERR_NONFINITE) {
-    if ((rc = true_residual<T>(g, b, x, &rel_true, s))) return rc;
-  } else {
+  if (status == WFA_ERR_NONFINITE) {
     rel_true = NAN;
+  } else if (use_tail && (h.status == ST_CONV || h.status == ST_NOCONV)) {
+    // the tail ran behind the chunk that ended the solve
+    rel_true = ha.bb > 0.0 ? sqrt(ha.rr / ha.bb) : sqrt(ha.rr);
+  } else {
+    if ((rc = true_residual<T>(g, b, x, &rel_true, s))) return rc;
   }
   if (status != WFA_OK)
     set_error(status, "solve ended with %s after %d iterations (%d restarts)",
@@ -938,7 +1049,25 @@ static int solve_ir(wfa_grid* g, const double* b_user, double* x, bool form_b, d
       launch_residual<double>(L64, x, b, r, rh, g->sc_in, 2, g->shadow);
     }
     if ((rc = check_launch("residual"))) return rc;
-    if ((rc = read_scalars(g, g->sc, &ho, s))) return rc;
+    const bool last = ref >= max_ref || total_it >= maxit;
+    int inner_restarts = 0, inner_par = 0;
+    if (last) {
+      if ((rc = read_scalars(g, g->sc, &ho, s))) return rc;
+    } else {
+      // inner FP32 solve of A d = r32 from d = 0 with the two-reduction
+      // BiCGStab (r32 sits in r[0]; an inner breakdown ends the inner solve
+      // and the next refinement restarts it from the FP64 true residual).
+      // Its first chunk is queued behind the residual pass, whose outer
+      // scalars come back with the chunk's: when the residual already meets
+      // the tolerance, the pass marks the inner solve converged and the
+      // chunk's passes exit at once.
+      ChunkTail outer;
+      outer.dev = g->sc;
+      outer.host = &ho;
+      if ((rc = iterate_bicgstab2<float>(g, L32, d, rbuf, rh, p, v, t, nullptr, &hi,
+                                         &inner_restarts, &inner_par, false, &outer)))
+        return rc;
+    }
     if (ho.status != ST_RUN) {
       status = status_code(ho.status);
       if (ho.status == ST_BZERO) {
@@ -947,14 +1076,7 @@ static int solve_ir(wfa_grid* g, const double* b_user, double* x, bool form_b, d
       }
       break;
     }
-    if (ref >= max_ref || total_it >= maxit) { status = WFA_ERR_NOCONV; break; }
-    // inner FP32 solve of A d = r32 from d = 0 with the two-reduction
-    // BiCGStab (r32 sits in r[0]; an inner breakdown ends the inner solve and
-    // the next refinement restarts it from the FP64 true residual)
-    int inner_restarts = 0, inner_par = 0;
-    if ((rc = iterate_bicgstab2<float>(g, L32, d, rbuf, rh, p, v, t, nullptr, &hi,
-                                       &inner_restarts, &inner_par, false)))
-      return rc;
+    if (last) { status = WFA_ERR_NOCONV; break; }
     if (hi.status == ST_RUN && hi.restart) ++restarts;
     if (restarts > WFA_MAX_RESTARTS) { status = WFA_ERR_BREAKDOWN; break; }
     total_it += hi.iter;

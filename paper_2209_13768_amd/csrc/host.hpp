@@ -56,6 +56,21 @@ struct GraphCache {
   void clear();
 };
 
+// Pinned host copies of device scalar blocks: the host reads a solve's
+// scalars with asynchronous copies into this block and one event, which it
+// polls (a wait of a few tens of microseconds is common on small grids, and
+// polling answers sooner than a blocking wait).
+struct Readback {
+  static constexpr int kSlots = 2;
+  Scalars* host = nullptr;   // kSlots blocks (hipHostMalloc)
+  hipEvent_t done = nullptr;
+  int init();                // 0 or a WFA_ERR_* code
+  void clear();
+};
+
+// Waits for `e` (polling first); clears the thread's last-error state.
+hipError_t wait_event(hipEvent_t e);
+
 int set_error(int code, const char* fmt, ...);
 int ir_inner_maxit(int maxit, int used);
 // The inner FP32 solve of iterative refinement stops as diverged once its
@@ -89,6 +104,7 @@ struct wfa_grid {
   int force_div;         // n > 0: the next IR solve's first inner solve diverges at n
   wfa::Profiler prof;
   wfa::GraphCache graphs;
+  wfa::Readback rb;
 };
 
 namespace wfa {

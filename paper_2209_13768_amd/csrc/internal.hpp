@@ -80,10 +80,15 @@ void launch_cg_b(const Launch<T>& L, T* x, const T* d, T* r, const T* q);
 // FP64 residual of Tin-typed x, b: (r,r), (b,b); optionally r32 = fp32(r *
 // scale) into r32, the inner shadow residual (r32 itself into rh32, or the
 // index-hashed field when `hashed`), and (r32, r32), (rh, r32) for the inner
-// solve (sc_inner).
+// solve (sc_inner).  With `after`, the pass runs only if the solve whose
+// scalars `after` points at has converged or reached its iteration limit
+// when the pass starts; otherwise it leaves everything untouched.
 template <typename Tin>
 void launch_residual(const Launch<double>& L, const Tin* x, const Tin* b, float* r32,
-                     float* rh32, Scalars* sc_inner, int mode, int hashed);
+                     float* rh32, Scalars* sc_inner, int mode, int hashed,
+                     const Scalars* after = nullptr);
+// *dst = v, stream-ordered, from a kernel argument (no host copy to wait on)
+void launch_set_scalars(Scalars* dst, const Scalars& v, hipStream_t s);
 // x64 += inv_scale * d32 (scalars of the inner solve)
 void launch_promote(size_t n, int blocks, double* x, const float* d, const Scalars* sc_inner,
                     hipStream_t s);

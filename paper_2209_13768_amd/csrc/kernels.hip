@@ -30,13 +30,18 @@ namespace wfa {
 template <typename T, bool CELL, int RY, class Ph, class Fin>
 __global__ void __launch_bounds__(kThreads)
 k_march(Geo g, Op<T> op, const float* __restrict__ kappa, Ph ph, double* partials,
-        Scalars* sc, Fin fin, int gated, int publish) {
+        Scalars* sc, Fin fin, const Scalars* gate, int gated, int publish) {
   static_assert(Ph::NV <= kMaxReduce, "the workspace holds kMaxReduce partials per tile");
   using TS = TileShape<RY>;
   __shared__ T su[2 * TS::LH * TS::LW];
   __shared__ float sk[CELL ? 2 * TS::LH * TS::LW : 1];
   __shared__ double red[kWaves * Ph::NV];
-  if (gated && (sc->status != ST_RUN || sc->restart)) return;
+  // gated 1: an iteration pass, skipped once its solve has stopped or awaits
+  // a restart; gated 2: a true-residual pass queued behind a chunk of
+  // iterations, run only once the solve `gate` has converged or reached its
+  // iteration limit
+  if (gated == 1 && (gate->status != ST_RUN || gate->restart)) return;
+  if (gated == 2 && gate->status != ST_CONV && gate->status != ST_NOCONV) return;
   ph.bind(sc);
   double acc[Ph::NV];
 #pragma unroll
@@ -47,13 +52,15 @@ k_march(Geo g, Op<T> op, const float* __restrict__ kappa, Ph ph, double* partial
 }
 
 template <typename T, class Ph, class Fin>
-void dispatch_march(const Launch<T>& L, const Ph& ph, const Fin& fin, bool gated, bool publish) {
+void dispatch_march(const Launch<T>& L, const Ph& ph, const Fin& fin, bool gated, bool publish,
+                    const Scalars* after = nullptr) {
   const Geo g = L.tl.geo;
   dim3 grid(g.ntiles), block(kThreads);
-  const int G = gated ? 1 : 0, P = publish ? 1 : 0;
+  const int G = after ? 2 : gated ? 1 : 0, P = publish ? 1 : 0;
+  const Scalars* gate = after ? after : L.sc;
 #define WFA_MARCH(CELLV, RYV)                                                              \
   hipLaunchKernelGGL((k_march<T, CELLV, RYV, Ph, Fin>), grid, block, 0, L.stream, g, L.op, \
-                     L.kappa, ph, L.partials, L.sc, fin, G, P)
+                     L.kappa, ph, L.partials, L.sc, fin, gate, G, P)
   if (L.cell) {
     switch (L.tl.ry) {
       case 1: WFA_MARCH(true, 1); break;
@@ -153,10 +160,20 @@ void launch_cg_a(const Launch<T>& L, const T* r, const T* d, T* d_out, T* q) {
 
 template <typename Tin>
 void launch_residual(const Launch<double>& L, const Tin* x, const Tin* b, float* r32,
-                     float* rh32, Scalars* sc_inner, int mode, int hashed) {
+                     float* rh32, Scalars* sc_inner, int mode, int hashed, const Scalars* after) {
   PhResid<Tin> ph{};
   ph.x = x; ph.b = b; ph.r32 = r32; ph.rh32 = rh32; ph.emit = mode; ph.hashed = hashed;
-  dispatch_march(L, ph, FinResid{L.sc, mode ? sc_inner : nullptr}, false, true);
+  dispatch_march(L, ph, FinResid{L.sc, mode ? sc_inner : nullptr}, false, true, after);
+}
+
+// The host's values arrive as a kernel argument, so setting a scalar block
+// never waits on a host copy.
+__global__ void __launch_bounds__(64) k_set_scalars(Scalars* __restrict__ dst, Scalars v) {
+  if (threadIdx.x == 0) *dst = v;
+}
+
+void launch_set_scalars(Scalars* dst, const Scalars& v, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_scalars, dim3(1), dim3(64), 0, s, dst, v);
 }
 
 // ============================================================================
@@ -331,8 +348,8 @@ WFA_INST(double)
 WFA_INST(float)
 #undef WFA_INST
 template void launch_residual<double>(const Launch<double>&, const double*, const double*,
-                                      float*, float*, Scalars*, int, int);
+                                      float*, float*, Scalars*, int, int, const Scalars*);
 template void launch_residual<float>(const Launch<double>&, const float*, const float*, float*,
-                                     float*, Scalars*, int, int);
+                                     float*, Scalars*, int, int, const Scalars*);
 
 }  // namespace wfa

@@ -1,0 +1,90 @@
+"""Host driver of the Krylov solves on the GPU.
+
+The true residual of a plain solve comes back with the chunk of iterations
+that ends it: a residual pass is queued behind every chunk and runs only once
+the solve has converged or used its iterations.  Here that figure must equal a
+separate true-residual computation bit for bit (same pass, same inputs), for
+a converged solve, one stopped by its iteration limit and one that converges
+at its initial residual.  A profiled grid takes the separate path; its
+iterates and reports must be identical.  Torch work after a solve must see
+no stale HIP error from the driver's polling.
+"""
+import numpy as np
+import pytest
+
+from paper_2209_13768_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def wfa():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2209_13768_amd import wfa as w
+    w.lib()
+    return w
+
+
+CASES = [(m, p) for m in ("bicgstab", "bicgstab2", "cg") for p in ("f64", "f32")]
+
+
+def _solve(wfa, prob, prec, method, tol, maxit, profile):
+    g = wfa.Grid.from_problem(prob, precision=prec)
+    if profile:
+        g.set_option(wfa.OPT_PROFILE, 1)
+    b = g.rhs(g.field(prob.T0))
+    x, info = g.solve(b, g.field(prob.T0), tol=tol, maxit=maxit, method=method, check=False)
+    return g, b, x, info
+
+
+@pytest.mark.parametrize("method,precision", CASES, ids=[f"{m}-{p}" for m, p in CASES])
+def test_residual_with_last_chunk_equals_separate_pass(wfa, method, precision):
+    import torch
+    u = (0.0, 0.0, 0.0) if method == "cg" else (1.0, -0.5, 0.25)
+    prob = inputs.random_problem(151, 40, 33, 21, cell=True, u=u, bc_kind=inputs.MIXED_BC_KIND)
+    prec = wfa.PRECISIONS[precision]
+    tol = 1e-5 if precision == "f32" else 1e-10
+    for tol, maxit, status, iters in ((tol, 5000, wfa.OK, None), (1e-300, 7, wfa.ERR_NOCONV, 7),
+                                      (10.0, 100, wfa.OK, 0)):
+        g, b, x, info = _solve(wfa, prob, prec, method, tol, maxit, False)
+        assert info.status == status, (tol, info)
+        if iters is not None:
+            assert info.iterations == iters
+        assert info.rel_res_true == g.true_residual(b, x)
+        y = (x * 2).sum()               # torch work right after the solve
+        torch.cuda.synchronize()
+        assert torch.isfinite(y)
+        _, _, xp, ip = _solve(wfa, prob, prec, method, tol, maxit, True)
+        assert np.array_equal(xp.cpu().numpy(), x.cpu().numpy())
+        assert (ip.status, ip.iterations, ip.restarts) == (info.status, info.iterations, info.restarts)
+        assert ip.rel_res_true == info.rel_res_true
+        assert ip.rel_res_recursive == info.rel_res_recursive
+
+
+def test_restarts_and_refinement_unchanged_by_profiling(wfa):
+    """A forced breakdown (restart queued without a readback) and FP32-in-FP64
+    refinement (outer scalars read back with the inner chunks): identical
+    with and without the profiled path."""
+    prob = inputs.convdiff(n=36, seed=12)
+    out = []
+    for profile in (0, 1):
+        g = wfa.Grid.from_problem(prob, precision=wfa.F64)
+        g.set_option(wfa.OPT_PROFILE, profile)
+        g.set_option(wfa.OPT_FORCE_BREAKDOWN, 4)
+        b = g.rhs(g.field(prob.T0))
+        x, info = g.solve(b, g.field(prob.T0), tol=1e-10, maxit=5000, method="bicgstab2")
+        assert info.status == wfa.OK and info.restarts == 1
+        gi = wfa.Grid.from_problem(prob, precision=wfa.F32_IR64)
+        gi.set_option(wfa.OPT_PROFILE, profile)
+        bi = gi.rhs(gi.field(prob.T0))
+        xi, ii = gi.solve(bi, gi.field(prob.T0), tol=1e-12, maxit=5000)
+        assert ii.status == wfa.OK and ii.refinements >= 2
+        assert gi.true_residual(bi, xi) <= 1e-12
+        out.append((x.cpu().numpy(), info.iterations, info.rel_res_true, xi.cpu().numpy(),
+                    ii.iterations, ii.refinements, ii.rel_res_true))
+    for a, c in zip(out[0], out[1]):
+        if isinstance(a, np.ndarray):
+            assert np.array_equal(a, c)
+        else:
+            assert a == c
