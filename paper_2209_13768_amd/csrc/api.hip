@@ -164,6 +164,7 @@ void grid_setup(wfa_grid* g, int nx, int ny, int nz, const wfa_coeffs* c, char* 
   g->zchunk = 0;
   g->ir_inner_tol = 1e-4;
   g->force_div = 0;
+  g->hint_iters = 0;
   const int w = g->prec == WFA_F32 ? 4 : 8;
   g->ry = 0;
   g->jacobi = 0;
@@ -539,11 +540,16 @@ static int status_code(int dev_status) {
 }
 
 // Iterations to launch before the next host check: an estimate of what
-// remains from the residual history, bounded by the iteration budget.
-static int next_chunk(const wfa_grid* g, const Scalars& h, int budget) {
+// remains from the residual history, bounded by the iteration budget.  The
+// first chunk of a solve takes `hint` iterations when given (the count the
+// grid's previous solve of the same kind converged in: successive time steps
+// and refinements take similar counts, so most solves end in one chunk).
+static int next_chunk(const wfa_grid* g, const Scalars& h, int budget, int hint) {
   int m;
   if (g->check_every > 0) {
     m = g->check_every;
+  } else if (h.iter == 0 && hint > 0) {
+    m = hint;
   } else if (h.iter == 0 || !(h.rr > 0.0) || !(h.rr0 > 0.0) || h.rr >= h.rr0) {
     m = 8;
   } else {
@@ -709,7 +715,7 @@ static int read_chunk(wfa_grid* g, const Scalars* dev, Scalars* h, hipStream_t s
 template <typename T>
 static int iterate_bicgstab(wfa_grid* g, const Launch<T>& L, T* x, T* r, T* rh, T** p, T** v,
                             T* t, const T* b, Scalars* h, int* restarts, bool restartable,
-                            ChunkTail* tail) {
+                            ChunkTail* tail, int hint) {
   int par = 0;
   int rc = WFA_OK;
   if (use_persistent(g, L.tl)) {
@@ -729,7 +735,7 @@ static int iterate_bicgstab(wfa_grid* g, const Launch<T>& L, T* x, T* r, T* rh, 
       if (use_persistent(g, L.tl) && (rc = read_chunk(g, L.sc, h, L.stream, tail))) return rc;
       continue;
     }
-    const int m = next_chunk(g, *h, h->maxit - h->iter);
+    const int m = next_chunk(g, *h, h->maxit - h->iter, hint);
     if (use_persistent(g, L.tl)) {
       hipError_t e;
       {
@@ -786,7 +792,7 @@ static int iterate_bicgstab(wfa_grid* g, const Launch<T>& L, T* x, T* r, T* rh, 
 template <typename T>
 static int iterate_bicgstab2(wfa_grid* g, const Launch<T>& L, T* x, T** r, T* rh, T** p, T** v,
                              T* t, const T* b, Scalars* h, int* restarts, int* par_io,
-                             bool restartable, ChunkTail* tail) {
+                             bool restartable, ChunkTail* tail, int hint) {
   int par = *par_io;
   int rc = WFA_OK;
   while (h->status == ST_RUN) {
@@ -802,7 +808,7 @@ static int iterate_bicgstab2(wfa_grid* g, const Launch<T>& L, T* x, T** r, T* rh
       continue;
     }
     // maxit iterations take maxit + 1 first passes (the last applies the update)
-    const int m = next_chunk(g, *h, h->maxit - h->iter + 1);
+    const int m = next_chunk(g, *h, h->maxit - h->iter + 1, hint);
     int q = 0;
     if (use_graph(g) && m >= kGraphIters) {
       uint64_t key[GraphCache::kKey];
@@ -839,11 +845,11 @@ static int iterate_bicgstab2(wfa_grid* g, const Launch<T>& L, T* x, T** r, T* rh
 
 template <typename T>
 static int iterate_cg(wfa_grid* g, const Launch<T>& L, T* x, T* r, T** d, T* q, Scalars* h,
-                      ChunkTail* tail) {
+                      ChunkTail* tail, int hint) {
   int par = 0;
   int rc = WFA_OK;
   while (h->status == ST_RUN) {
-    const int m = next_chunk(g, *h, h->maxit - h->iter);
+    const int m = next_chunk(g, *h, h->maxit - h->iter, hint);
     int k = 0;
     if (use_graph(g) && m >= kGraphIters) {
       uint64_t key[GraphCache::kKey];
@@ -948,13 +954,15 @@ static int solve_plain(wfa_grid* g, const T* b_user, T* x, bool form_b, double t
   T* rbuf[2] = {r, vec[8]};
   int rpar = 0;
   ChunkTail* tp = use_tail ? &tail : nullptr;
+  const int hint = g->hint_iters;
   if (g->method == WFA_METHOD_CG)
-    rc = iterate_cg<T>(g, L, x, r, p, t, &h, tp);
+    rc = iterate_cg<T>(g, L, x, r, p, t, &h, tp, hint);
   else if (g->method == WFA_METHOD_BICGSTAB2)
-    rc = iterate_bicgstab2<T>(g, L, x, rbuf, rh, p, v, t, b, &h, &restarts, &rpar, true, tp);
+    rc = iterate_bicgstab2<T>(g, L, x, rbuf, rh, p, v, t, b, &h, &restarts, &rpar, true, tp, hint);
   else
-    rc = iterate_bicgstab<T>(g, L, x, r, rh, p, v, t, b, &h, &restarts, true, tp);
+    rc = iterate_bicgstab<T>(g, L, x, r, rh, p, v, t, b, &h, &restarts, true, tp, hint);
   if (rc) return rc;
+  g->hint_iters = h.status == ST_CONV && restarts == 0 ? h.iter : 0;
   int status;
   if (h.status == -1) status = WFA_ERR_BREAKDOWN;
   else status = status_code(h.status);
@@ -1028,6 +1036,7 @@ static int solve_ir(wfa_grid* g, const double* b_user, double* x, bool form_b, d
   g->force_bd = 0;
   const int force_div = g->force_div;
   g->force_div = 0;
+  g->hint_iters = 0;
   // > 0: this refinement repeats one whose inner solve diverged, stopping it
   // at the iteration that had reached its smallest residual (the kernels are
   // deterministic, so the repeat retraces the same iterates)
@@ -1065,8 +1074,10 @@ static int solve_ir(wfa_grid* g, const double* b_user, double* x, bool form_b, d
       outer.dev = g->sc;
       outer.host = &ho;
       if ((rc = iterate_bicgstab2<float>(g, L32, d, rbuf, rh, p, v, t, nullptr, &hi,
-                                         &inner_restarts, &inner_par, false, &outer)))
+                                         &inner_restarts, &inner_par, false, &outer,
+                                         g->hint_iters)))
         return rc;
+      g->hint_iters = hi.status == ST_CONV && !hi.restart && hi.iter > 0 ? hi.iter : 0;
     }
     if (ho.status != ST_RUN) {
       status = status_code(ho.status);

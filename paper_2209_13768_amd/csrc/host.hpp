@@ -102,6 +102,7 @@ struct wfa_grid {
   int shadow;  // two-reduction BiCGStab: 0 r^ = r0 (stored), 1 index-hashed r^
   double ir_inner_tol;
   int force_div;         // n > 0: the next IR solve's first inner solve diverges at n
+  int hint_iters;        // iterations of the last converged (inner) solve: first chunk size
   wfa::Profiler prof;
   wfa::GraphCache graphs;
   wfa::Readback rb;

@@ -120,11 +120,15 @@ struct wfa_server {
   int* bases;                // 4 * (max_slots + 1)
   size_t heap_base;
   Heap heap;
-  // host mirrors
-  std::vector<Scalars> h_sc;
-  std::vector<SolveDesc<float>> h_d32;
-  std::vector<SolveDesc<double>> h_d64;
-  std::vector<int> h_bases;
+  // host mirrors, in one pinned block: the tables are uploaded and the slot
+  // scalars read back with asynchronous copies (the host rewrites a table
+  // only after the round that uploaded it has been waited for)
+  void* pinned = nullptr;
+  Scalars* h_sc = nullptr;          // max_slots * kScalarsPerSlot
+  SolveDesc<float>* h_d32 = nullptr;
+  SolveDesc<double>* h_d64 = nullptr;
+  int* h_bases = nullptr;           // 4 * (max_slots + 1)
+  hipEvent_t round_done = nullptr;  // the round's scalar readback
   // requests
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
@@ -156,9 +160,16 @@ int fail(wfa_server* sv, const char* what, hipError_t e) {
   return WFA_ERR_HIP;
 }
 
-// Host-to-device copy of scalar blocks; remembers the first failure.
+// Host-to-device copy of a table; remembers the first failure.
 int put(wfa_server* sv, void* dst, const void* src, size_t bytes) {
   const hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, sv->stream);
+  return e == hipSuccess ? WFA_OK : fail(sv, "table upload", e);
+}
+
+// Sets `count` consecutive device scalar blocks from kernel arguments.
+int put_scalars(wfa_server* sv, Scalars* dst, const Scalars* h, int count) {
+  for (int k = 0; k < count; ++k) launch_set_scalars(dst + k, h[k], sv->stream);
+  const hipError_t e = hipGetLastError();
   return e == hipSuccess ? WFA_OK : fail(sv, "scalar upload", e);
 }
 
@@ -203,12 +214,9 @@ int start_request(wfa_server* sv, Request* r) {
   hipStream_t s = sv->stream;
   r->par = 0;  // the first residual goes to the parity-0 buffer
   if (g.prec == WFA_F32_IR64) {
-    Scalars ho = fresh(r->tol, r->maxit), hi = fresh(1e-4, ir_inner_maxit(r->maxit, 0));
-    hi.guard = kIrGuard;
-    sv->h_sc[r->slot * kScalarsPerSlot + 0] = ho;
-    sv->h_sc[r->slot * kScalarsPerSlot + 1] = hi;
-    if (int rc = put(sv, g.sc, &sv->h_sc[r->slot * kScalarsPerSlot], 2 * sizeof(Scalars)))
-      return rc;
+    Scalars h2[2] = {fresh(r->tol, r->maxit), fresh(1e-4, ir_inner_maxit(r->maxit, 0))};
+    h2[1].guard = kIrGuard;
+    if (int rc = put_scalars(sv, g.sc, h2, 2)) return rc;
     Launch<double> L{g.tl, g.op64, g.c.mode == WFA_COEF_CELL, (const float*)g.c.kappa,
                      g.partials, g.sc, s};
     launch_rhs<double>(L, (const double*)r->T, g.b64);
@@ -216,10 +224,8 @@ int start_request(wfa_server* sv, Request* r) {
     launch_residual<double>(L, (const double*)r->T, g.b64, v[0], v[1], g.sc_in, 2,
                             kServerShadow);
   } else {
-    Scalars h = fresh(r->tol, r->maxit);
-    sv->h_sc[r->slot * kScalarsPerSlot] = h;
-    if (int rc = put(sv, g.sc, &sv->h_sc[r->slot * kScalarsPerSlot], sizeof(Scalars)))
-      return rc;
+    const Scalars h = fresh(r->tol, r->maxit);
+    if (int rc = put_scalars(sv, g.sc, &h, 1)) return rc;
     if (g.prec == WFA_F64) {
       Launch<double> L{g.tl, g.op64, g.c.mode == WFA_COEF_CELL, (const float*)g.c.kappa,
                        g.partials, g.sc, s};
@@ -245,15 +251,14 @@ int refine_request(wfa_server* sv, Request* r, double scale_next, bool promote) 
   wfa_grid& g = r->g;
   hipStream_t s = sv->stream;
   if (promote) launch_promote(g.n, g.tl.pw_blocks, (double*)r->T, g.d32, g.sc_in, s);
-  Scalars ho = fresh(r->tol, r->maxit);
+  Scalars h2[2] = {fresh(r->tol, r->maxit),
+                   fresh(1e-4, r->inner_cap > 0 ? r->inner_cap : ir_inner_maxit(r->maxit, r->total_it))};
+  Scalars& ho = h2[0];
+  Scalars& hi = h2[1];
   ho.scale = scale_next; ho.inv_scale = 1.0 / scale_next;
-  Scalars hi = fresh(1e-4, r->inner_cap > 0 ? r->inner_cap : ir_inner_maxit(r->maxit, r->total_it));
   hi.scale = scale_next; hi.inv_scale = 1.0 / scale_next;
   hi.guard = r->inner_cap > 0 ? 0.0 : kIrGuard;
-  sv->h_sc[r->slot * kScalarsPerSlot + 0] = ho;
-  sv->h_sc[r->slot * kScalarsPerSlot + 1] = hi;
-  if (int rc = put(sv, g.sc, &sv->h_sc[r->slot * kScalarsPerSlot], 2 * sizeof(Scalars)))
-    return rc;
+  if (int rc = put_scalars(sv, g.sc, h2, 2)) return rc;
   Launch<double> L{g.tl, g.op64, g.c.mode == WFA_COEF_CELL, (const float*)g.c.kappa,
                    g.partials, g.sc, s};
   float** v = (float**)g.vec;
@@ -270,9 +275,8 @@ int refine_request(wfa_server* sv, Request* r, double scale_next, bool promote) 
 int final_residual(wfa_server* sv, Request* r) {
   wfa_grid& g = r->g;
   hipStream_t s = sv->stream;
-  sv->h_sc[r->slot * kScalarsPerSlot + 2] = fresh(1.0, 1);
-  if (int rc = put(sv, g.sc_aux, &sv->h_sc[r->slot * kScalarsPerSlot + 2], sizeof(Scalars)))
-    return rc;
+  const Scalars ha = fresh(1.0, 1);
+  if (int rc = put_scalars(sv, g.sc_aux, &ha, 1)) return rc;
   Launch<double> L{g.tl, g.op64, g.c.mode == WFA_COEF_CELL, (const float*)g.c.kappa,
                    g.partials, g.sc_aux, s};
   void** v = g.vec;
@@ -499,9 +503,9 @@ void worker_main(wfa_server* sv) {
     }
     if (!rc) {
       const int S = sv->max_slots;
-      rc = put(sv, sv->d32, sv->h_d32.data(), sizeof(SolveDesc<float>) * std::max(n32, 1));
-      if (!rc) rc = put(sv, sv->d64, sv->h_d64.data(), sizeof(SolveDesc<double>) * std::max(n64, 1));
-      if (!rc) rc = put(sv, sv->bases, sv->h_bases.data(), sizeof(int) * 4 * (S + 1));
+      rc = put(sv, sv->d32, sv->h_d32, sizeof(SolveDesc<float>) * std::max(n32, 1));
+      if (!rc) rc = put(sv, sv->d64, sv->h_d64, sizeof(SolveDesc<double>) * std::max(n64, 1));
+      if (!rc) rc = put(sv, sv->bases, sv->h_bases, sizeof(int) * 4 * (S + 1));
     }
     if (!rc) {
       const int S = sv->max_slots;
@@ -519,10 +523,11 @@ void worker_main(wfa_server* sv) {
       if (e != hipSuccess) rc = fail(sv, "batched iteration", e);
     }
     if (!rc) {
-      hipError_t e = hipMemcpyAsync(sv->h_sc.data(), sv->slot_sc,
+      hipError_t e = hipMemcpyAsync(sv->h_sc, sv->slot_sc,
                                     sizeof(Scalars) * kScalarsPerSlot * sv->max_slots,
                                     hipMemcpyDeviceToHost, sv->stream);
-      if (e == hipSuccess) e = hipStreamSynchronize(sv->stream);
+      if (e == hipSuccess) e = hipEventRecord(sv->round_done, sv->stream);
+      if (e == hipSuccess) e = wait_event(sv->round_done);
       if (e != hipSuccess) rc = fail(sv, "scalar readback", e);
     }
     std::unique_lock<std::mutex> lk(sv->mu);
@@ -572,10 +577,22 @@ extern "C" int wfa_server_create(void* arena, size_t arena_bytes, int max_slots,
   sv->bases = (int*)(sv->arena + sc_bytes + d32_bytes + d64_bytes);
   sv->heap_base = meta;
   sv->heap.init(arena_bytes - meta);
-  sv->h_sc.assign((size_t)kScalarsPerSlot * max_slots, Scalars{});
-  sv->h_d32.assign(max_slots, SolveDesc<float>{});
-  sv->h_d64.assign(max_slots, SolveDesc<double>{});
-  sv->h_bases.assign(4 * (max_slots + 1), 0);
+  {
+    const size_t hb = sc_bytes + d32_bytes + d64_bytes + b_bytes;  // same carving as the arena
+    hipError_t e = hipHostMalloc(&sv->pinned, hb, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&sv->round_done, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      if (sv->pinned) (void)hipHostFree(sv->pinned);
+      delete sv;
+      return set_error(WFA_ERR_HIP, "server host tables: %s", hipGetErrorString(e));
+    }
+    char* h = (char*)sv->pinned;
+    memset(h, 0, hb);
+    sv->h_sc = (Scalars*)h;
+    sv->h_d32 = (SolveDesc<float>*)(h + sc_bytes);
+    sv->h_d64 = (SolveDesc<double>*)(h + sc_bytes + d32_bytes);
+    sv->h_bases = (int*)(h + sc_bytes + d32_bytes + d64_bytes);
+  }
   sv->slots.assign(max_slots, nullptr);
   if (const char* c = getenv("WFA_SERVER_CHUNK")) {
     const int v = atoi(c);
@@ -584,6 +601,8 @@ extern "C" int wfa_server_create(void* arena, size_t arena_bytes, int max_slots,
   try {
     sv->worker = std::thread(worker_main, sv);
   } catch (...) {
+    (void)hipEventDestroy(sv->round_done);
+    (void)hipHostFree(sv->pinned);
     delete sv;
     return set_error(WFA_ERR_NOMEM, "could not start the server thread");
   }
@@ -657,6 +676,8 @@ extern "C" int wfa_server_destroy(wfa_server* sv) {
   sv->cv_work.notify_all();
   if (sv->worker.joinable()) sv->worker.join();
   for (auto& kv : sv->reqs) delete kv.second;
+  (void)hipEventDestroy(sv->round_done);  // teardown: nothing to report a failure to
+  (void)hipHostFree(sv->pinned);
   delete sv;
   return WFA_OK;
 }
