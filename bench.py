@@ -97,8 +97,10 @@ def kernel_label(name: str):
 
 
 def counter_means(csv_path: str, counter: str):
-    """Mean value of `counter` per dispatch, by kernel label, from a
-    rocprofv3 --pmc counter_collection.csv."""
+    """Mean value of `counter` per working dispatch, by kernel label, from a
+    rocprofv3 --pmc counter_collection.csv.  An iteration pass queued past
+    convergence exits at its first instruction; its dispatches (under a
+    fifth of the kernel's 90th-percentile value) are left out."""
     import csv
     per = {}
     with open(csv_path) as f:
@@ -111,7 +113,13 @@ def counter_means(csv_path: str, counter: str):
             d = per.setdefault(label, {})
             did = row["Dispatch_Id"]
             d[did] = d.get(did, 0.0) + float(row["Counter_Value"])
-    return {k: (sum(v.values()) / len(v), len(v)) for k, v in per.items()}
+    out = {}
+    for k, v in per.items():
+        vals = sorted(v.values())
+        cut = 0.2 * vals[int(0.9 * (len(vals) - 1))]
+        w = [x for x in vals if x >= cut]
+        out[k] = (sum(w) / len(w), len(w))
+    return out
 
 
 def summarize_counters(fetch_csv: str, write_csv: str, workload: str, commands: list):
@@ -146,23 +154,48 @@ def summarize_counters(fetch_csv: str, write_csv: str, workload: str, commands: 
 
 
 def summarize_trace(stats_csv: str, title: str, command: str) -> str:
-    """Markdown table of a rocprofv3 --kernel-trace --stats kernel_stats.csv."""
+    """Markdown table of a rocprofv3 --kernel-trace --stats kernel_stats.csv.
+    With the run's kernel_trace.csv beside it, also the calls and average of
+    the working launches: an iteration pass queued past convergence exits at
+    its first instruction, and such launches (under a fifth of the kernel's
+    90th-percentile duration) are left out of those two columns."""
     import csv
     import re
+    trace_csv = stats_csv.replace("kernel_stats", "kernel_trace")
+    durs = {}
+    if trace_csv != stats_csv and os.path.exists(trace_csv):
+        with open(trace_csv) as f:
+            for r in csv.DictReader(f):
+                durs.setdefault(r["Kernel_Name"], []).append(
+                    (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    head = "| kernel | calls | total (us) | average (us) | % |"
+    rule = "|---|---:|---:|---:|---:|"
+    if durs:
+        head += " working calls | working average (us) |"
+        rule += "---:|---:|"
     lines = [f"# {title}", "", "Command (run from the repository root on one MI355X):", "",
              "```", command, "```", "",
              f"Kernel sources hash (bench.kernel_source_hash): `{kernel_source_hash()}`; "
              f"library sources hash (bench.library_source_hash): `{library_source_hash()}`", "",
-             "| kernel | calls | total (us) | average (us) | % |", "|---|---:|---:|---:|---:|"]
+             head, rule]
     with open(stats_csv) as f:
         for r in csv.DictReader(f):
             if float(r["Percentage"]) < 0.01:
                 continue
-            name = re.sub(r"wfa::", "", r["Name"])
+            name = re.sub(r"wfa::|\(anonymous namespace\)::", "", r["Name"])
             m = re.match(r"void (\w+)<([^(]*)>\(", name)
-            name = f"{m.group(1)}<{m.group(2)}>" if m else name.split("(")[0][:80]
-            lines.append(f"| `{name}` | {int(r['Calls'])} | {float(r['TotalDurationNs']) / 1e3:.1f} | "
-                         f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} |")
+            short = f"{m.group(1)}<{m.group(2)}>" if m else name.split("(")[0][:80]
+            row = (f"| `{short}` | {int(r['Calls'])} | {float(r['TotalDurationNs']) / 1e3:.1f} | "
+                   f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} |")
+            if durs:
+                d = durs.get(r["Name"], []) if "wfa::" in r["Name"] else []
+                if d:
+                    cut = 0.2 * sorted(d)[int(0.9 * (len(d) - 1))]
+                    w = [x for x in d if x >= cut]
+                    row += f" {len(w)} | {sum(w) / len(w):.2f} |"
+                else:
+                    row += " | |"
+            lines.append(row)
     return "\n".join(lines) + "\n"
 
 
@@ -241,10 +274,19 @@ def run_convdiff(args, torch, inputs, wfa):
         g.set_option(wfa.OPT_PROFILE, 1)
         for k in range(wfa.K_COUNT):
             g.kernel_stats(k, reset=True)
-        for _ in range(args.steps):
-            g.timestep(T, 1, tol=args.tol, maxit=args.maxit, check=False)
+        # the repeat retraces the timed steps (same field, deterministic
+        # kernels), so each step's iteration count is known: one chunk of
+        # exactly that many iterations per step leaves no pass that exits at
+        # once after convergence to dilute the per-launch averages (only the
+        # converged iteration's second pass)
+        pinfos = []
+        for k in range(args.steps):
+            g.set_option(wfa.OPT_CHECK_EVERY, infos[k].iterations + 1)
+            pinfos += g.timestep(T, 1, tol=args.tol, maxit=args.maxit, check=False)
+        g.set_option(wfa.OPT_CHECK_EVERY, 0)
         torch.cuda.synchronize()
         g.set_option(wfa.OPT_PROFILE, 0)
+        retraced = [i.iterations for i in pinfos] == [i.iterations for i in infos]
         for k, name in enumerate(wfa.KERNEL_NAMES):
             n, ms, by = g.kernel_stats(k)
             if n:
@@ -259,7 +301,9 @@ def run_convdiff(args, torch, inputs, wfa):
                     "frac": round(achieved / HBM_PEAK_GBPS, 4),
                     "traffic": load_traffic(dom),
                     "measured": "HIP events around every launch on the solve stream, over "
-                                "the timed steps repeated from the same initial field"}
+                                "the timed steps repeated from the same initial field, one "
+                                "chunk of the step's iteration count per step",
+                    "repeat_matches_timed_iterations": retraced}
     w = 4 if prec == wfa.F32 else 8
     streams = streams_of(args)
     alg_bytes_iter = (streams * w + 2 * 4) * prob.cells   # vector streams + 2 kappa reads
@@ -294,13 +338,17 @@ def run_convdiff(args, torch, inputs, wfa):
     if args.compare:
         # the other organisations on the same steps, for comparison (plain
         # launches, wall clock around the synchronised steps)
-        others = [("bicgstab2", "r0"), ("bicgstab", "r0")]
+        # organisations, and the Jacobi-scaled form of the benchmark's one:
+        # the same cost per iteration, far fewer iterations on this
+        # diffusivity field (time to solution, not the iteration rate)
+        others = [("bicgstab2", "r0", 0), ("bicgstab", "r0", 0), ("bicgstab2", "hashed", 1)]
         line["compare"] = {}
-        for method, shadow in others:
-            if (method, shadow) == (args.method, args.shadow if args.method == "bicgstab2" else "r0"):
+        for method, shadow, jac in others:
+            if (method, shadow, jac) == (args.method, args.shadow if args.method == "bicgstab2" else "r0", 0):
                 continue
             g.set_option(wfa.OPT_METHOD, METHODS[method])
             g.set_option(wfa.OPT_SHADOW, 1 if shadow == "hashed" else 0)
+            g.set_option(wfa.OPT_JACOBI, jac)
             T.copy_(T0)
             for _ in range(args.warmup):
                 g.timestep(T, 1, tol=args.tol, maxit=args.maxit, check=False)
@@ -314,10 +362,12 @@ def run_convdiff(args, torch, inputs, wfa):
             tdt = time.perf_counter() - t0
             tit = sum(i.iterations for i in tinfos)
             streams = STREAMS[method] - (2 if (method, shadow) == ("bicgstab2", "hashed") else 0)
-            line["compare"][f"{method}_{shadow}"] = {
+            line["compare"][f"{method}_{shadow}" + ("_jacobi" if jac else "")] = {
                 "value": prob.cells * tit / tdt, "ms_per_step": tdt / args.steps * 1e3,
                 "iterations_per_step": tit / args.steps,
-                "alg_bytes_per_cell_iter": streams * w + 8}
+                "alg_bytes_per_cell_iter": streams * w + 8,
+                "rel_res_true_max": max(i.rel_res_true for i in tinfos)}
+        g.set_option(wfa.OPT_JACOBI, 0)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(prob, args.cpu_iters)
     return line
@@ -458,6 +508,7 @@ def run_serve(args, torch, inputs, wfa):
     """Poisson request stream (200/s) of heat-step solves on grids with dims
     in {32,...,192}, FP32 inside FP64 refinement to 1e-10."""
     reqs = inputs.request_stream(count=args.requests)
+    prec = wfa.PRECISIONS[args.serve_precision]
     fields = []
     for rq in reqs:       # inputs resident in HBM before the clock starts
         fields.append(torch.from_numpy(rq.problem().T0).to("cuda"))
@@ -470,22 +521,24 @@ def run_serve(args, torch, inputs, wfa):
         if rq.arrival > now:
             time.sleep(rq.arrival - now)
         h = 1.0 / (max(rq.nx, rq.ny, rq.nz) + 1)
-        tickets[q] = (sv.submit(fields[q], h=h, dt=1e-3, alpha=1.0, precision=wfa.F32_IR64,
+        tickets[q] = (sv.submit(fields[q], h=h, dt=1e-3, alpha=1.0, precision=prec,
                                 tol=1e-10, maxit=20000), time.perf_counter() - t_start)
     sv.drain()
     t_end = time.perf_counter() - t_start
-    lat, cell_it, fails = [], 0, 0
+    lat, cell_it, fails, its = [], 0, 0, 0
     for q, rq in enumerate(reqs):
         code, info = sv.poll(tickets[q][0])
         if code != wfa.OK:
             fails += 1
         lat.append((tickets[q][1] - rq.arrival) + info.seconds)
         cell_it += rq.nx * rq.ny * rq.nz * info.iterations
+        its += info.iterations
     sv.close()
-    return {"workload": f"serve_{args.requests}req_200rps", "requests": len(reqs),
-            "failed": fails, "makespan_s": t_end,
+    return {"workload": f"serve_{args.requests}req_200rps", "precision": args.serve_precision,
+            "requests": len(reqs), "failed": fails, "makespan_s": t_end,
             "latency_ms": {"p50": percentile(lat, 50) * 1e3, "p99": percentile(lat, 99) * 1e3,
                            "mean": sum(lat) / len(lat) * 1e3},
+            "iterations_mean": its / len(reqs),
             "cell_iters_per_s": cell_it / t_end, "slots": args.slots,
             "budget_gb": args.budget_gb}
 
@@ -564,6 +617,8 @@ def main():
     ap.add_argument("--budget-gb", type=int, default=64)
     ap.add_argument("--cpu-iters", type=int, default=120)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--serve-precision", default="f32_ir64", choices=["f32_ir64", "f64"],
+                    help="serve: precision of every request")
     ap.add_argument("--no-profile", action="store_true",
                     help="time without per-launch events (no roofline)")
     ap.add_argument("--probe-copy", action="store_true",

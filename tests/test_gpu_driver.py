@@ -88,3 +88,41 @@ def test_restarts_and_refinement_unchanged_by_profiling(wfa):
             assert np.array_equal(a, c)
         else:
             assert a == c
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32_ir64"])
+def test_first_chunk_hint_leaves_results_unchanged(wfa, precision):
+    """The first chunk of a solve is sized from the grid's previous solve:
+    results on a grid that has solved before (the hint set) must equal, bit
+    for bit, those of fresh grids (no hint), for repeated solves and for
+    time steps; and a hint far too large or too small changes nothing."""
+    prob = inputs.convdiff(n=30, seed=21)
+    prec = wfa.PRECISIONS[precision]
+    tol = 1e-10
+
+    def fresh_step(T):
+        g = wfa.Grid.from_problem(prob, precision=prec)
+        g.set_option(wfa.OPT_METHOD, wfa.METHOD_BICGSTAB2)
+        return g.timestep(T, 1, tol=tol, maxit=5000)[0]
+
+    warm = wfa.Grid.from_problem(prob, precision=prec)
+    warm.set_option(wfa.OPT_METHOD, wfa.METHOD_BICGSTAB2)
+    Tw = warm.field(prob.T0)
+    Tf = warm.field(prob.T0)
+    for step in range(4):
+        iw = warm.timestep(Tw, 1, tol=tol, maxit=5000)[0]
+        i_f = fresh_step(Tf)
+        assert iw.status == wfa.OK and i_f.status == wfa.OK
+        assert (iw.iterations, iw.refinements) == (i_f.iterations, i_f.refinements), step
+        assert iw.rel_res_true == i_f.rel_res_true
+        assert np.array_equal(Tw.cpu().numpy(), Tf.cpu().numpy()), step
+    # a solve of a much easier system right after (hint far too large), then
+    # the original again (hint far too small)
+    b = warm.rhs(warm.field(prob.T0))
+    _, ie = warm.solve(b, warm.field(prob.T0), tol=1e-2, maxit=5000, method="bicgstab2")
+    x1, i1 = warm.solve(b, warm.field(prob.T0), tol=tol, maxit=5000, method="bicgstab2")
+    g2 = wfa.Grid.from_problem(prob, precision=prec)
+    x2, i2 = g2.solve(b, g2.field(prob.T0), tol=tol, maxit=5000, method="bicgstab2")
+    assert ie.status == wfa.OK and ie.iterations < i1.iterations
+    assert (i1.iterations, i1.rel_res_true) == (i2.iterations, i2.rel_res_true)
+    assert np.array_equal(x1.cpu().numpy(), x2.cpu().numpy())
