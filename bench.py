@@ -304,6 +304,11 @@ def run_convdiff(args, torch, inputs, wfa):
                                 "the timed steps repeated from the same initial field, one "
                                 "chunk of the step's iteration count per step",
                     "repeat_matches_timed_iterations": retraced}
+        # the measured reference: a 1 GiB device-to-device copy (one read and
+        # one write stream) on the same GPU
+        copy = wfa.stream_probe(COPY_PROBE_BYTES, 10)
+        roofline["copy_gbps"] = round(copy, 1)
+        roofline["frac_of_copy"] = round(achieved / copy, 4)
     w = 4 if prec == wfa.F32 else 8
     streams = streams_of(args)
     alg_bytes_iter = (streams * w + 2 * 4) * prob.cells   # vector streams + 2 kappa reads
