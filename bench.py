@@ -23,7 +23,9 @@ bounded sample of the same workload on this host.
 
 Other workloads (--workload): heat32 (32^3, 10 steps), poisson_large
 (512x512x1024 FP32, 500 iterations), mixed384 (FP32 inside FP64 refinement
-vs FP64), serve (Poisson request stream through the batching server).
+vs FP64), serve (Poisson request stream through the batching server),
+explicit (forward-time steps, one and several per pass), apply (the
+operator alone).  --method cg applies to the symmetric workloads.
 """
 import argparse
 import hashlib
@@ -228,6 +230,8 @@ def percentile(vals, q):
 
 def run_convdiff(args, torch, inputs, wfa):
     """The headline workload: 256^3 convection-diffusion time steps."""
+    if args.method == "cg":
+        raise SystemExit("CG needs a symmetric operator; the convection-diffusion workload is not")
     prob = inputs.convdiff(n=args.n)
     prec = wfa.PRECISIONS[args.precision]
     g = wfa.Grid.from_problem(prob, precision=prec)
@@ -463,7 +467,8 @@ def run_poisson_large(args, torch, inputs, wfa):
         if n:
             kernels[name] = {"us_avg": round(ms / n * 1e3, 1), "gbps": round(by / (ms / n * 1e-3) / 1e9, 1)}
     streams = streams_of(args)
-    bytes_iter = (streams * 4 + 8) * prob.cells
+    kappa_reads = 1 if args.method == "cg" else 2     # diffusivity reads: one per operator product
+    bytes_iter = (streams * 4 + 4 * kappa_reads) * prob.cells
     return {"workload": "poisson_512x512x1024_f32_500it", "method": args.method,
             "shadow": args.shadow if args.method == "bicgstab2" else "r0",
             "seconds_best": best, "seconds": times, "iterations": info.iterations,
@@ -548,6 +553,36 @@ def run_serve(args, torch, inputs, wfa):
             "budget_gb": args.budget_gb}
 
 
+def run_apply(args, torch, inputs, wfa):
+    """y = A x alone (wfa_stencil_apply): the 256^3 convection-diffusion
+    operator in FP64 and the 512x512x1024 diffusion operator in FP32, both
+    with a per-cell diffusivity; 2w + 4 bytes per cell."""
+    out = {"workload": "stencil_apply", "results": []}
+    for label, prob, prec, w in (("convdiff_256^3_f64", inputs.convdiff(n=256), wfa.F64, 8),
+                                 ("poisson_512x512x1024_f32", inputs.poisson_large(), wfa.F32, 4)):
+        g = wfa.Grid.from_problem(prob, precision=prec)
+        x = g.field(prob.T0)
+        y = g.field()
+        reps = 50
+        for _ in range(3):
+            g.apply(x, y)
+        stream = torch.cuda.current_stream()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            g.apply(x, y)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / reps
+        by = (2 * w + 4) * prob.cells
+        out["results"].append({"grid": label, "us_per_apply": round(us, 2),
+                               "alg_gbps": round(by / (us * 1e-6) / 1e9, 1),
+                               "frac_8tbs": round(by / (us * 1e-6) / 8e12, 4)})
+        del g, x, y
+    return out
+
+
 def run_explicit(args, torch, inputs, wfa):
     """Explicit forward-time heat steps (Eq. 2, omega = 1/10, constant
     diffusivity, Dirichlet 0) on 512x512x1024 in FP32: the paper's explicit
@@ -605,8 +640,10 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="convdiff",
-                    choices=["convdiff", "heat32", "poisson_large", "mixed384", "serve", "explicit"])
-    ap.add_argument("--method", default="bicgstab2", choices=["bicgstab", "bicgstab2"])
+                    choices=["convdiff", "heat32", "poisson_large", "mixed384", "serve", "explicit",
+                             "apply"])
+    ap.add_argument("--method", default="bicgstab2", choices=["bicgstab", "bicgstab2", "cg"],
+                    help="cg: the symmetric workloads only (poisson_large, heat32)")
     ap.add_argument("--shadow", default="hashed", choices=["r0", "hashed"],
                     help="shadow residual of the two-reduction BiCGStab: r0 (stored) or a "
                          "field hashed from the cell index (computed, one stream less per pass)")
@@ -664,6 +701,7 @@ def main():
     if args.probe_copy:
         print(json.dumps({"copy_probe_gbps": wfa.stream_probe(COPY_PROBE_BYTES, 1)}), file=sys.stderr)
     run = {"convdiff": run_convdiff, "heat32": run_heat32, "poisson_large": run_poisson_large,
+           "apply": run_apply,
            "mixed384": run_mixed384, "serve": run_serve, "explicit": run_explicit}[args.workload]
     print(json.dumps(run(args, torch, inputs, wfa)))
 
