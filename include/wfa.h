@@ -119,7 +119,9 @@ size_t wfa_workspace_bytes(int nx, int ny, int nz, int precision);
 int wfa_grid_create(int nx, int ny, int nz, const wfa_coeffs* c,
                     void* workspace, size_t workspace_bytes, wfa_grid** out);
 
-/* Release the host descriptor (the workspace stays the caller's). */
+/* Release the host descriptor (the workspace stays the caller's), with the
+ * small pinned host block and the event its first solve set up for reading
+ * scalars back (host memory, not device memory). */
 int wfa_grid_destroy(wfa_grid* g);
 
 /* y = A x with the ghosts held at zero, i.e. the operator alone (boundary
@@ -295,7 +297,10 @@ int wfa_stream_probe(const void* src, void* dst, size_t bytes, int reps, double*
  * WFA_OPT_SHADOW = 1; WFA_F32_IR64 requests run it as the inner solve of
  * refinement, as wfa_timestep does.  A background host
  * thread drives the GPU on `stream`.  Precision of every request:
- * c->precision. */
+ * c->precision.  The server also holds a pinned host mirror of its slot
+ * tables and scalars and one event, freed by wfa_server_destroy.
+ * Errors: WFA_ERR_INVALID, WFA_ERR_NOMEM (arena smaller than its tables),
+ * WFA_ERR_HIP (the pinned mirror or the event). */
 int wfa_server_create(void* arena, size_t arena_bytes, int max_slots, void* stream,
                       wfa_server** out);
 

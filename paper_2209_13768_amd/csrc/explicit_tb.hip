@@ -13,8 +13,11 @@
 // the x/y neighbours, so the levels run as a pipeline behind the loads: when
 // level 0 (the input) of plane j arrives, level s is computed on plane
 // j - s.  Each thread keeps the last three planes of every level for its
-// own cells in registers (the z neighbours); the middle plane of every level
-// goes through LDS for the x/y neighbours.  Level s is correct on the
+// own cells in registers (the z neighbours).  The x neighbours are the
+// adjacent lanes of the same wave, read with DPP lane shifts; the y
+// neighbours are the thread's own rows, except across the boundary between
+// two waves, whose first and last rows of every level go through a small
+// double-buffered LDS exchange (one barrier per plane).  Level s is correct on the
 // column shrunk by s cells on each side, so a tile's output is the inner
 // (64 - 2S) x (TY - 2S) cells; neighbouring tiles overlap by 2S cells and
 // recompute the overlap.  Along z a tile covers zc output planes and reads
@@ -34,19 +37,38 @@ struct TbGeo {
   long long plane;
 };
 
+// Value of lane - 1 (from_left) or lane + 1 (from_right) of the wave; 0 at
+// the wave's ends, which hold the column's halo, outside every level's
+// valid region.
+__device__ __forceinline__ int dpp_left(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xF, 0xF, true);   // wave_shr:1
+}
+__device__ __forceinline__ int dpp_right(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xF, 0xF, true);   // wave_shl:1
+}
+__device__ __forceinline__ float from_left(float v) { return __int_as_float(dpp_left(__float_as_int(v))); }
+__device__ __forceinline__ float from_right(float v) { return __int_as_float(dpp_right(__float_as_int(v))); }
+__device__ __forceinline__ double from_left(double v) {
+  return __hiloint2double(dpp_left(__double2hiint(v)), dpp_left(__double2loint(v)));
+}
+__device__ __forceinline__ double from_right(double v) {
+  return __hiloint2double(dpp_right(__double2hiint(v)), dpp_right(__double2loint(v)));
+}
+
 template <typename T, int S, int RY>
 __global__ void __launch_bounds__(kThreads)
 k_explicit_tb(TbGeo g, Op<T> op, const T* __restrict__ x, T* __restrict__ y) {
   constexpr int TY = kWaves * RY;
+  // input planes loaded ahead (measured: 2 is no faster, 3 slower)
+  constexpr int PD = 1;
   constexpr int OW = kTX - 2 * S;
   constexpr int OH = TY - 2 * S;
-  // LDS planes with a one-cell border that is never written: every
-  // neighbour is a fixed offset from the thread's cell, and the border is
-  // read only by cells outside the valid region
-  constexpr int PW = kTX + 2;
-  constexpr int PH = TY + 2;
   static_assert(OW > 0 && OH > 0, "tile too small for the number of fused steps");
-  __shared__ T lds[S * PH * PW];
+  static_assert(RY >= 2, "a wave's first and last rows must differ");
+  // [parity][level][wave][lane]: each wave's first (top) and last (bottom)
+  // row of the middle plane of every level below S
+  __shared__ T top[2][S][kWaves][kTX];
+  __shared__ T bot[2][S][kWaves][kTX];
 
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -62,7 +84,10 @@ k_explicit_tb(TbGeo g, Op<T> op, const T* __restrict__ x, T* __restrict__ y) {
   const bool col_in = i >= 0 && i < g.nx;
   const bool col_out = lane >= S && lane < kTX - S && i < g.nx;
   const uint32_t ins_x = (i > 0 ? 1u : 0u) | (i < g.nx - 1 ? 2u : 0u);
-  T* const me = lds + (wave * RY + 1) * PW + lane + 1;  // row 0 of this thread, level 0
+  // the neighbouring waves' rows (the tile's outermost waves read a row of
+  // their own instead: it lies in the halo, outside every valid region)
+  const int wup = wave > 0 ? wave - 1 : wave;
+  const int wdn = wave < kWaves - 1 ? wave + 1 : wave;
 
   // W[q][0..2]: level q on planes (newest - 2, newest - 1, newest)
   T W[S][3][RY];
@@ -74,17 +99,23 @@ k_explicit_tb(TbGeo g, Op<T> op, const T* __restrict__ x, T* __restrict__ y) {
       for (int r = 0; r < RY; ++r) W[q][a][r] = T(0);
 
   const int jb = zs - S > 0 ? zs - S : 0;
-  T pre[RY];
+  // input planes jb .. jb + PD - 1 in flight before the first step; each
+  // step consumes the oldest and issues the load of the plane PD ahead
+  T pre[PD][RY];
 #pragma unroll
-  for (int r = 0; r < RY; ++r) {
-    const int j = j0 + r;
-    const T* row = x + (size_t)jb * g.plane + (long long)j * g.nx;
-    pre[r] = (col_in && j >= 0 && j < g.ny && jb < g.nz) ? row[i] : T(0);
-  }
+  for (int d = 0; d < PD; ++d)
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      const int j = j0 + r;
+      const int kk = jb + d;
+      const T* row = x + (size_t)kk * g.plane + (long long)j * g.nx;
+      pre[d][r] = (col_in && j >= 0 && j < g.ny && kk < g.nz) ? row[i] : T(0);
+    }
 
   const T kz[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};  // constant diffusivity
   const InteriorCoef<T> kin = interior_coef(op);
-  for (int k = jb; k < ze + S; ++k) {
+  int par = 0;
+  for (int k = jb; k < ze + S; ++k, par ^= 1) {
     // opaque copies: the face masks below are recomputed every step instead
     // of being hoisted out of the loop as per-row coefficient registers
     int jr = j0;
@@ -99,32 +130,42 @@ k_explicit_tb(TbGeo g, Op<T> op, const T* __restrict__ x, T* __restrict__ y) {
         W[q][1][r] = W[q][2][r];
       }
 #pragma unroll
-    for (int r = 0; r < RY; ++r) W[0][2][r] = k < g.nz ? pre[r] : T(0);
-    if (k + 1 < g.nz) {
+    for (int r = 0; r < RY; ++r) W[0][2][r] = k < g.nz ? pre[0][r] : T(0);
+#pragma unroll
+    for (int d = 0; d + 1 < PD; ++d)
+#pragma unroll
+      for (int r = 0; r < RY; ++r) pre[d][r] = pre[d + 1][r];
+    if (k + PD < g.nz) {
 #pragma unroll
       for (int r = 0; r < RY; ++r) {
         const int j = j0 + r;
-        const T* row = x + (size_t)(k + 1) * g.plane + (long long)j * g.nx;
-        pre[r] = (col_in && j >= 0 && j < g.ny) ? row[i] : T(0);
+        const T* row = x + (size_t)(k + PD) * g.plane + (long long)j * g.nx;
+        pre[PD - 1][r] = (col_in && j >= 0 && j < g.ny) ? row[i] : T(0);
       }
     }
-    // every level's middle plane into LDS
+    // every level's middle plane: the wave's boundary rows into LDS (the
+    // buffer of this parity was last read two steps ago, before the
+    // previous step's barrier)
 #pragma unroll
-    for (int q = 0; q < S; ++q)
-#pragma unroll
-      for (int r = 0; r < RY; ++r) me[q * PH * PW + r * PW] = W[q][1][r];
+    for (int q = 0; q < S; ++q) {
+      top[par][q][wave][lane] = W[q][1][0];
+      bot[par][q][wave][lane] = W[q][1][RY - 1];
+    }
     __syncthreads();
 #pragma unroll
     for (int s = 1; s <= S; ++s) {
       const int m = k - s;  // plane of level s computed in this step
       const bool plane_ok = m >= 0 && m < g.nz;
       const uint32_t ins_z = (m > 0 ? 16u : 0u) | (m < g.nz - 1 ? 32u : 0u);
-      const T* P = me + (s - 1) * PH * PW;
+      const T above = bot[par][s - 1][wup][lane];  // row j0 - 1
+      const T below = top[par][s - 1][wdn][lane];  // row j0 + RY
 #pragma unroll
       for (int r = 0; r < RY; ++r) {
         const int j = jr + r;
         const T c = W[s - 1][1][r];
-        const T nb[6] = {P[r * PW - 1], P[r * PW + 1], P[(r - 1) * PW], P[(r + 1) * PW],
+        const T nb[6] = {from_left(c), from_right(c),
+                         r > 0 ? W[s - 1][1][r - 1] : above,
+                         r < RY - 1 ? W[s - 1][1][r + 1] : below,
                          W[s - 1][0][r], W[s - 1][2][r]};
         const uint32_t ins = ix | (j > 0 ? 4u : 0u) | (j < g.ny - 1 ? 8u : 0u) | ins_z;
         T v;
@@ -146,7 +187,6 @@ k_explicit_tb(TbGeo g, Op<T> op, const T* __restrict__ x, T* __restrict__ y) {
         }
       }
     }
-    __syncthreads();  // the LDS planes are rewritten by the next step
   }
 }
 
