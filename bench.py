@@ -489,11 +489,16 @@ def run_mixed384(args, torch, inputs, wfa):
            "results": []}
     Tref = None
     for tol in (1e-10, 1e-12):
-        for name, prec, jac in (("f64", wfa.F64, 0), ("f64_jacobi", wfa.F64, 1),
-                                ("f32_ir64", wfa.F32_IR64, 0)):
+        # refinement with the default inner tolerance (1e-4) and with 1e-3,
+        # which needs one more refinement but cheaper inner solves here
+        for name, prec, jac, itol in (("f64", wfa.F64, 0, None), ("f64_jacobi", wfa.F64, 1, None),
+                                      ("f32_ir64", wfa.F32_IR64, 0, None),
+                                      ("f32_ir64_inner1e-3", wfa.F32_IR64, 0, 1e-3)):
             g = wfa.Grid.from_problem(prob, precision=prec)
             g.set_option(wfa.OPT_METHOD, METHODS["bicgstab2"])
             g.set_option(wfa.OPT_JACOBI, jac)
+            if itol is not None:
+                g.set_option(wfa.OPT_IR_INNER_TOL, int(round(itol * 1e12)))
             T = g.field(prob.T0)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
