@@ -190,12 +190,20 @@ enum {
   WFA_OPT_PERSISTENT = 2,      /* 0: one launch per phase (default),
                                   1: one persistent launch per solve chunk,
                                   -1: automatic by grid size                   */
-  WFA_OPT_PROFILE = 3,         /* 1: time every phase launch with HIP events   */
+  WFA_OPT_PROFILE = 3,         /* 1: time every phase launch with HIP events
+                                  (the true residual then gets its own pass
+                                  after the solve, instead of one queued
+                                  behind each chunk of iterations)             */
   WFA_OPT_FORCE_BREAKDOWN = 4, /* n > 0: treat sigma as exactly 0 at full
                                   iteration n of the next solve (once), to
                                   exercise the restart path from the host      */
   WFA_OPT_CHECK_EVERY = 5,     /* iterations between host convergence checks;
-                                  0 = adaptive (default)                       */
+                                  0 = adaptive (default): the first chunk of a
+                                  solve takes the iteration count of the grid's
+                                  previous converged solve (else 8), later
+                                  ones an estimate from the residual history.
+                                  Passes queued past convergence exit at
+                                  once, so results never depend on this.      */
   WFA_OPT_IR_INNER_TOL = 6,    /* (value / 1e12) = inner relative tolerance of
                                   WFA_F32_IR64; default 1e-4 * 1e12            */
   WFA_OPT_ZCHUNK = 7,          /* z planes per workgroup; 0 = default rule     */
