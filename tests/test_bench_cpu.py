@@ -1,0 +1,79 @@
+"""The benchmark's measurement helpers, on synthetic rocprofv3 outputs (CPU).
+
+Iteration passes queued past convergence exit at their first instruction;
+the trace summary's working columns and the per-launch traffic must leave
+them out, and the committed traffic figures must only be used for the
+kernel sources they were taken from.
+"""
+import csv
+import json
+
+import bench
+
+AC = "void wfa::k_march<double, true, 2, wfa::PhAC<double>, wfa::FinAC>(wfa::Geo, int)"
+B2 = "void wfa::k_march<double, true, 2, wfa::PhB2<double>, wfa::FinB2>(wfa::Geo, int)"
+COPY = "wfa::k_copy(unsigned long, unsigned int const*, unsigned int*)"
+
+
+def _write(path, fields, rows):
+    with open(path, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=fields)
+        w.writeheader()
+        for r in rows:
+            w.writerow(r)
+
+
+def test_trace_summary_working_columns(tmp_path):
+    durs = {AC: [250.0] * 10 + [2.0] * 3, B2: [120.0] * 9 + [1.5] * 4}
+    trace, t = [], 0
+    for name, ds in durs.items():
+        for d in ds:
+            trace.append({"Kernel_Name": name, "Start_Timestamp": t, "End_Timestamp": t + int(d * 1000)})
+            t += int(d * 1000) + 500
+    _write(tmp_path / "run_kernel_trace.csv", ["Kernel_Name", "Start_Timestamp", "End_Timestamp"], trace)
+    stats = []
+    for name, ds in durs.items():
+        stats.append({"Name": name, "Calls": len(ds), "TotalDurationNs": sum(ds) * 1000,
+                      "AverageNs": sum(ds) / len(ds) * 1000, "Percentage": 50.0})
+    _write(tmp_path / "run_kernel_stats.csv", ["Name", "Calls", "TotalDurationNs", "AverageNs",
+                                               "Percentage"], stats)
+    md = bench.summarize_trace(str(tmp_path / "run_kernel_stats.csv"), "title", "cmd")
+    rows = {line.split("`")[1]: line for line in md.splitlines() if line.startswith("| `")}
+    ac = rows["k_march<double, true, 2, PhAC<double>, FinAC>"].split("|")
+    b2 = rows["k_march<double, true, 2, PhB2<double>, FinB2>"].split("|")
+    assert int(ac[2]) == 13 and int(ac[6]) == 10 and float(ac[7]) == 250.0
+    assert int(b2[2]) == 13 and int(b2[6]) == 9 and float(b2[7]) == 120.0
+    # all-call average still reported as the profiler gave it
+    assert abs(float(ac[4]) - sum(durs[AC]) / 13) < 0.01
+
+
+def test_counter_means_leave_out_skipped_dispatches(tmp_path):
+    rows, did = [], 0
+    # FETCH_SIZE arrives as one row per XCD-level block: the dispatch's value is their sum
+    for value in [1000.0] * 5 + [0.5] * 3:
+        did += 1
+        for part in (0.25, 0.75):
+            rows.append({"Counter_Name": "FETCH_SIZE", "Kernel_Name": AC, "Dispatch_Id": did,
+                         "Counter_Value": value * part})
+    did += 1
+    rows.append({"Counter_Name": "FETCH_SIZE", "Kernel_Name": COPY, "Dispatch_Id": did,
+                 "Counter_Value": 524288.0})
+    rows.append({"Counter_Name": "WRITE_SIZE", "Kernel_Name": COPY, "Dispatch_Id": did,
+                 "Counter_Value": 7.0})
+    _write(tmp_path / "c.csv", ["Counter_Name", "Kernel_Name", "Dispatch_Id", "Counter_Value"], rows)
+    means = bench.counter_means(str(tmp_path / "c.csv"), "FETCH_SIZE")
+    assert means["phase_ac"] == (1000.0, 5)
+    assert means["copy"] == (524288.0, 1)
+    assert "phase_ac" not in bench.counter_means(str(tmp_path / "c.csv"), "WRITE_SIZE")
+
+
+def test_traffic_figures_gated_by_source_hash(tmp_path, monkeypatch):
+    path = tmp_path / "traffic.json"
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(path))
+    assert bench.load_traffic("phase_ac") is None          # no file
+    body = {"kernels": {"phase_ac": {"hbm_bytes_per_launch": 123}}}
+    path.write_text(json.dumps(dict(body, source_hash="0" * 16)))
+    assert bench.load_traffic("phase_ac") is None          # other sources
+    path.write_text(json.dumps(dict(body, source_hash=bench.kernel_source_hash())))
+    assert bench.load_traffic("phase_ac") == 123
+    assert bench.load_traffic("phase_b2") is None
