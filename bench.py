@@ -529,6 +529,8 @@ def run_serve(args, torch, inputs, wfa):
         fields.append(torch.from_numpy(rq.problem().T0).to("cuda"))
     torch.cuda.synchronize()
     sv = wfa.Server(args.budget_gb << 30, max_slots=args.slots)
+    sv.set_option(wfa.OPT_PERSISTENT, args.serve_persistent)
+    sv.set_option(wfa.OPT_CHECK_EVERY, args.serve_round)
     tickets = {}
     t_start = time.perf_counter()
     for q, rq in enumerate(reqs):
@@ -550,6 +552,8 @@ def run_serve(args, torch, inputs, wfa):
         its += info.iterations
     sv.close()
     return {"workload": f"serve_{args.requests}req_200rps", "precision": args.serve_precision,
+            "round": {"iterations": args.serve_round,
+                      "launch": "persistent" if args.serve_persistent else "per pass"},
             "requests": len(reqs), "failed": fails, "makespan_s": t_end,
             "latency_ms": {"p50": percentile(lat, 50) * 1e3, "p99": percentile(lat, 99) * 1e3,
                            "mean": sum(lat) / len(lat) * 1e3},
@@ -666,6 +670,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serve-precision", default="f32_ir64", choices=["f32_ir64", "f64"],
                     help="serve: precision of every request")
+    ap.add_argument("--serve-round", type=int, default=4,
+                    help="serve: iterations per round between host reads of the scalars")
+    ap.add_argument("--serve-persistent", type=int, default=0, choices=[0, 1],
+                    help="serve: 1 = each round is one cooperative launch per precision")
     ap.add_argument("--no-profile", action="store_true",
                     help="time without per-launch events (no roofline)")
     ap.add_argument("--probe-copy", action="store_true",

@@ -312,6 +312,18 @@ int wfa_stream_probe(const void* src, void* dst, size_t bytes, int reps, double*
 int wfa_server_create(void* arena, size_t arena_bytes, int max_slots, void* stream,
                       wfa_server** out);
 
+/* Server options, applied from the next round on:
+ *   WFA_OPT_CHECK_EVERY  iterations per round between the worker's reads of
+ *                        the slots' scalars, 1..1024 (default 4);
+ *   WFA_OPT_PERSISTENT   1: each round is one cooperative launch per
+ *                        precision, with grid barriers in place of the
+ *                        per-pass kernel boundaries (bitwise the same
+ *                        results); 0: one launch per pass (default).  A
+ *                        barrier wait that times out fails the server
+ *                        (WFA_ERR_HIP) instead of hanging.
+ * Errors: WFA_ERR_INVALID (null server, unknown option, value out of range). */
+int wfa_server_set_option(wfa_server* sv, int option, int64_t value);
+
 /* Queue one backward-Euler step of T (device, nx*ny*nz, in/out; the
  * caller keeps it, and kappa, alive until wfa_poll reports completion).
  * WFA_ERR_NOMEM if the request can never fit the arena. */

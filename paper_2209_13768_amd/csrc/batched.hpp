@@ -33,4 +33,15 @@ template <typename T>
 void launch_batch_iteration2(const SolveDesc<T>* descs, const int* tile_bases, int tiles_total,
                              int nsolves, int q, int ry, hipStream_t s);
 
+// `iters` such iterations in one cooperative launch, with grid barriers in
+// place of the kernel boundaries (bitwise the same iterates).  `bar` is a
+// barrier in device memory whose count and timeout start at zero; the
+// launch leaves them so unless a wait timed out: then bar->timeout is set,
+// the waves have left early and the solves' state is undefined.  Returns
+// the launch's error code.
+template <typename T>
+hipError_t launch_batch_persistent(const SolveDesc<T>* descs, const int* tile_bases,
+                                   int tiles_total, int nsolves, int iters, int ry,
+                                   GridBarrier* bar, int spin_limit, hipStream_t s);
+
 }  // namespace wfa

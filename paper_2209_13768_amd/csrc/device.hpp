@@ -314,6 +314,60 @@ __device__ __forceinline__ void publish_and_finalize(double (&v)[NV], int slot, 
   }
 }
 
+// ---- grid-wide barrier of a persistent (cooperative) launch -------------------
+// Sense-free barrier: arrivals counted in `count`, release by bumping `gen`.
+// Waits are bounded: after `spin_limit` polls the waiter records a timeout
+// and leaves, so every wave of the grid always exits.
+__device__ __forceinline__ bool grid_sync(GridBarrier* b, uint32_t nblocks, int spin_limit) {
+  __shared__ int ok;
+  // every wave's stores have reached its XCD's L2 ...
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    // ... one wave writes that L2 back (release) for the whole workgroup
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    int good = 1;
+    const uint32_t gen = __hip_atomic_load(&b->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    const uint32_t arrived =
+        __hip_atomic_fetch_add(&b->count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (arrived == nblocks - 1) {
+      __hip_atomic_store(&b->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      __hip_atomic_store(&b->gen, gen + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      int spins = 0;
+      while (__hip_atomic_load(&b->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > spin_limit) {
+          __hip_atomic_store(&b->timeout, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          good = 0;
+          break;
+        }
+      }
+    }
+    // and invalidates stale lines of the CU's L1 and the XCD's L2 (acquire)
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    ok = good;
+  }
+  __syncthreads();
+  return ok != 0;
+}
+
+// One workgroup's partial sums into slot `slot` of a region of NV x nslots
+// values (the layout publish_and_finalize uses), without the arrival count:
+// a persistent launch reduces them after a grid barrier instead.
+template <int NV>
+__device__ __forceinline__ void store_partial(double* region, int nslots, int slot,
+                                              const double (&v)[NV]) {
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q)
+      __hip_atomic_store(&region[(size_t)q * nslots + slot], v[q], __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
 // ---- the z-marching plane engine ----------------------------------------------
 //
 // A tile is kTX x TY cells of the x-y plane times zc planes in z.  Each of

@@ -129,6 +129,8 @@ struct wfa_server {
   SolveDesc<double>* h_d64 = nullptr;
   int* h_bases = nullptr;           // 4 * (max_slots + 1)
   hipEvent_t round_done = nullptr;  // the round's scalar readback
+  GridBarrier* bar = nullptr;       // device: grid barrier of a persistent round
+  GridBarrier* h_bar = nullptr;     // pinned: its state after the round
   // requests
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
@@ -140,7 +142,8 @@ struct wfa_server {
   bool stop = false;
   int worker_error = WFA_OK;
   char worker_msg[256] = "";
-  int chunk = 4;
+  int chunk = 4;      // iterations per round (WFA_OPT_CHECK_EVERY)
+  int persistent = 0; // 1: a round is one cooperative launch per precision (WFA_OPT_PERSISTENT)
   int ry = 0;        // rows per wave of every resident solve's tiling
   std::thread worker;
 };
@@ -159,6 +162,11 @@ int fail(wfa_server* sv, const char* what, hipError_t e) {
   sv->worker_error = WFA_ERR_HIP;
   return WFA_ERR_HIP;
 }
+
+// A persistent round's waits are bounded: a barrier wait that gives up (after
+// about this many polls of a few cycles' sleep each) makes every wave leave,
+// and the server reports the failure instead of hanging.
+constexpr int kRoundSpinLimit = 1 << 22;
 
 // Host-to-device copy of a table; remembers the first failure.
 int put(wfa_server* sv, void* dst, const void* src, size_t bytes) {
@@ -454,8 +462,11 @@ void worker_main(wfa_server* sv) {
   std::vector<Request*> admitted;
   while (true) {
     admitted.clear();
+    int chunk = 0, persist = 0;  // this round's options
     {
       std::unique_lock<std::mutex> lk(sv->mu);
+      chunk = sv->chunk;
+      persist = sv->persistent;
       // admission in arrival order: slot + arena space
       while (!sv->queue.empty()) {
         Request* r = sv->queue.front();
@@ -509,26 +520,47 @@ void worker_main(wfa_server* sv) {
     }
     if (!rc) {
       const int S = sv->max_slots;
-      // two-reduction BiCGStab iterations of every resident solve
-      for (int q = 0; q < sv->chunk; ++q) {
+      // two-reduction BiCGStab iterations of every resident solve: one
+      // launch per pass, or the whole round in one cooperative launch per
+      // precision (bitwise the same iterates)
+      hipError_t e = hipSuccess;
+      if (persist) {
         if (n32)
-          launch_batch_iteration2<float>(sv->d32, sv->bases, t32, n32, q, sv->ry, sv->stream);
-        if (n64)
-          launch_batch_iteration2<double>(sv->d64, sv->bases + 2 * (S + 1), t64, n64, q, sv->ry,
-                                          sv->stream);
+          e = launch_batch_persistent<float>(sv->d32, sv->bases, t32, n32, chunk, sv->ry, sv->bar,
+                                             kRoundSpinLimit, sv->stream);
+        if (e == hipSuccess && n64)
+          e = launch_batch_persistent<double>(sv->d64, sv->bases + 2 * (S + 1), t64, n64, chunk,
+                                              sv->ry, sv->bar, kRoundSpinLimit, sv->stream);
+      } else {
+        for (int q = 0; q < chunk; ++q) {
+          if (n32)
+            launch_batch_iteration2<float>(sv->d32, sv->bases, t32, n32, q, sv->ry, sv->stream);
+          if (n64)
+            launch_batch_iteration2<double>(sv->d64, sv->bases + 2 * (S + 1), t64, n64, q, sv->ry,
+                                            sv->stream);
+        }
+        e = hipGetLastError();
       }
       for (Request* r : sv->slots)
-        if (r && (r->phase == R_ITER || r->phase == R_REFINE)) r->par ^= (sv->chunk & 1);
-      hipError_t e = hipGetLastError();
+        if (r && (r->phase == R_ITER || r->phase == R_REFINE)) r->par ^= (chunk & 1);
       if (e != hipSuccess) rc = fail(sv, "batched iteration", e);
     }
     if (!rc) {
       hipError_t e = hipMemcpyAsync(sv->h_sc, sv->slot_sc,
                                     sizeof(Scalars) * kScalarsPerSlot * sv->max_slots,
                                     hipMemcpyDeviceToHost, sv->stream);
+      if (e == hipSuccess && persist)
+        e = hipMemcpyAsync(sv->h_bar, sv->bar, sizeof(GridBarrier), hipMemcpyDeviceToHost,
+                           sv->stream);
       if (e == hipSuccess) e = hipEventRecord(sv->round_done, sv->stream);
       if (e == hipSuccess) e = wait_event(sv->round_done);
-      if (e != hipSuccess) rc = fail(sv, "scalar readback", e);
+      if (e != hipSuccess) {
+        rc = fail(sv, "scalar readback", e);
+      } else if (persist && sv->h_bar->timeout) {
+        snprintf(sv->worker_msg, sizeof sv->worker_msg,
+                 "persistent round: a grid barrier wait timed out");
+        sv->worker_error = rc = WFA_ERR_HIP;
+      }
     }
     std::unique_lock<std::mutex> lk(sv->mu);
     if (rc) {
@@ -563,7 +595,8 @@ extern "C" int wfa_server_create(void* arena, size_t arena_bytes, int max_slots,
   const size_t d32_bytes = align256(sizeof(SolveDesc<float>) * max_slots);
   const size_t d64_bytes = align256(sizeof(SolveDesc<double>) * max_slots);
   const size_t b_bytes = align256(sizeof(int) * 4 * (max_slots + 1));
-  const size_t meta = sc_bytes + d32_bytes + d64_bytes + b_bytes;
+  const size_t bar_bytes = align256(sizeof(GridBarrier));
+  const size_t meta = sc_bytes + d32_bytes + d64_bytes + b_bytes + bar_bytes;
   if (arena_bytes <= meta) return set_error(WFA_ERR_NOMEM, "arena smaller than the slot tables");
   wfa_server* sv = new (std::nothrow) wfa_server();
   if (!sv) return set_error(WFA_ERR_NOMEM, "host allocation failed");
@@ -575,13 +608,17 @@ extern "C" int wfa_server_create(void* arena, size_t arena_bytes, int max_slots,
   sv->d32 = (SolveDesc<float>*)(sv->arena + sc_bytes);
   sv->d64 = (SolveDesc<double>*)(sv->arena + sc_bytes + d32_bytes);
   sv->bases = (int*)(sv->arena + sc_bytes + d32_bytes + d64_bytes);
+  sv->bar = (GridBarrier*)(sv->arena + sc_bytes + d32_bytes + d64_bytes + b_bytes);
   sv->heap_base = meta;
   sv->heap.init(arena_bytes - meta);
   {
-    const size_t hb = sc_bytes + d32_bytes + d64_bytes + b_bytes;  // same carving as the arena
+    const size_t hb = meta;  // same carving as the arena
     hipError_t e = hipHostMalloc(&sv->pinned, hb, hipHostMallocDefault);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&sv->round_done, hipEventDisableTiming);
+    // the persistent rounds' barrier starts with no arrivals and no timeout
+    if (e == hipSuccess) e = hipMemsetAsync(sv->bar, 0, sizeof(GridBarrier), sv->stream);
     if (e != hipSuccess) {
+      if (sv->round_done) (void)hipEventDestroy(sv->round_done);
       if (sv->pinned) (void)hipHostFree(sv->pinned);
       delete sv;
       return set_error(WFA_ERR_HIP, "server host tables: %s", hipGetErrorString(e));
@@ -592,12 +629,9 @@ extern "C" int wfa_server_create(void* arena, size_t arena_bytes, int max_slots,
     sv->h_d32 = (SolveDesc<float>*)(h + sc_bytes);
     sv->h_d64 = (SolveDesc<double>*)(h + sc_bytes + d32_bytes);
     sv->h_bases = (int*)(h + sc_bytes + d32_bytes + d64_bytes);
+    sv->h_bar = (GridBarrier*)(h + sc_bytes + d32_bytes + d64_bytes + b_bytes);
   }
   sv->slots.assign(max_slots, nullptr);
-  if (const char* c = getenv("WFA_SERVER_CHUNK")) {
-    const int v = atoi(c);
-    if (v >= 1 && v <= 1024) sv->chunk = v;
-  }
   try {
     sv->worker = std::thread(worker_main, sv);
   } catch (...) {
@@ -608,6 +642,24 @@ extern "C" int wfa_server_create(void* arena, size_t arena_bytes, int max_slots,
   }
   *out = sv;
   return WFA_OK;
+}
+
+extern "C" int wfa_server_set_option(wfa_server* sv, int option, int64_t value) {
+  if (!sv) return set_error(WFA_ERR_INVALID, "server is NULL");
+  std::lock_guard<std::mutex> lk(sv->mu);  // the worker reads them once per round
+  switch (option) {
+    case WFA_OPT_PERSISTENT:
+      if (value != 0 && value != 1) return set_error(WFA_ERR_INVALID, "persistent must be 0 or 1");
+      sv->persistent = (int)value;
+      return WFA_OK;
+    case WFA_OPT_CHECK_EVERY:
+      if (value < 1 || value > 1024)
+        return set_error(WFA_ERR_INVALID, "iterations per round must be in [1, 1024]");
+      sv->chunk = (int)value;
+      return WFA_OK;
+    default:
+      return set_error(WFA_ERR_INVALID, "option %d is not a server option", option);
+  }
 }
 
 extern "C" int wfa_submit(wfa_server* sv, int nx, int ny, int nz, const wfa_coeffs* c, void* T,

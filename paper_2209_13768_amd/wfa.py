@@ -37,7 +37,8 @@ EXPORTS = (
     "wfa_workspace_bytes", "wfa_grid_create", "wfa_grid_destroy", "wfa_stencil_apply",
     "wfa_rhs", "wfa_explicit_step", "wfa_bicgstab_solve", "wfa_bicgstab2_solve", "wfa_cg_solve", "wfa_timestep", "wfa_true_residual",
     "wfa_grid_set_option", "wfa_kernel_stats", "wfa_grid_tiling", "wfa_stream_probe",
-    "wfa_server_create", "wfa_submit", "wfa_poll", "wfa_server_drain", "wfa_server_destroy",
+    "wfa_server_create", "wfa_server_set_option", "wfa_submit", "wfa_poll", "wfa_server_drain",
+    "wfa_server_destroy",
     "wfa_last_error", "wfa_version", "wfa_autotune", "wfa_tune_save", "wfa_tune_load",
     "wfa_tune_clear",
 )
@@ -124,6 +125,7 @@ def lib() -> ctypes.CDLL:
     L.wfa_grid_tiling.argtypes = [vp] + [ctypes.POINTER(i32)] * 4
     L.wfa_stream_probe.argtypes = [vp, vp, sz, i32, ctypes.POINTER(dbl), vp]
     L.wfa_server_create.argtypes = [vp, sz, i32, vp, ctypes.POINTER(vp)]
+    L.wfa_server_set_option.argtypes = [vp, i32, i64]
     L.wfa_submit.argtypes = [vp, i32, i32, i32, ctypes.POINTER(Coeffs), vp, dbl, i32,
                              ctypes.POINTER(ctypes.c_uint64)]
     L.wfa_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(_Info)]
@@ -385,6 +387,11 @@ class Server:
                                 float(tol), int(maxit), ctypes.byref(t)))
         self._keep[t.value] = (T, kappa)
         return t.value
+
+    def set_option(self, option: int, value: int):
+        """OPT_CHECK_EVERY (iterations per round) or OPT_PERSISTENT (one
+        cooperative launch per round), from the next round on."""
+        _check(lib().wfa_server_set_option(self._h, int(option), int(value)))
 
     def submit_problem(self, prob, T, **kw) -> int:
         torch = _torch()

@@ -29,16 +29,19 @@ def _requests(dims=DIMS):
     return [inputs.Request(q, 0.0, *d) for q, d in enumerate(dims)]
 
 
-def _serve(wfa, reqs, budget, slots, precision=None, tol=1e-10):
+def _serve(wfa, reqs, budget, slots, precision=None, tol=1e-10, options=None):
     import torch
     sv = wfa.Server(budget, max_slots=slots)
+    for opt, val in (options or {}).items():
+        sv.set_option(opt, val)
     outs, tickets = [], []
     for q, rq in enumerate(reqs):
         prob = rq.problem()
         prec = precision[q] if isinstance(precision, list) else (precision or wfa.F32_IR64)
         dtype = torch.float32 if prec == wfa.F32 else torch.float64
         T = torch.from_numpy(prob.T0).to("cuda", dtype)
-        tickets.append(sv.submit_problem(prob, T, precision=prec, tol=tol, maxit=20000))
+        tq = tol[q] if isinstance(tol, list) else tol
+        tickets.append(sv.submit_problem(prob, T, precision=prec, tol=tq, maxit=20000))
         outs.append(T)
     sv.drain()
     infos = []
@@ -107,3 +110,33 @@ def test_mixed_precisions_in_one_server(wfa, oracle_mod):
         prob = rq.problem()
         o = oracle_mod.Oracle(prob)
         assert o.true_relres(o.rhs(prob.T0), m) <= 1e-10
+
+
+def test_persistent_rounds_are_bitwise_per_pass_rounds(wfa):
+    """A round as one cooperative launch per precision (grid barriers in
+    place of kernel boundaries) gives the per-pass launches' results bit for
+    bit, for every round length, with FP32-in-FP64, FP64 and FP32 requests
+    resident together."""
+    reqs = _requests(DIMS + [(96, 96, 64), (20, 30, 40)])
+    precs = [wfa.F32_IR64, wfa.F64, wfa.F32, wfa.F32_IR64, wfa.F64, wfa.F32_IR64, wfa.F32,
+             wfa.F64]
+    tols = [1e-5 if p == wfa.F32 else 1e-9 for p in precs]
+    ref, rinfo = _serve(wfa, reqs, 1 << 30, slots=8, precision=precs, tol=tols)
+    for opts in ({wfa.OPT_PERSISTENT: 1}, {wfa.OPT_PERSISTENT: 1, wfa.OPT_CHECK_EVERY: 3},
+                 {wfa.OPT_PERSISTENT: 0, wfa.OPT_CHECK_EVERY: 1},
+                 {wfa.OPT_PERSISTENT: 1, wfa.OPT_CHECK_EVERY: 16}):
+        got, ginfo = _serve(wfa, reqs, 1 << 30, slots=8, precision=precs, tol=tols, options=opts)
+        for rq, a, b, ia, ib in zip(reqs, ref, got, rinfo, ginfo):
+            assert np.array_equal(a, b), (opts, rq)
+            assert (ia.iterations, ia.refinements) == (ib.iterations, ib.refinements), (opts, rq)
+
+
+def test_server_options_are_validated(wfa):
+    sv = wfa.Server(1 << 26, max_slots=2)
+    for opt, val in ((wfa.OPT_PERSISTENT, 2), (wfa.OPT_CHECK_EVERY, 0),
+                     (wfa.OPT_CHECK_EVERY, 1025), (wfa.OPT_PROFILE, 1)):
+        with pytest.raises(wfa.WfaError):
+            sv.set_option(opt, val)
+    sv.set_option(wfa.OPT_CHECK_EVERY, 8)
+    sv.set_option(wfa.OPT_PERSISTENT, 1)
+    sv.close()
