@@ -313,7 +313,9 @@ def run_convdiff(args, torch, inputs, wfa):
         copy = wfa.stream_probe(COPY_PROBE_BYTES, 10)
         roofline["copy_gbps"] = round(copy, 1)
         roofline["frac_of_copy"] = round(achieved / copy, 4)
-    w = 4 if prec == wfa.F32 else 8
+    # vector width of the counted iterations: FP32 for the refinement's inner
+    # solve too (its few FP64 residual passes are left out of this figure)
+    w = 8 if prec == wfa.F64 else 4
     streams = streams_of(args)
     alg_bytes_iter = (streams * w + 2 * 4) * prob.cells   # vector streams + 2 kappa reads
     whole = alg_bytes_iter * iters / (total_ms * 1e-3) / 1e9
