@@ -285,7 +285,10 @@ def run_convdiff(args, torch, inputs, wfa):
         # converged iteration's second pass)
         pinfos = []
         for k in range(args.steps):
-            g.set_option(wfa.OPT_CHECK_EVERY, infos[k].iterations + 1)
+            # refinement reports only the total over its inner solves: there,
+            # one iteration per chunk (a host check after every iteration)
+            chunk = 1 if prec == wfa.F32_IR64 else infos[k].iterations + 1
+            g.set_option(wfa.OPT_CHECK_EVERY, chunk)
             pinfos += g.timestep(T, 1, tol=args.tol, maxit=args.maxit, check=False)
         g.set_option(wfa.OPT_CHECK_EVERY, 0)
         torch.cuda.synchronize()
