@@ -688,10 +688,11 @@ static void graph_key(uint64_t (&k)[GraphCache::kKey], const wfa_grid* g, const 
 // restarts from the true residual b - A x when `restartable`; otherwise the
 // loop returns with h->restart set (the caller restarts at a higher level).
 //
-// The caller has queued the pass that initialised the scalar block, and h
-// holds the values it wrote there; the first chunk is queued behind that
-// pass without reading it back (if it ended the solve, every pass of the
-// chunk exits at its first instruction).  The same holds after a restart.
+// The caller has queued the pass that initialises the scalar block; h holds
+// the host's values for the block from before that pass (iteration count,
+// limits).  The first chunk is queued behind that pass without reading it
+// back (if it ended the solve, every pass of the chunk exits at its first
+// instruction).  The same holds after a restart.
 // Each chunk's scalars are read back once, together with the optional
 // `tail`: a second scalar block, and a pass queued behind every chunk.
 
