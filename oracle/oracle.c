@@ -17,7 +17,8 @@
  *     (harmonic mean on faces), constant-velocity first-order upwind
  *     convection, and per-face Dirichlet or zero-flux boundaries;
  *   - Krylov solution of A x = b (section 1.1.2 names classic CG for the
- *     symmetric case; BiCGStab of van der Vorst (1992) covers the
+ *     symmetric case, also in its one-reduction form of Chronopoulos and
+ *     Gear (1989); BiCGStab of van der Vorst (1992) covers the
  *     non-symmetric upwind operator).
  *
  * Conventions
@@ -632,6 +633,88 @@ done:
   }
   if (r_out) memcpy(r_out, r, bytes);
   free(r); free(d); free(q);
+  return status;
+}
+
+/*
+ * Conjugate gradients with one global reduction per iteration (Chronopoulos
+ * and Gear, 1989).  Besides p it carries s = A p and w = A r by recurrence, so
+ * that the two inner products an iteration needs, gamma = (r, r) and
+ * delta = (A r, r), are formed together after the only operator product of
+ * the iteration, w = A r.  The step length follows from them:
+ *   beta = gamma / gamma_old,  alpha = gamma / (delta - beta * gamma / alpha_old),
+ * the CG step lengths in exact arithmetic, so the iterates are those of
+ * orc_cg up to rounding (the paper's reduction-bound CG, section 3.2.2,
+ * needs two reductions per iteration in its textbook form).
+ *   r = b - A x, w = A r, gamma = (r, r), delta = (w, r); stop if ||r|| <= tol ||b||
+ *   alpha = gamma / delta, p = r, s = w
+ *   repeat: x += alpha p; r -= alpha s; w = A r; gamma' = (r, r), delta = (w, r)
+ *           stop if ||r|| <= tol ||b||
+ *           beta = gamma' / gamma; alpha = gamma' / (delta - beta gamma' / alpha)
+ *           p = r + beta p; s = w + beta s; gamma = gamma'
+ * A denominator that is not positive (A not positive definite) ends the solve
+ * with ORC_BREAKDOWN, as in orc_cg.
+ */
+int orc_cg1(const orc_problem* p, const double* b, double* x, double tol,
+            int maxit, double* r_out, orc_info* info)
+{
+  const long n = cells(p);
+  const size_t bytes = sizeof(double) * (size_t)n;
+  double* r = (double*)malloc(bytes);
+  double* w = (double*)malloc(bytes);
+  double* pv = (double*)malloc(bytes);
+  double* s = (double*)malloc(bytes);
+  int status = ORC_NOCONV, it = 0;
+  double rnorm = 0.0;
+
+  const double bn = sqrt(dot(p, b, b));
+  if (!isfinite(bn) || !all_finite(x, n)) { status = ORC_NONFINITE; goto done; }
+  if (bn == 0.0) {
+    memset(x, 0, bytes);
+    memset(r, 0, bytes);
+    status = ORC_OK;
+    goto done;
+  }
+  residual(p, b, x, r);
+  double gamma = dot(p, r, r);
+  rnorm = sqrt(gamma);
+  if (!isfinite(rnorm)) { status = ORC_NONFINITE; goto done; }
+  if (rnorm <= tol * bn) { status = ORC_OK; goto done; }
+  orc_apply(p, r, w);
+  double delta = dot(p, w, r);
+  if (!isfinite(delta) || delta <= 0.0) { status = ORC_BREAKDOWN; goto done; }
+  double alpha = gamma / delta;
+  memcpy(pv, r, bytes);
+  memcpy(s, w, bytes);
+  while (it < maxit) {
+    ++it;
+#pragma omp parallel for schedule(static)
+    for (long c = 0; c < n; ++c) { x[c] += alpha * pv[c]; r[c] -= alpha * s[c]; }
+    orc_apply(p, r, w);
+    const double gamma_new = dot(p, r, r);
+    delta = dot(p, w, r);
+    rnorm = sqrt(gamma_new);
+    if (!isfinite(rnorm) || !isfinite(delta)) { status = ORC_NONFINITE; goto done; }
+    if (rnorm <= tol * bn) { status = ORC_OK; goto done; }
+    const double beta = gamma_new / gamma;
+    const double denom = delta - beta * gamma_new / alpha;
+    if (!(denom > 0.0)) { status = ORC_BREAKDOWN; goto done; }
+    alpha = gamma_new / denom;
+#pragma omp parallel for schedule(static)
+    for (long c = 0; c < n; ++c) { pv[c] = r[c] + beta * pv[c]; s[c] = w[c] + beta * s[c]; }
+    gamma = gamma_new;
+  }
+  status = ORC_NOCONV;
+done:
+  if (info) {
+    info->status = status;
+    info->iterations = it;
+    info->restarts = 0;
+    info->rel_res_recursive = bn > 0.0 ? rnorm / bn : 0.0;
+    info->rel_res_true = (status == ORC_NONFINITE) ? NAN : orc_true_relres(p, b, x);
+  }
+  if (r_out) memcpy(r_out, r, bytes);
+  free(r); free(w); free(pv); free(s);
   return status;
 }
 

@@ -92,6 +92,7 @@ def load(path: str | None = None) -> ctypes.CDLL:
     lib.orc_true_relres.restype = ctypes.c_double
     lib.orc_bicgstab.argtypes = [P, D, D, ctypes.c_double, ctypes.c_int, D, I]
     lib.orc_cg.argtypes = [P, D, D, ctypes.c_double, ctypes.c_int, D, I]
+    lib.orc_cg1.argtypes = [P, D, D, ctypes.c_double, ctypes.c_int, D, I]
     lib.orc_bicgstab2.argtypes = [P, D, D, ctypes.c_double, ctypes.c_int, D, I]
     lib.orc_bicgstab2_shadow.argtypes = [P, D, D, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                          D, I]
@@ -210,6 +211,10 @@ class Oracle:
 
     def cg(self, b, x0, tol: float, maxit: int, want_r: bool = False):
         return self._krylov(self.lib.orc_cg, b, x0, tol, maxit, want_r)
+
+    def cg1(self, b, x0, tol: float, maxit: int, want_r: bool = False):
+        """CG with one reduction per iteration (Chronopoulos-Gear; oracle.c)."""
+        return self._krylov(self.lib.orc_cg1, b, x0, tol, maxit, want_r)
 
     def timestep(self, T, nsteps: int, tol: float, maxit: int):
         T = self._vec(T).copy()

@@ -56,6 +56,10 @@ MUTANTS = [
      "if (rnorm <= tol) { status = ORC_OK; goto done; }\n    if (omega"),
     ("cg_beta_inverted", "const double beta = rr_new / rr;", "const double beta = rr / rr_new;"),
     ("cg_step_sign", "x[c] += a * d[c]; r[c] -= a * q[c];", "x[c] -= a * d[c]; r[c] -= a * q[c];"),
+    ("cg1_step_ignores_beta", "const double denom = delta - beta * gamma_new / alpha;",
+     "const double denom = delta;"),
+    ("cg1_s_recurrence_dropped", "pv[c] = r[c] + beta * pv[c]; s[c] = w[c] + beta * s[c];",
+     "pv[c] = r[c] + beta * pv[c]; s[c] = w[c];"),
     ("bicgstab2_beta_uses_exact_rho", "const double rho_pred = rs - omega * rt;",
      "const double rho_pred = rs + omega * rt;"),
     ("bicgstab2_x_update_order", "x[c] = x[c] + alpha * pv[c] + omega * sc;",

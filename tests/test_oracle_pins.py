@@ -611,3 +611,55 @@ def test_bicgstab2_hashed_shadow_follows_textbook_iterates(oracle_mod, cell, u):
         assert rel_l2(x2, xt) <= 1e-12
         xr, _ = o.bicgstab2(b, p.T0, 1e-300, k)
         assert rel_l2(xr, xt) > 1e-9                     # r^ = r0 gives other iterates
+
+
+# ------------------------------------------------- CG with one reduction per iteration
+def _textbook_cg(apply, b, x, k):
+    """Hestenes-Stiefel CG restated here (independently of oracle.c)."""
+    r = b - apply(x)
+    d = r.copy()
+    rr = float(np.vdot(r, r))
+    for _ in range(k):
+        q = apply(d)
+        a = rr / float(np.vdot(d, q))
+        x = x + a * d
+        r = r - a * q
+        rr_new = float(np.vdot(r, r))
+        d = r + (rr_new / rr) * d
+        rr = rr_new
+    return x
+
+
+@pytest.mark.parametrize("cell", [False, True])
+def test_cg1_follows_textbook_cg_iterates(oracle_mod, cell):
+    """The Chronopoulos-Gear recurrences give the CG iterates in exact
+    arithmetic: every iterate agrees with textbook CG to rounding."""
+    p = inputs.random_problem(161, 9, 8, 7, cell=cell, bc_kind=inputs.MIXED_BC_KIND)
+    o = oracle_mod.Oracle(p)
+    b = o.rhs(p.T0)
+    for k in (1, 2, 3, 5, 8, 13):
+        x1, info = o.cg1(b, p.T0, 1e-300, k)
+        assert info.status == oracle_mod.NOCONV and info.iterations == k
+        xt = _textbook_cg(o.apply, b, p.T0.copy(), k)
+        xc, _ = o.cg(b, p.T0, 1e-300, k)
+        assert rel_l2(x1, xt) <= 1e-12, k
+        assert rel_l2(x1, xc) <= 1e-12, k
+
+
+@pytest.mark.parametrize("shape", [(4, 4, 4), (5, 3, 4)])
+def test_cg1_dense_direct_solve_and_stop_rule(oracle_mod, shape):
+    p = inputs.random_problem(162, *shape, cell=True, bc_kind=inputs.MIXED_BC_KIND)
+    o = oracle_mod.Oracle(p)
+    A = dense_by_columns(o)
+    b = o.rhs(p.T0)
+    x_ref = np.linalg.solve(A, b.ravel()).reshape(p.shape)
+    x, info = o.cg1(b, p.T0, 1e-14, 400)
+    assert info.status == oracle_mod.OK
+    assert rel_l2(x, x_ref) <= 1e-12
+    # the same stop iteration as textbook CG at a looser tolerance
+    _, i1 = o.cg1(b, p.T0, 1e-6, 400)
+    _, ic = o.cg(b, p.T0, 1e-6, 400)
+    assert i1.iterations == ic.iterations and i1.rel_res_recursive <= 1e-6
+    # b = 0 gives x = 0 at once
+    x0, iz = o.cg1(np.zeros_like(b), p.T0, 1e-10, 10)
+    assert iz.status == oracle_mod.OK and iz.iterations == 0 and not x0.any()
