@@ -25,7 +25,7 @@ Other workloads (--workload): heat32 (32^3, 10 steps), poisson_large
 (512x512x1024 FP32, 500 iterations), mixed384 (FP32 inside FP64 refinement
 vs FP64), serve (Poisson request stream through the batching server),
 explicit (forward-time steps, one and several per pass), apply (the
-operator alone).  --method cg applies to the symmetric workloads.
+operator alone).  --method cg and cg1 apply to the symmetric workloads.
 """
 import argparse
 import hashlib
@@ -87,6 +87,7 @@ def load_traffic(kernel: str):
 KERNEL_PATTERNS = (("PhAC<", "phase_ac"), ("PhB2<", "phase_b2"), ("PhA<", "phase_a"),
                    ("PhB<", "phase_b"), ("k_phase_c<", "phase_c"), ("PhInit<", "init"),
                    ("PhResid<", "residual"), ("PhCgA<", "cg_a"), ("k_cg_b<", "cg_b"),
+                   ("PhCg1<", "cg1"),
                    ("PhExplicit<", "explicit"), ("PhApply<", "apply"), ("k_copy", "copy"))
 COPY_PROBE_BYTES = 1 << 30   # --probe-copy: one copy of this many bytes (read and written)
 
@@ -230,7 +231,7 @@ def percentile(vals, q):
 
 def run_convdiff(args, torch, inputs, wfa):
     """The headline workload: 256^3 convection-diffusion time steps."""
-    if args.method == "cg":
+    if args.method in ("cg", "cg1"):
         raise SystemExit("CG needs a symmetric operator; the convection-diffusion workload is not")
     prob = inputs.convdiff(n=args.n)
     prec = wfa.PRECISIONS[args.precision]
@@ -472,7 +473,7 @@ def run_poisson_large(args, torch, inputs, wfa):
         if n:
             kernels[name] = {"us_avg": round(ms / n * 1e3, 1), "gbps": round(by / (ms / n * 1e-3) / 1e9, 1)}
     streams = streams_of(args)
-    kappa_reads = 1 if args.method == "cg" else 2     # diffusivity reads: one per operator product
+    kappa_reads = 1 if args.method in ("cg", "cg1") else 2   # one per operator product
     bytes_iter = (streams * 4 + 4 * kappa_reads) * prob.cells
     return {"workload": "poisson_512x512x1024_f32_500it", "method": args.method,
             "shadow": args.shadow if args.method == "bicgstab2" else "r0",
@@ -637,8 +638,8 @@ def run_explicit(args, torch, inputs, wfa):
     return out
 
 
-METHODS = {"bicgstab": 0, "cg": 1, "bicgstab2": 2}
-STREAMS = {"bicgstab": 17, "cg": 10, "bicgstab2": 14}
+METHODS = {"bicgstab": 0, "cg": 1, "bicgstab2": 2, "cg1": 3}
+STREAMS = {"bicgstab": 17, "cg": 10, "bicgstab2": 14, "cg1": 10}
 
 
 def streams_of(args) -> int:
@@ -656,8 +657,10 @@ def main():
     ap.add_argument("--workload", default="convdiff",
                     choices=["convdiff", "heat32", "poisson_large", "mixed384", "serve", "explicit",
                              "apply"])
-    ap.add_argument("--method", default="bicgstab2", choices=["bicgstab", "bicgstab2", "cg"],
-                    help="cg: the symmetric workloads only (poisson_large, heat32)")
+    ap.add_argument("--method", default="bicgstab2",
+                    choices=["bicgstab", "bicgstab2", "cg", "cg1"],
+                    help="cg, cg1 (one reduction per iteration): the symmetric workloads only "
+                         "(poisson_large, heat32)")
     ap.add_argument("--shadow", default="hashed", choices=["r0", "hashed"],
                     help="shadow residual of the two-reduction BiCGStab: r0 (stored) or a "
                          "field hashed from the cell index (computed, one stream less per pass)")

@@ -72,8 +72,11 @@ enum { WFA_BC_DIRICHLET = 0, WFA_BC_ZEROFLUX = 1 };
 enum {
   WFA_METHOD_BICGSTAB = 0,   /* textbook BiCGStab: 3 reductions per iteration     */
   WFA_METHOD_CG = 1,         /* classic CG (u == 0): 2 reductions per iteration   */
-  WFA_METHOD_BICGSTAB2 = 2   /* BiCGStab reorganised to 2 reductions and 2 passes
+  WFA_METHOD_BICGSTAB2 = 2,  /* BiCGStab reorganised to 2 reductions and 2 passes
                                 per iteration (same iterates in exact arithmetic) */
+  WFA_METHOD_CG1 = 3         /* CG with 1 reduction and 1 pass per iteration
+                                (Chronopoulos-Gear; u == 0; CG's iterates in
+                                exact arithmetic)                               */
 };
 
 /* ---- problem description --------------------------------------------------- */
@@ -150,6 +153,22 @@ int wfa_bicgstab_solve(wfa_grid* g, const void* b, void* x, double tol, int maxi
 int wfa_cg_solve(wfa_grid* g, const void* b, void* x, double tol, int maxit,
                  wfa_solve_info* info, void* stream);
 
+/* Conjugate gradients reorganised to one global reduction per iteration
+ * (Chronopoulos-Gear: w = A r and the pair (r,r), (w,r) give alpha and beta
+ * by recurrence; s = A p is carried as a vector).  The update of each
+ * iteration is applied on the fly inside the next operator pass, so an
+ * iteration is one pass over the grid and one reduction.  The paper solves
+ * its symmetric systems with CG (section 1.1.2) and finds each iteration's
+ * global reductions to set its cost at scale (section 3.2.2); on small grids
+ * an iteration here is bound by the same latency, so halving the passes and
+ * reductions halves it.
+ * Same iterates as wfa_cg_solve in exact arithmetic.  Same contract as
+ * wfa_bicgstab_solve; WFA_F64 / WFA_F32 grids, u == 0, no Jacobi scaling
+ * (WFA_ERR_INVALID otherwise).  A non-positive (p, A p) denominator ends the
+ * solve with WFA_ERR_BREAKDOWN. */
+int wfa_cg1_solve(wfa_grid* g, const void* b, void* x, double tol, int maxit,
+                  wfa_solve_info* info, void* stream);
+
 /* BiCGStab with two global reductions per iteration: the x and r update of
  * each iteration is applied on the fly inside the next operator pass, and
  * the next rho is predicted from (rh,s) - omega (rh,t) so that beta is
@@ -184,9 +203,9 @@ int wfa_true_residual(wfa_grid* g, const void* b, const void* x, double* rel, vo
 
 /* ---- options and instrumentation -------------------------------------------- */
 enum {
-  WFA_OPT_METHOD = 1,          /* WFA_METHOD_BICGSTAB (default), _CG or
-                                  _BICGSTAB2 (used by wfa_timestep; the
-                                  *_solve entry points name their method)   */
+  WFA_OPT_METHOD = 1,          /* WFA_METHOD_BICGSTAB (default), _CG,
+                                  _BICGSTAB2 or _CG1 (used by wfa_timestep;
+                                  the *_solve entry points name their method) */
   WFA_OPT_PERSISTENT = 2,      /* 0: one launch per phase (default),
                                   1: one persistent launch per solve chunk,
                                   -1: automatic by grid size                   */
@@ -247,7 +266,7 @@ enum {
   WFA_K_APPLY = 0, WFA_K_INIT = 1, WFA_K_PHASE_A = 2, WFA_K_PHASE_B = 3,
   WFA_K_PHASE_C = 4, WFA_K_RESIDUAL = 5, WFA_K_PROMOTE = 6, WFA_K_CG_A = 7,
   WFA_K_CG_B = 8, WFA_K_PERSISTENT = 9, WFA_K_PHASE_AC = 10, WFA_K_PHASE_B2 = 11,
-  WFA_K_EXPLICIT = 12, WFA_K_EXPLICIT_FUSED = 13, WFA_K_COUNT = 14
+  WFA_K_EXPLICIT = 12, WFA_K_EXPLICIT_FUSED = 13, WFA_K_CG1 = 14, WFA_K_COUNT = 15
 };
 /* With WFA_OPT_PROFILE on: launches and summed event time (ms) of one
  * kernel since the last reset; `bytes` = algorithmic HBM bytes per launch

@@ -222,7 +222,8 @@ extern "C" int wfa_grid_set_option(wfa_grid* g, int option, int64_t value) {
   if (!g) return set_error(WFA_ERR_INVALID, "grid is NULL");
   switch (option) {
     case WFA_OPT_METHOD:
-      if (value != WFA_METHOD_BICGSTAB && value != WFA_METHOD_CG && value != WFA_METHOD_BICGSTAB2)
+      if (value != WFA_METHOD_BICGSTAB && value != WFA_METHOD_CG &&
+          value != WFA_METHOD_BICGSTAB2 && value != WFA_METHOD_CG1)
         return set_error(WFA_ERR_INVALID, "bad method %lld", (long long)value);
       g->method = (int)value;
       return WFA_OK;
@@ -385,6 +386,7 @@ static double bytes_per_cell(const wfa_grid* g, int kernel) {
     case WFA_K_EXPLICIT: return 2 * w + k;
     case WFA_K_EXPLICIT_FUSED: return 2 * w;  // one read, one write per pass
     case WFA_K_PHASE_B2: return (g->shadow ? 3 : 4) * wi + k;
+    case WFA_K_CG1: return 10 * wi + k;  // r w s p x read; r' w' s' p x written
     default: return 0.0;
   }
 }
@@ -883,6 +885,46 @@ static int iterate_cg(wfa_grid* g, const Launch<T>& L, T* x, T* r, T** d, T* q, 
   return WFA_OK;
 }
 
+// CG with one reduction per iteration: one pass per iteration.  r, w and s
+// are read on the halo, so each is double-buffered ([par] in, [par ^ 1]
+// out); p and x are only touched at the own cell and are updated in place.
+// The first pass after init only forms w0 = A r0 (and copies r0 across), so
+// maxit iterations take maxit + 1 passes.
+template <typename T>
+static int iterate_cg1(wfa_grid* g, const Launch<T>& L, T* x, T** r, T** w, T** sv, T* p,
+                       Scalars* h, ChunkTail* tail, int hint) {
+  int par = 0;
+  int rc = WFA_OK;
+  while (h->status == ST_RUN) {
+    // passes still needed: the iterations left, and w0 = A r0 if not formed
+    const int m = next_chunk(g, *h, h->maxit - h->iter + (h->stage == 0 ? 1 : 0), hint);
+    int k = 0;
+    if (use_graph(g) && m >= kGraphIters) {
+      uint64_t key[GraphCache::kKey];
+      graph_key<T>(key, g, L, 3, par, {x, r[0], r[1], w[0], w[1], sv[0], sv[1], p});
+      const int p0 = par;
+      rc = replay<T>(g, L, key, m / kGraphIters, [&](const Launch<T>& Lc) {
+        int pp = p0;
+        for (int j = 0; j < kGraphIters; ++j, pp ^= 1)
+          launch_phase_cg1<T>(Lc, r[pp], w[pp], sv[pp], p, x, r[pp ^ 1], w[pp ^ 1], sv[pp ^ 1]);
+      });
+      if (rc) return rc;
+      k = m - m % kGraphIters;
+    }
+    for (; k < m; ++k) {
+      {
+        ProfScope ps(g, WFA_K_CG1, L.stream);
+        launch_phase_cg1<T>(L, r[par], w[par], sv[par], p, x, r[par ^ 1], w[par ^ 1],
+                            sv[par ^ 1]);
+      }
+      par ^= 1;
+    }
+    if ((rc = check_launch("cg1"))) return rc;
+    if ((rc = read_chunk(g, L.sc, h, L.stream, tail))) return rc;
+  }
+  return WFA_OK;
+}
+
 static Scalars fresh_scalars(double tol, int maxit, int force_bd) {
   Scalars h{};
   h.tol = tol;
@@ -956,8 +998,12 @@ static int solve_plain(wfa_grid* g, const T* b_user, T* x, bool form_b, double t
   int rpar = 0;
   ChunkTail* tp = use_tail ? &tail : nullptr;
   const int hint = g->hint_iters;
-  if (g->method == WFA_METHOD_CG)
+  if (g->method == WFA_METHOD_CG) {
     rc = iterate_cg<T>(g, L, x, r, p, t, &h, tp, hint);
+  } else if (g->method == WFA_METHOD_CG1) {
+    T* w[2] = {v[0], v[1]};
+    rc = iterate_cg1<T>(g, L, x, rbuf, w, p, t, &h, tp, hint);
+  }
   else if (g->method == WFA_METHOD_BICGSTAB2)
     rc = iterate_bicgstab2<T>(g, L, x, rbuf, rh, p, v, t, b, &h, &restarts, &rpar, true, tp, hint);
   else
@@ -1147,9 +1193,10 @@ static int validate_solve(wfa_grid* g, const void* b, void* x, double tol, int m
 namespace wfa {
 int solve_any(wfa_grid* g, const void* b, void* x, bool form_b, double tol, int maxit,
               wfa_solve_info* info, hipStream_t s) {
-  if (g->method == WFA_METHOD_CG && (g->c.u[0] != 0.0 || g->c.u[1] != 0.0 || g->c.u[2] != 0.0))
+  const bool cg = g->method == WFA_METHOD_CG || g->method == WFA_METHOD_CG1;
+  if (cg && (g->c.u[0] != 0.0 || g->c.u[1] != 0.0 || g->c.u[2] != 0.0))
     return set_error(WFA_ERR_INVALID, "CG needs a symmetric operator (u == 0)");
-  if (g->jacobi && (g->method == WFA_METHOD_CG || g->prec == WFA_F32_IR64))
+  if (g->jacobi && (cg || g->prec == WFA_F32_IR64))
     return set_error(WFA_ERR_INVALID,
                      "Jacobi scaling is available for BiCGStab on WFA_F64 / WFA_F32 grids");
   switch (g->prec) {
@@ -1157,7 +1204,7 @@ int solve_any(wfa_grid* g, const void* b, void* x, bool form_b, double tol, int 
     case WFA_F32: return solve_plain<float>(g, (const float*)b, (float*)x, form_b, tol, maxit, info, s);
     default:
       // the inner solve is always the two-reduction BiCGStab
-      if (g->method == WFA_METHOD_CG)
+      if (cg)
         return set_error(WFA_ERR_INVALID, "WFA_F32_IR64 grids iterate with BiCGStab, not CG");
       return solve_ir(g, (const double*)b, (double*)x, form_b, tol, maxit, info, s);
   }
@@ -1192,6 +1239,17 @@ extern "C" int wfa_cg_solve(wfa_grid* g, const void* b, void* x, double tol, int
   if (rc) return rc;
   const int saved = g->method;
   g->method = WFA_METHOD_CG;
+  rc = solve_any(g, b, x, false, tol, maxit, info, (hipStream_t)stream);
+  g->method = saved;
+  return rc;
+}
+
+extern "C" int wfa_cg1_solve(wfa_grid* g, const void* b, void* x, double tol, int maxit,
+                             wfa_solve_info* info, void* stream) {
+  int rc = validate_solve(g, b, x, tol, maxit);
+  if (rc) return rc;
+  const int saved = g->method;
+  g->method = WFA_METHOD_CG1;
   rc = solve_any(g, b, x, false, tol, maxit, info, (hipStream_t)stream);
   g->method = saved;
   return rc;

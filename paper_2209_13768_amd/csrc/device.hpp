@@ -50,7 +50,8 @@ struct alignas(64) Scalars {
   int32_t diverged;            // set with ST_NOCONV when the guard tripped
   int32_t it_min;              // ... and the iteration that reached it
   int32_t force_div;           // n > 0: declare the solve diverged at iteration n (test hook)
-  int32_t pad[3];
+  int32_t stage;               // CG with one reduction: 0 w0 = A r0, 1 first update, 2 steady
+  int32_t pad[2];
 };
 static_assert(sizeof(Scalars) == 192, "the scalar block is three 64-byte lines");
 

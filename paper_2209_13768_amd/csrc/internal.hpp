@@ -71,6 +71,13 @@ void launch_phase_ac(const Launch<T>& L, const T* r, const T* v, const T* t, con
 // pass 2: s = r - alpha v; t = A s; (t,s), (t,t), (rh,s), (rh,t)
 template <typename T>
 void launch_phase_b2(const Launch<T>& L, const T* r, const T* v, const T* rh, T* t);
+// One iteration of CG with one reduction (Chronopoulos-Gear): the previous
+// update applied on the fly (p, x in place; s' into s_out, r' into r_out),
+// w' = A r' into w_out; (r', r') and (w', r') reduced.  Stage 0 (after
+// init) only forms w0 = A r0 and copies r through.
+template <typename T>
+void launch_phase_cg1(const Launch<T>& L, const T* r, const T* w, const T* s, T* p, T* x,
+                      T* r_out, T* w_out, T* s_out);
 // CG: d' = r + beta d (d' = r first); q = A d'; (d', q)
 template <typename T>
 void launch_cg_a(const Launch<T>& L, const T* r, const T* d, T* d_out, T* q);

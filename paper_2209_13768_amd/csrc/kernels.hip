@@ -152,6 +152,15 @@ void launch_phase_b2(const Launch<T>& L, const T* r, const T* v, const T* rh, T*
 }
 
 template <typename T>
+void launch_phase_cg1(const Launch<T>& L, const T* r, const T* w, const T* s, T* p, T* x,
+                      T* r_out, T* w_out, T* s_out) {
+  PhCg1<T> ph{};
+  ph.r = r; ph.w = w; ph.s = s; ph.p = p; ph.x = x;
+  ph.r_out = r_out; ph.w_out = w_out; ph.s_out = s_out;
+  dispatch_march(L, ph, FinCg1{L.sc}, true, true);
+}
+
+template <typename T>
 void launch_cg_a(const Launch<T>& L, const T* r, const T* d, T* d_out, T* q) {
   PhCgA<T> ph{};
   ph.r = r; ph.d = d; ph.d_out = d_out; ph.q = q;
@@ -347,6 +356,8 @@ Tiling make_tiling(int nx, int ny, int nz, int elem_bytes, int zc_override, int 
   template void launch_phase_ac<T>(const Launch<T>&, const T*, const T*, const T*, const T*, \
                                    const T*, T*, T*, T*, T*);                                \
   template void launch_phase_b2<T>(const Launch<T>&, const T*, const T*, const T*, T*);      \
+  template void launch_phase_cg1<T>(const Launch<T>&, const T*, const T*, const T*, T*, T*,  \
+                                    T*, T*, T*);                                             \
   template void launch_cg_b<T>(const Launch<T>&, T*, const T*, T*, const T*);                \
   template void launch_fill<T>(size_t, T*, T, hipStream_t);
 WFA_INST(double)

@@ -43,7 +43,7 @@ struct FinInit {
     sc->bb = bb; sc->rr = rr; sc->rr0 = rr;
     sc->rho = rho; sc->rho_prev = 1.0; sc->alpha = 1.0; sc->omega = 1.0; sc->beta = 0.0;
     sc->first = 1; sc->restart = 0; sc->szero = 0; sc->restart_pending = 0;
-    sc->rr_min = rr; sc->it_min = 0;
+    sc->rr_min = rr; sc->it_min = 0; sc->stage = 0;
     if (!fin_ok(bb) || !fin_ok(rr) || !fin_ok(rho)) sc->status = ST_NONFINITE;
     else if (bb == 0.0) sc->status = ST_BZERO;
     else if (sqrt(rr) <= sc->tol * sqrt(bb)) sc->status = ST_CONV;
@@ -128,6 +128,41 @@ struct FinCgB {
       sc->rho = rr;
       sc->first = 0;
     }
+  }
+};
+
+// CG with one reduction per iteration (Chronopoulos-Gear), after its pass:
+// gamma = (r, r), delta = (A r, r) of the iterate the pass produced.  The
+// pass of stage 0 only formed w0 = A r0: alpha0 = gamma / delta.  Later
+// passes apply one iteration each: convergence and limits on gamma, then
+// beta = gamma / gamma_old and alpha = gamma / (delta - beta gamma / alpha_old)
+// for the update the next pass applies.  A step denominator that is not
+// positive means A is not positive definite: ST_BREAKDOWN, as for CG.
+struct FinCg1 {
+  Scalars* sc;
+  __device__ void operator()(const double (&s)[2]) const {
+    const double gamma = s[0], delta = s[1];
+    sc->sigma = delta;
+    if (!fin_ok(gamma) || !fin_ok(delta)) { sc->status = ST_NONFINITE; return; }
+    if (sc->stage == 0) {
+      if (!(delta > 0.0)) { sc->status = ST_BREAKDOWN; return; }
+      sc->alpha = gamma / delta;
+      sc->beta = 0.0;
+      sc->rho = gamma;
+      sc->stage = 1;
+      return;
+    }
+    sc->iter += 1;
+    sc->rr = gamma;
+    if (sqrt(gamma) <= sc->tol * sqrt(sc->bb)) { sc->status = ST_CONV; return; }
+    if (sc->iter >= sc->maxit) { sc->status = ST_NOCONV; return; }
+    const double beta = gamma / sc->rho;
+    const double denom = delta - beta * gamma / sc->alpha;
+    if (!(denom > 0.0)) { sc->status = ST_BREAKDOWN; return; }
+    sc->alpha = gamma / denom;
+    sc->beta = beta;
+    sc->rho = gamma;
+    sc->stage = 2;
   }
 };
 
@@ -541,6 +576,83 @@ struct PhB2 {
     acc[1] += (double)Au * (double)Au;
     acc[2] += (double)e.rh * (double)s;
     acc[3] += (double)e.rh * (double)Au;
+  }
+};
+
+// ============================================================================
+// CG with one reduction per iteration (Chronopoulos-Gear)
+// ============================================================================
+// One pass per iteration.  It applies the previous iteration's update on the
+// fly, s' = w + beta s, p' = r + beta p, x' = x + alpha p', r' = r - alpha s'
+// (stage 1: p' = r, s' = w), stages r' (with halo, from r, w, s) for
+// w' = A r', and reduces (r', r') and (w', r').  Stage 0 stages r itself
+// (copied through so the r buffers alternate) and only forms w0 = A r0.
+// r, w and s are read on neighbour cells and double-buffered; p and x are
+// read and written on own cells only, in place.
+template <typename T>
+struct PhCg1 {
+  static constexpr int NV = 2;
+  static constexpr int PD = 2;
+  using St = T;
+  static __device__ __forceinline__ T val(T u) { return u; }
+  const T* __restrict__ r;
+  const T* __restrict__ w;
+  const T* __restrict__ s;
+  T* __restrict__ p;
+  T* __restrict__ x;
+  T* __restrict__ r_out;
+  T* __restrict__ w_out;
+  T* __restrict__ s_out;
+  T alpha, beta;
+  int stage;
+  struct Raw { T r, w, s; };
+  struct ORaw { T r, w, s, p, x; };
+  struct ERaw {};
+  __device__ void bind(const Scalars* sc) {
+    alpha = (T)sc->alpha;
+    beta = (T)sc->beta;
+    stage = sc->stage;
+  }
+  // s' of this cell (the same expression for own and halo cells, so both
+  // stage the same r')
+  __device__ T s_new(T w_, T s_) const { return stage == 1 ? w_ : fma_t(beta, s_, w_); }
+  __device__ T r_new(T r_, T sn) const { return fma_t(-alpha, sn, r_); }
+  __device__ Raw fetch(size_t i) const {
+    if (stage == 0) return {r[i], T(0), T(0)};
+    if (stage == 1) return {r[i], w[i], T(0)};
+    return {r[i], w[i], s[i]};
+  }
+  __device__ T combine(const Raw& q) const {
+    if (stage == 0) return q.r;
+    return r_new(q.r, s_new(q.w, q.s));
+  }
+  __device__ ORaw fetch_own(size_t i) const {
+    if (stage == 0) return {r[i], T(0), T(0), T(0), T(0)};
+    if (stage == 1) return {r[i], w[i], T(0), T(0), ld_once(x + i)};
+    return {r[i], w[i], s[i], ld_once(p + i), ld_once(x + i)};
+  }
+  __device__ St combine_own(const ORaw& q, size_t i, double (&acc)[NV]) const {
+    T rn;
+    if (stage == 0) {
+      rn = q.r;
+    } else {
+      const T sn = s_new(q.w, q.s);
+      const T pn = stage == 1 ? q.r : fma_t(beta, q.p, q.r);
+      rn = r_new(q.r, sn);
+      st_once(s_out + i, sn);
+      st_once(p + i, pn);
+      st_once(x + i, fma_t(alpha, pn, q.x));
+    }
+    st_once(r_out + i, rn);
+    acc[0] += (double)rn * (double)rn;
+    return rn;
+  }
+  __device__ T value_own(const ORaw& q) const { return combine(Raw{q.r, q.w, q.s}); }
+  __device__ ERaw efetch(size_t) const { return {}; }
+  __device__ void epilogue(size_t i, T rn, T Au, T, uint32_t, const ERaw&, T dg,
+                           double (&acc)[NV]) const {
+    st_once(w_out + i, Au);
+    acc[1] += (double)Au * (double)rn;
   }
 };
 

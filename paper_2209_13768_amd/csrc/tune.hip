@@ -185,7 +185,8 @@ extern "C" int wfa_autotune(wfa_grid* g, int method, void* x, void* b, int iters
                             wfa_tune_result* out, void* stream) {
   if (!g || !x || !b || !out) return set_error(WFA_ERR_INVALID, "NULL argument");
   if (iters < 1 || iters > 10000) return set_error(WFA_ERR_INVALID, "iters must be 1..10000");
-  if (method != WFA_METHOD_BICGSTAB && method != WFA_METHOD_CG && method != WFA_METHOD_BICGSTAB2)
+  if (method != WFA_METHOD_BICGSTAB && method != WFA_METHOD_CG && method != WFA_METHOD_BICGSTAB2 &&
+      method != WFA_METHOD_CG1)
     return set_error(WFA_ERR_INVALID, "bad method %d", method);
   hipStream_t s = (hipStream_t)stream;
   hipEvent_t e0 = nullptr, e1 = nullptr;

@@ -20,22 +20,23 @@ ERR_INVALID, ERR_NOMEM, ERR_HIP, ERR_BREAKDOWN, ERR_NOCONV, ERR_NONFINITE = -1, 
 F64, F32, F32_IR64 = 0, 1, 2
 COEF_CONST, COEF_CELL = 0, 1
 BC_DIRICHLET, BC_ZEROFLUX = 0, 1
-METHOD_BICGSTAB, METHOD_CG, METHOD_BICGSTAB2 = 0, 1, 2
+METHOD_BICGSTAB, METHOD_CG, METHOD_BICGSTAB2, METHOD_CG1 = 0, 1, 2, 3
 OPT_METHOD, OPT_PERSISTENT, OPT_PROFILE, OPT_FORCE_BREAKDOWN, OPT_CHECK_EVERY = 1, 2, 3, 4, 5
 OPT_IR_INNER_TOL, OPT_ZCHUNK, OPT_RY, OPT_JACOBI, OPT_GRAPH = 6, 7, 8, 9, 10
 OPT_EXPLICIT_FUSE, OPT_SHADOW, OPT_FORCE_DIVERGE = 11, 12, 13
 K_APPLY, K_INIT, K_PHASE_A, K_PHASE_B, K_PHASE_C, K_RESIDUAL, K_PROMOTE = 0, 1, 2, 3, 4, 5, 6
 K_CG_A, K_CG_B, K_PERSISTENT, K_PHASE_AC, K_PHASE_B2, K_EXPLICIT = 7, 8, 9, 10, 11, 12
-K_EXPLICIT_FUSED, K_COUNT = 13, 14
+K_EXPLICIT_FUSED, K_CG1, K_COUNT = 13, 14, 15
 KERNEL_NAMES = ("apply", "init", "phase_a", "phase_b", "phase_c", "residual", "promote",
-                "cg_a", "cg_b", "persistent", "phase_ac", "phase_b2", "explicit", "explicit_fused")
+                "cg_a", "cg_b", "persistent", "phase_ac", "phase_b2", "explicit", "explicit_fused",
+                "cg1")
 
 PRECISIONS = {"f64": F64, "f32": F32, "f32_ir64": F32_IR64}
 
 # Every function the header declares; the library must export all of them.
 EXPORTS = (
     "wfa_workspace_bytes", "wfa_grid_create", "wfa_grid_destroy", "wfa_stencil_apply",
-    "wfa_rhs", "wfa_explicit_step", "wfa_bicgstab_solve", "wfa_bicgstab2_solve", "wfa_cg_solve", "wfa_timestep", "wfa_true_residual",
+    "wfa_rhs", "wfa_explicit_step", "wfa_bicgstab_solve", "wfa_bicgstab2_solve", "wfa_cg_solve", "wfa_cg1_solve", "wfa_timestep", "wfa_true_residual",
     "wfa_grid_set_option", "wfa_kernel_stats", "wfa_grid_tiling", "wfa_stream_probe",
     "wfa_server_create", "wfa_server_set_option", "wfa_submit", "wfa_poll", "wfa_server_drain",
     "wfa_server_destroy",
@@ -116,6 +117,7 @@ def lib() -> ctypes.CDLL:
     L.wfa_explicit_step.argtypes = [vp, vp, i32, vp]
     L.wfa_bicgstab_solve.argtypes = [vp, vp, vp, dbl, i32, ctypes.POINTER(_Info), vp]
     L.wfa_cg_solve.argtypes = [vp, vp, vp, dbl, i32, ctypes.POINTER(_Info), vp]
+    L.wfa_cg1_solve.argtypes = [vp, vp, vp, dbl, i32, ctypes.POINTER(_Info), vp]
     L.wfa_bicgstab2_solve.argtypes = [vp, vp, vp, dbl, i32, ctypes.POINTER(_Info), vp]
     L.wfa_timestep.argtypes = [vp, vp, i32, dbl, i32, ctypes.POINTER(_Info), vp]
     L.wfa_true_residual.argtypes = [vp, vp, vp, ctypes.POINTER(dbl), vp]
@@ -275,7 +277,7 @@ class Grid:
         x = self.field() if x is None else x
         info = _Info()
         fn = {"cg": lib().wfa_cg_solve, "bicgstab": lib().wfa_bicgstab_solve,
-              "bicgstab2": lib().wfa_bicgstab2_solve}[method]
+              "bicgstab2": lib().wfa_bicgstab2_solve, "cg1": lib().wfa_cg1_solve}[method]
         rc = fn(self._h, self._v(b, "b"), self._v(x, "x"), float(tol), int(maxit),
                 ctypes.byref(info), _stream_ptr(stream))
         if check:
@@ -301,7 +303,8 @@ class Grid:
         record it for grids of the same key (wfa_autotune)."""
         x, b = self.field(), self.field()
         r = TuneResult()
-        m = {"bicgstab": METHOD_BICGSTAB, "cg": METHOD_CG, "bicgstab2": METHOD_BICGSTAB2}[method]
+        m = {"bicgstab": METHOD_BICGSTAB, "cg": METHOD_CG, "bicgstab2": METHOD_BICGSTAB2,
+             "cg1": METHOD_CG1}[method]
         _check(lib().wfa_autotune(self._h, m, self._v(x, "x"), self._v(b, "b"), int(iters),
                                   ctypes.byref(r), _stream_ptr(stream)))
         return {"ry": r.ry, "zc": r.zc, "candidates": r.candidates, "us_per_iter": r.us_per_iter,

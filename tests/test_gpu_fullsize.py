@@ -6,8 +6,8 @@ shadow residual where the benchmark uses it).
   the whole operator and right-hand side in FP64 and FP32, the first
   iterates against the oracle's same variant, and one backward-Euler step
   whose result the oracle's operator must see at the benchmark's tolerance.
-* 512x512x1024 smooth-diffusivity diffusion in FP32: the whole operator and
-  the first iterate.
+* 512x512x1024 smooth-diffusivity diffusion in FP32: the whole operator, the
+  first iterate, and two iterations of the one-reduction CG.
 * 384^3 convection-diffusion (velocity x4): FP32 inside FP64 refinement to
   1e-12, judged by the oracle's FP64 operator.
 * The serving stream's first requests (their real grid sizes), batched
@@ -123,6 +123,12 @@ def test_poisson_512x512x1024_operator_and_first_iterate(wfa, oracle_mod):
                        check=False)
     assert info.iterations == 1
     assert rel_l2(_np(x1), xo) <= FP32_TOL
+    # the symmetric workload's one-reduction CG: two iterations (the second
+    # pass is the first with the fused update)
+    xc, _ = o.cg1(b, np.zeros_like(b), 1e-300, 2)
+    x2, info = g.solve(g.field(b), g.field(), tol=1e-300, maxit=2, method="cg1", check=False)
+    assert info.iterations == 2
+    assert rel_l2(_np(x2), xc) <= FP32_TOL
 
 
 def test_mixed_precision_384_reaches_1e12(wfa, oracle_mod):
