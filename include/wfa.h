@@ -158,10 +158,10 @@ int wfa_cg_solve(wfa_grid* g, const void* b, void* x, double tol, int maxit,
  * by recurrence; s = A p is carried as a vector).  The update of each
  * iteration is applied on the fly inside the next operator pass, so an
  * iteration is one pass over the grid and one reduction.  The paper solves
- * its symmetric systems with CG (section 1.1.2) and finds each iteration's
- * global reductions to set its cost at scale (section 3.2.2); on small grids
- * an iteration here is bound by the same latency, so halving the passes and
- * reductions halves it.
+ * its symmetric systems with classic CG, two reductions per iteration, and
+ * names those reductions the bottleneck at high parallelism (sections 1.1.2,
+ * 3.2.2), expecting reorganised Krylov forms to gain more (section 5).  On
+ * small grids an iteration here is bound by the same latency.
  * Same iterates as wfa_cg_solve in exact arithmetic.  Same contract as
  * wfa_bicgstab_solve; WFA_F64 / WFA_F32 grids, u == 0, no Jacobi scaling
  * (WFA_ERR_INVALID otherwise).  A non-positive (p, A p) denominator ends the
