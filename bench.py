@@ -537,6 +537,7 @@ def run_serve(args, torch, inputs, wfa):
     sv = wfa.Server(args.budget_gb << 30, max_slots=args.slots)
     sv.set_option(wfa.OPT_PERSISTENT, args.serve_persistent)
     sv.set_option(wfa.OPT_CHECK_EVERY, args.serve_round)
+    sv.set_option(wfa.OPT_METHOD, METHODS[args.serve_method])
     tickets = {}
     t_start = time.perf_counter()
     for q, rq in enumerate(reqs):
@@ -557,7 +558,10 @@ def run_serve(args, torch, inputs, wfa):
         cell_it += rq.nx * rq.ny * rq.nz * info.iterations
         its += info.iterations
     sv.close()
+    # a CG iteration is one operator pass, a BiCGStab iteration two
     return {"workload": f"serve_{args.requests}req_200rps", "precision": args.serve_precision,
+            "method": args.serve_method,
+            "passes_per_iteration": 1 if args.serve_method == "cg1" else 2,
             "round": {"iterations": args.serve_round,
                       "launch": "persistent" if args.serve_persistent else "per pass"},
             "requests": len(reqs), "failed": fails, "makespan_s": t_end,
@@ -680,6 +684,9 @@ def main():
                     help="serve: precision of every request")
     ap.add_argument("--serve-round", type=int, default=4,
                     help="serve: iterations per round between host reads of the scalars")
+    ap.add_argument("--serve-method", default="bicgstab2", choices=["bicgstab2", "cg1"],
+                    help="serve: cg1 = the (symmetric) heat requests iterate with CG with one "
+                         "reduction")
     ap.add_argument("--serve-persistent", type=int, default=0, choices=[0, 1],
                     help="serve: 1 = each round is one cooperative launch per precision")
     ap.add_argument("--no-profile", action="store_true",

@@ -163,9 +163,12 @@ int wfa_cg_solve(wfa_grid* g, const void* b, void* x, double tol, int maxit,
  * 3.2.2), expecting reorganised Krylov forms to gain more (section 5).  On
  * small grids an iteration here is bound by the same latency.
  * Same iterates as wfa_cg_solve in exact arithmetic.  Same contract as
- * wfa_bicgstab_solve; WFA_F64 / WFA_F32 grids, u == 0, no Jacobi scaling
- * (WFA_ERR_INVALID otherwise).  A non-positive (p, A p) denominator ends the
- * solve with WFA_ERR_BREAKDOWN. */
+ * wfa_bicgstab_solve; u == 0 and no Jacobi scaling (WFA_ERR_INVALID
+ * otherwise).  A non-positive (p, A p) denominator ends the solve with
+ * WFA_ERR_BREAKDOWN.  On a WFA_F32_IR64 grid it is the inner FP32 solve of
+ * the refinement, on A itself (BiCGStab's inner solve is Jacobi-scaled); an
+ * inner breakdown there ends the inner solve, and the next refinement
+ * restarts from the FP64 residual. */
 int wfa_cg1_solve(wfa_grid* g, const void* b, void* x, double tol, int maxit,
                   wfa_solve_info* info, void* stream);
 
@@ -334,6 +337,14 @@ int wfa_server_create(void* arena, size_t arena_bytes, int max_slots, void* stre
 /* Server options, applied from the next round on:
  *   WFA_OPT_CHECK_EVERY  iterations per round between the worker's reads of
  *                        the slots' scalars, 1..1024 (default 4);
+ *   WFA_OPT_METHOD       WFA_METHOD_BICGSTAB2 (default) or WFA_METHOD_CG1:
+ *                        requests submitted afterwards with u == 0 iterate
+ *                        with CG with one reduction (the inner solve of
+ *                        WFA_F32_IR64 requests, as wfa_cg1_solve on such a
+ *                        grid), two CG iterations per BiCGStab iteration of
+ *                        a round; other requests keep BiCGStab.  A round with
+ *                        a CG request resident makes one launch per pass
+ *                        whatever WFA_OPT_PERSISTENT says;
  *   WFA_OPT_PERSISTENT   1: each round is one cooperative launch per
  *                        precision, with grid barriers in place of the
  *                        per-pass kernel boundaries (bitwise the same

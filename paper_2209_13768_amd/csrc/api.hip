@@ -1062,11 +1062,14 @@ static int solve_ir(wfa_grid* g, const double* b_user, double* x, bool form_b, d
   float* d = g->d32;
   int rc;
   Launch<double> L64 = plain_ctx<double>(g, g->sc, s);
-  // the inner FP32 solve iterates on the Jacobi-scaled system D^{-1} A d =
+  // the inner FP32 BiCGStab iterates on the Jacobi-scaled system D^{-1} A d =
   // D^{-1} r: far better conditioned when the diffusivity varies by orders
-  // of magnitude, which FP32 BiCGStab needs to make progress at all there
+  // of magnitude, which FP32 BiCGStab needs to make progress at all there.
+  // The inner CG (one reduction) keeps the symmetric A d = r.
+  const bool cg1 = g->method == WFA_METHOD_CG1;
+  float* w[2] = {v[0], v[1]};
   Launch<float> L32 = ctx<float>(g, g->sc_in, s);
-  L32.op.jac = 1;
+  L32.op.jac = cg1 ? 0 : 1;
   L32.shadow = g->shadow;  // the inner solve's shadow residual (as the residual pass wrote it)
   const double* b = b_user;
   if (form_b) {
@@ -1102,7 +1105,7 @@ static int solve_ir(wfa_grid* g, const double* b_user, double* x, bool form_b, d
     if ((rc = write_scalars(&hi, g->sc_in, s))) return rc;
     {
       ProfScope ps(g, WFA_K_RESIDUAL, s);
-      launch_residual<double>(L64, x, b, r, rh, g->sc_in, 2, g->shadow);
+      launch_residual<double>(L64, x, b, r, rh, g->sc_in, cg1 ? 1 : 2, g->shadow);
     }
     if ((rc = check_launch("residual"))) return rc;
     const bool last = ref >= max_ref || total_it >= maxit;
@@ -1120,10 +1123,12 @@ static int solve_ir(wfa_grid* g, const double* b_user, double* x, bool form_b, d
       ChunkTail outer;
       outer.dev = g->sc;
       outer.host = &ho;
-      if ((rc = iterate_bicgstab2<float>(g, L32, d, rbuf, rh, p, v, t, nullptr, &hi,
-                                         &inner_restarts, &inner_par, false, &outer,
-                                         g->hint_iters)))
-        return rc;
+      if (cg1)
+        rc = iterate_cg1<float>(g, L32, d, rbuf, w, p, t, &hi, &outer, g->hint_iters);
+      else
+        rc = iterate_bicgstab2<float>(g, L32, d, rbuf, rh, p, v, t, nullptr, &hi,
+                                      &inner_restarts, &inner_par, false, &outer, g->hint_iters);
+      if (rc) return rc;
       g->hint_iters = hi.status == ST_CONV && !hi.restart && hi.iter > 0 ? hi.iter : 0;
     }
     if (ho.status != ST_RUN) {
@@ -1203,9 +1208,10 @@ int solve_any(wfa_grid* g, const void* b, void* x, bool form_b, double tol, int 
     case WFA_F64: return solve_plain<double>(g, (const double*)b, (double*)x, form_b, tol, maxit, info, s);
     case WFA_F32: return solve_plain<float>(g, (const float*)b, (float*)x, form_b, tol, maxit, info, s);
     default:
-      // the inner solve is always the two-reduction BiCGStab
-      if (cg)
-        return set_error(WFA_ERR_INVALID, "WFA_F32_IR64 grids iterate with BiCGStab, not CG");
+      // the inner solve is the two-reduction BiCGStab, or CG with one reduction
+      if (g->method == WFA_METHOD_CG)
+        return set_error(WFA_ERR_INVALID,
+                         "WFA_F32_IR64 grids iterate with BiCGStab or the one-reduction CG");
       return solve_ir(g, (const double*)b, (double*)x, form_b, tol, maxit, info, s);
   }
 }

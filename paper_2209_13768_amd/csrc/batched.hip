@@ -35,6 +35,21 @@ k_batch_march(const SolveDesc<T>* __restrict__ descs, const int* __restrict__ ba
   Scalars* sc = d.sc;
   if (sc->status != ST_RUN || sc->restart) return;
   const int tile = blockIdx.x - bases[s];
+  if (d.cg1) {
+    // two CG iterations per launch pair: the pair returns the buffers to
+    // where they started, whatever the launch's place in a round
+    const int pp = PASS ^ d.par;
+    PhCg1<T> ph{};
+    ph.r = pp ? d.r1 : d.r; ph.w = pp ? d.v1 : d.v0; ph.s = pp ? d.p1 : d.p0;
+    ph.p = d.t; ph.x = d.x;
+    ph.r_out = pp ? d.r : d.r1; ph.w_out = pp ? d.v0 : d.v1; ph.s_out = pp ? d.p0 : d.p1;
+    ph.bind(sc);
+    double acc[2] = {0.0, 0.0};
+    if (d.cell) march_tile<T, true, RY>(d.geo, d.op, d.kappa, tile, ph, acc, su, sk);
+    else march_tile<T, false, RY>(d.geo, d.op, d.kappa, tile, ph, acc, su, sk);
+    publish_and_finalize<2>(acc, tile, d.geo.ntiles, d.partials, sc, red, FinCg1{sc});
+    return;
+  }
   parity ^= d.par;
   T* r_in = parity ? d.r1 : d.r;
   T* r_out = parity ? d.r : d.r1;

@@ -16,6 +16,9 @@ struct SolveDesc {
   T* r1;                // second residual buffer of the two-reduction BiCGStab
   int par;              // buffer parity of the solve at the first iteration of the launch
   int hashed;           // shadow residual hashed from the cell index (not stored)
+  int cg1;              // 1: CG with one reduction (symmetric A): each of the two passes
+                        // is one CG iteration; r (r, r1), w (v0, v1) and s (p0, p1)
+                        // alternate per pass, p in t; parity 0 at the first pass
   double* partials;
   Scalars* sc;
   size_t n;
@@ -24,7 +27,7 @@ struct SolveDesc {
 };
 
 // One two-reduction BiCGStab iteration (passes AC and B2) of every solve in
-// descs[0..nsolves).  tile_bases: prefix sums of the solves' tile counts
+// descs[0..nsolves), or two iterations of a solve marked cg1.  tile_bases: prefix sums of the solves' tile counts
 // (nsolves + 1 entries, device memory); every solve's tiling must use `ry`
 // rows per wave.  Solve s uses the buffers of parity descs[s].par ^ (q & 1),
 // q = the index of this iteration among the launches made since the

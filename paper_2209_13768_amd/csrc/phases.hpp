@@ -154,7 +154,15 @@ struct FinCg1 {
     }
     sc->iter += 1;
     sc->rr = gamma;
+    sc->x_zero = 0;
+    if (gamma < sc->rr_min) { sc->rr_min = gamma; sc->it_min = sc->iter; }
     if (sqrt(gamma) <= sc->tol * sqrt(sc->bb)) { sc->status = ST_CONV; return; }
+    // the divergence guard of an inner refinement solve (as for BiCGStab)
+    if ((sc->guard > 0.0 && gamma > sc->guard * sc->rr0) || sc->iter == sc->force_div) {
+      sc->status = ST_NOCONV;
+      sc->diverged = 1;
+      return;
+    }
     if (sc->iter >= sc->maxit) { sc->status = ST_NOCONV; return; }
     const double beta = gamma / sc->rho;
     const double denom = delta - beta * gamma / sc->alpha;
@@ -182,7 +190,7 @@ struct FinResid {
       inner->rho = rho; inner->rho_prev = 1.0; inner->alpha = 1.0; inner->omega = 1.0;
       inner->beta = 0.0; inner->first = 1; inner->restart = 0; inner->szero = 0;
       inner->x_zero = 1; inner->iter = 0; inner->diverged = 0;
-      inner->rr_min = r2; inner->it_min = 0;
+      inner->rr_min = r2; inner->it_min = 0; inner->stage = 0;
       if (sc->status != ST_RUN) inner->status = ST_CONV;
       else if (!fin_ok(r2) || !fin_ok(rho)) inner->status = ST_NONFINITE;
       else if (r2 == 0.0) inner->status = ST_CONV;
@@ -605,6 +613,7 @@ struct PhCg1 {
   T* __restrict__ s_out;
   T alpha, beta;
   int stage;
+  int x_zero;      // x is still the zero initial guess (refinement's correction)
   struct Raw { T r, w, s; };
   struct ORaw { T r, w, s, p, x; };
   struct ERaw {};
@@ -612,6 +621,7 @@ struct PhCg1 {
     alpha = (T)sc->alpha;
     beta = (T)sc->beta;
     stage = sc->stage;
+    x_zero = sc->x_zero;
   }
   // s' of this cell (the same expression for own and halo cells, so both
   // stage the same r')
@@ -628,7 +638,7 @@ struct PhCg1 {
   }
   __device__ ORaw fetch_own(size_t i) const {
     if (stage == 0) return {r[i], T(0), T(0), T(0), T(0)};
-    if (stage == 1) return {r[i], w[i], T(0), T(0), ld_once(x + i)};
+    if (stage == 1) return {r[i], w[i], T(0), T(0), x_zero ? T(0) : ld_once(x + i)};
     return {r[i], w[i], s[i], ld_once(p + i), ld_once(x + i)};
   }
   __device__ St combine_own(const ORaw& q, size_t i, double (&acc)[NV]) const {

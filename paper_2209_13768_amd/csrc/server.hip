@@ -99,6 +99,7 @@ struct Request {
   int total_it = 0, refinements = 0, restarts = 0;
   int inner_cap = 0;  // > 0: repeating a diverged inner solve up to its best iterate
   int par = 0;        // buffer parity of the next iteration (0 after every (re)start)
+  int cg1 = 0;        // 1: iterates with CG with one reduction (symmetric request)
   double scale = 1.0;
   double last_rec = 0.0;
   double t_submit = 0.0, t_done = 0.0;
@@ -144,6 +145,7 @@ struct wfa_server {
   char worker_msg[256] = "";
   int chunk = 4;      // iterations per round (WFA_OPT_CHECK_EVERY)
   int persistent = 0; // 1: a round is one cooperative launch per precision (WFA_OPT_PERSISTENT)
+  int method = WFA_METHOD_BICGSTAB2;  // WFA_OPT_METHOD: _CG1 for symmetric requests
   int ry = 0;        // rows per wave of every resident solve's tiling
   std::thread worker;
 };
@@ -198,8 +200,9 @@ SolveDesc<T> make_desc(Request* r, T* x) {
   const Tiling& tl = (sizeof(T) == 4 && g.prec == WFA_F32_IR64) ? g.tl32 : g.tl;
   d.geo = tl.geo;
   if constexpr (sizeof(T) == 4) d.op = g.op32; else d.op = g.op64;
-  // the inner FP32 solve of refinement iterates on D^{-1} A (as wfa_timestep)
-  d.op.jac = g.prec == WFA_F32_IR64 ? 1u : 0u;
+  // the inner FP32 BiCGStab of refinement iterates on D^{-1} A (as
+  // wfa_timestep); CG keeps the symmetric A
+  d.op.jac = g.prec == WFA_F32_IR64 && !r->cg1 ? 1u : 0u;
   d.kappa = (const float*)g.c.kappa;
   T** v = (T**)g.vec;
   d.x = x;
@@ -207,6 +210,7 @@ SolveDesc<T> make_desc(Request* r, T* x) {
   d.r1 = v[8];
   d.par = r->par;
   d.hashed = kServerShadow;
+  d.cg1 = r->cg1;
   d.partials = g.partials;
   d.sc = g.prec == WFA_F32_IR64 ? g.sc_in : g.sc;
   d.n = g.n;
@@ -229,7 +233,7 @@ int start_request(wfa_server* sv, Request* r) {
                      g.partials, g.sc, s};
     launch_rhs<double>(L, (const double*)r->T, g.b64);
     float** v = (float**)g.vec;
-    launch_residual<double>(L, (const double*)r->T, g.b64, v[0], v[1], g.sc_in, 2,
+    launch_residual<double>(L, (const double*)r->T, g.b64, v[0], v[1], g.sc_in, r->cg1 ? 1 : 2,
                             kServerShadow);
   } else {
     const Scalars h = fresh(r->tol, r->maxit);
@@ -270,7 +274,8 @@ int refine_request(wfa_server* sv, Request* r, double scale_next, bool promote) 
   Launch<double> L{g.tl, g.op64, g.c.mode == WFA_COEF_CELL, (const float*)g.c.kappa,
                    g.partials, g.sc, s};
   float** v = (float**)g.vec;
-  launch_residual<double>(L, (const double*)r->T, g.b64, v[0], v[1], g.sc_in, 2, kServerShadow);
+  launch_residual<double>(L, (const double*)r->T, g.b64, v[0], v[1], g.sc_in, r->cg1 ? 1 : 2,
+                          kServerShadow);
   r->par = 0;
   r->scale = scale_next;
   hipError_t e = hipGetLastError();
@@ -512,6 +517,10 @@ void worker_main(wfa_server* sv) {
     if (!rc) {
       rc = build_tables(sv, &n32, &t32, &p32, &n64, &t64, &p64);
     }
+    // persistent rounds carry two-reduction BiCGStab only: a round with a
+    // CG1 solve resident makes one launch per pass
+    for (Request* r : sv->slots)
+      if (r && r->cg1) persist = 0;
     if (!rc) {
       const int S = sv->max_slots;
       rc = put(sv, sv->d32, sv->h_d32, sizeof(SolveDesc<float>) * std::max(n32, 1));
@@ -541,8 +550,9 @@ void worker_main(wfa_server* sv) {
         }
         e = hipGetLastError();
       }
+      // (a CG1 solve's buffers return to parity 0 after each pair of passes)
       for (Request* r : sv->slots)
-        if (r && (r->phase == R_ITER || r->phase == R_REFINE)) r->par ^= (chunk & 1);
+        if (r && !r->cg1 && (r->phase == R_ITER || r->phase == R_REFINE)) r->par ^= (chunk & 1);
       if (e != hipSuccess) rc = fail(sv, "batched iteration", e);
     }
     if (!rc) {
@@ -652,6 +662,11 @@ extern "C" int wfa_server_set_option(wfa_server* sv, int option, int64_t value) 
       if (value != 0 && value != 1) return set_error(WFA_ERR_INVALID, "persistent must be 0 or 1");
       sv->persistent = (int)value;
       return WFA_OK;
+    case WFA_OPT_METHOD:
+      if (value != WFA_METHOD_BICGSTAB2 && value != WFA_METHOD_CG1)
+        return set_error(WFA_ERR_INVALID, "server method must be WFA_METHOD_BICGSTAB2 or _CG1");
+      sv->method = (int)value;
+      return WFA_OK;
     case WFA_OPT_CHECK_EVERY:
       if (value < 1 || value > 1024)
         return set_error(WFA_ERR_INVALID, "iterations per round must be in [1, 1024]");
@@ -688,6 +703,7 @@ extern "C" int wfa_submit(wfa_server* sv, int nx, int ny, int nz, const wfa_coef
       return set_error(sv->worker_error, "server failed: %s", sv->worker_msg);
     }
     r->ticket = sv->next_ticket++;
+    r->cg1 = sv->method == WFA_METHOD_CG1 && c->u[0] == 0.0 && c->u[1] == 0.0 && c->u[2] == 0.0;
     sv->reqs[r->ticket] = r;
     sv->queue.push_back(r);
     ++sv->inflight;

@@ -11,6 +11,8 @@ Bars (relative L2):
 The fused pass applies each iteration's update while it forms the next
 operator product, so the halo cells recompute the neighbours' new residual:
 the trajectory tests run on tilings with many tiles and ragged tails.
+As the inner FP32 solve of refinement it must reach FP64 accuracy (1e-12
+under the oracle's operator), including after a forced inner divergence.
 """
 import numpy as np
 import pytest
@@ -170,7 +172,7 @@ def test_cg1_status_paths(wfa, oracle_mod):
     assert e.value.code == wfa.ERR_INVALID
     gi = wfa.Grid.from_problem(prob, precision=wfa.F32_IR64)
     with pytest.raises(wfa.WfaError) as e:
-        gi.solve(gi.field(b), gi.field(), tol=1e-10, maxit=10, method="cg1")
+        gi.solve(gi.field(b), gi.field(), tol=1e-10, maxit=10, method="cg")
     assert e.value.code == wfa.ERR_INVALID
     gj = wfa.Grid.from_problem(prob, precision=wfa.F64)
     gj.set_option(wfa.OPT_JACOBI, 1)
@@ -230,3 +232,60 @@ def test_cg1_needs_half_the_passes_of_classic_cg(wfa):
     assert abs(out["cg"][0] - out["cg1"][0]) <= 1
     assert out["cg"][1] == 2 * 40
     assert out["cg1"][1] == 40 + 1
+
+
+def test_cg1_refinement_reaches_fp64_accuracy(wfa, oracle_mod):
+    """FP32 one-reduction CG (on A itself) inside FP64 refinement, on the
+    log-normal-diffusivity grid without velocity: the result meets 1e-12
+    under the oracle's operator, and the host's chunking leaves it unchanged
+    bit for bit."""
+    prob = inputs.convdiff(n=40, seed=4, u=(0.0, 0.0, 0.0))
+    o = oracle_mod.Oracle(prob)
+    b = o.rhs(prob.T0)
+    xo, _ = o.cg1(b, prob.T0, 1e-13, 5000)
+    outs = []
+    for check_every in (0, 5):
+        g = wfa.Grid.from_problem(prob, precision=wfa.F32_IR64)
+        g.set_option(wfa.OPT_CHECK_EVERY, check_every)
+        x, info = g.solve(g.field(b), g.field(prob.T0), tol=1e-12, maxit=5000, method="cg1")
+        assert info.status == wfa.OK, info
+        assert info.refinements >= 2
+        assert o.true_relres(b, to_np(x)) <= 1e-12
+        assert info.rel_res_true <= 1e-12
+        assert rel_l2(to_np(x), xo) <= 1e-7
+        outs.append((to_np(x), info.iterations, info.refinements))
+    assert np.array_equal(outs[0][0], outs[1][0]) and outs[0][1:] == outs[1][1:]
+
+
+def test_cg1_refinement_recovers_from_a_diverged_inner_solve(wfa, oracle_mod):
+    """An inner CG solve declared diverged from the host at inner iteration 7
+    is repeated once, stopped at its smallest residual, and its correction
+    applied: the solve still reaches 1e-12, with one more residual pass."""
+    prob = inputs.convdiff(n=40, seed=4, u=(0.0, 0.0, 0.0))
+    o = oracle_mod.Oracle(prob)
+    b = o.rhs(prob.T0)
+    runs = []
+    for force in (0, 7):
+        g = wfa.Grid.from_problem(prob, precision=wfa.F32_IR64)
+        g.set_option(wfa.OPT_PROFILE, 1)
+        g.set_option(wfa.OPT_FORCE_DIVERGE, force)
+        x, info = g.solve(g.field(b), g.field(prob.T0), tol=1e-12, maxit=5000, method="cg1")
+        assert info.status == wfa.OK, (force, info)
+        assert o.true_relres(b, to_np(x)) <= 1e-12
+        runs.append((to_np(x), info, g.kernel_stats(wfa.K_RESIDUAL)[0]))
+    (x0, i0, n0), (x1, i1, n1) = runs
+    assert n0 == i0.refinements + 1
+    assert n1 == i1.refinements + 2
+    assert rel_l2(x1, x0) <= 1e-9
+
+
+def test_cg1_heat_refinement_matches_oracle(wfa, oracle_mod):
+    prob = inputs.heat_32()
+    o = oracle_mod.Oracle(prob)
+    To, _ = o.timestep(prob.T0, 3, 1e-12, 1000)
+    g = wfa.Grid.from_problem(prob, precision=wfa.F32_IR64)
+    g.set_option(wfa.OPT_METHOD, wfa.METHOD_CG1)
+    T = g.field(prob.T0)
+    infos = g.timestep(T, 3, tol=1e-12, maxit=1000)
+    assert all(i.status == wfa.OK and i.refinements >= 2 for i in infos)
+    assert rel_l2(to_np(T), To) <= 3 * 14 * 2e-12

@@ -4,7 +4,8 @@ Each request is one backward-Euler step of the 32^3 heat physics on its own
 grid (dims from {32,...,192}), FP32 BiCGStab inside FP64 refinement to 1e-10.
 A request's result must be bitwise the same alone, in a mix, and through the
 single-grid entry point, and its FP64 residual (evaluated by the oracle's
-operator) must meet the tolerance.
+operator) must meet the tolerance.  The same holds with the server set to
+iterate symmetric requests with the one-reduction CG.
 """
 import numpy as np
 import pytest
@@ -134,9 +135,66 @@ def test_persistent_rounds_are_bitwise_per_pass_rounds(wfa):
 def test_server_options_are_validated(wfa):
     sv = wfa.Server(1 << 26, max_slots=2)
     for opt, val in ((wfa.OPT_PERSISTENT, 2), (wfa.OPT_CHECK_EVERY, 0),
-                     (wfa.OPT_CHECK_EVERY, 1025), (wfa.OPT_PROFILE, 1)):
+                     (wfa.OPT_CHECK_EVERY, 1025), (wfa.OPT_PROFILE, 1),
+                     (wfa.OPT_METHOD, wfa.METHOD_CG), (wfa.OPT_METHOD, 9)):
         with pytest.raises(wfa.WfaError):
             sv.set_option(opt, val)
     sv.set_option(wfa.OPT_CHECK_EVERY, 8)
     sv.set_option(wfa.OPT_PERSISTENT, 1)
+    sv.set_option(wfa.OPT_METHOD, wfa.METHOD_CG1)
+    sv.set_option(wfa.OPT_METHOD, wfa.METHOD_BICGSTAB2)
     sv.close()
+
+
+class _Given:
+    """A request whose problem is given rather than drawn from the stream."""
+
+    def __init__(self, prob):
+        self.prob = prob
+
+    def problem(self):
+        return self.prob
+
+
+def test_cg1_requests_served(wfa, oracle_mod):
+    """With the server's method set to the one-reduction CG, the symmetric
+    (heat) requests iterate with it and the convective ones keep BiCGStab, in
+    the same rounds.  Each result meets its tolerance under the oracle's
+    operator and equals the single-grid path with the same method bit for
+    bit (iterations and refinements too); the convective results equal those
+    of a server that runs BiCGStab for all; results are unchanged by the
+    round length, by a persistent-rounds setting (ignored while a CG solve
+    is resident) and by being served alone."""
+    heat = _requests(DIMS[:4])
+    conv = [_Given(inputs.random_problem(320 + k, 40, 30, 20, cell=True, u=(1.0, 0.5, 0.25),
+                                         bc_kind=inputs.MIXED_BC_KIND)) for k in range(2)]
+    reqs = heat[:2] + conv[:1] + heat[2:] + conv[1:]
+    precs = [wfa.F64, wfa.F32_IR64, wfa.F32_IR64, wfa.F32_IR64, wfa.F32, wfa.F32_IR64]
+    tols = [1e-5 if p == wfa.F32 else 1e-10 for p in precs]
+    opts = {wfa.OPT_METHOD: wfa.METHOD_CG1}
+    mix, infos = _serve(wfa, reqs, 1 << 30, slots=8, precision=precs, tol=tols, options=opts)
+    ref, _ = _serve(wfa, reqs, 1 << 30, slots=8, precision=precs, tol=tols)
+    for rq, m, info, r0, p, tq in zip(reqs, mix, infos, ref, precs, tols):
+        prob = rq.problem()
+        o = oracle_mod.Oracle(prob)
+        assert o.true_relres(o.rhs(prob.T0), m) <= (1e-4 if p == wfa.F32 else tq), rq
+        sym = all(v == 0.0 for v in prob.u)
+        g = wfa.Grid.from_problem(prob, precision=p)
+        g.set_option(wfa.OPT_SHADOW, 1)
+        g.set_option(wfa.OPT_METHOD, wfa.METHOD_CG1 if sym else wfa.METHOD_BICGSTAB2)
+        T = g.field(prob.T0)
+        gi = g.timestep(T, 1, tol=tq, maxit=20000)[0]
+        assert np.array_equal(T.cpu().double().numpy(), m), rq
+        assert (gi.iterations, gi.refinements) == (info.iterations, info.refinements), rq
+        if not sym:
+            assert np.array_equal(m, r0), rq
+    for extra in ({wfa.OPT_CHECK_EVERY: 1}, {wfa.OPT_CHECK_EVERY: 7}, {wfa.OPT_PERSISTENT: 1}):
+        got, ginfo = _serve(wfa, reqs, 1 << 30, slots=8, precision=precs, tol=tols,
+                            options={**opts, **extra})
+        for rq, a, b, ia, ib in zip(reqs, mix, got, infos, ginfo):
+            assert np.array_equal(a, b), (extra, rq)
+            assert (ia.iterations, ia.refinements) == (ib.iterations, ib.refinements), (extra, rq)
+    for q in (0, 1, 2):
+        alone, _ = _serve(wfa, [reqs[q]], 1 << 30, slots=1, precision=[precs[q]], tol=[tols[q]],
+                          options=opts)
+        assert np.array_equal(alone[0], mix[q]), reqs[q]
