@@ -538,6 +538,7 @@ def run_serve(args, torch, inputs, wfa):
     sv.set_option(wfa.OPT_PERSISTENT, args.serve_persistent)
     sv.set_option(wfa.OPT_CHECK_EVERY, args.serve_round)
     sv.set_option(wfa.OPT_METHOD, METHODS[args.serve_method])
+    sv.set_option(wfa.OPT_CG1_MAX_CELLS, args.serve_cg1_max_cells)
     tickets = {}
     t_start = time.perf_counter()
     for q, rq in enumerate(reqs):
@@ -549,25 +550,30 @@ def run_serve(args, torch, inputs, wfa):
                                 tol=1e-10, maxit=20000), time.perf_counter() - t_start)
     sv.drain()
     t_end = time.perf_counter() - t_start
-    lat, cell_it, fails, its = [], 0, 0, 0
+    lat, cell_it, fails, its, passes = [], 0, 0, 0, 0
+    limit = args.serve_cg1_max_cells
     for q, rq in enumerate(reqs):
         code, info = sv.poll(tickets[q][0])
         if code != wfa.OK:
             fails += 1
         lat.append((tickets[q][1] - rq.arrival) + info.seconds)
-        cell_it += rq.nx * rq.ny * rq.nz * info.iterations
+        cells = rq.nx * rq.ny * rq.nz
+        cell_it += cells * info.iterations
         its += info.iterations
+        # a CG iteration is one operator pass, a BiCGStab iteration two (the
+        # stream's heat requests are all symmetric)
+        cg = args.serve_method == "cg1" and (limit == 0 or cells <= limit)
+        passes += info.iterations * (1 if cg else 2)
     sv.close()
-    # a CG iteration is one operator pass, a BiCGStab iteration two
     return {"workload": f"serve_{args.requests}req_200rps", "precision": args.serve_precision,
             "method": args.serve_method,
-            "passes_per_iteration": 1 if args.serve_method == "cg1" else 2,
+            "cg1_max_cells": args.serve_cg1_max_cells if args.serve_method == "cg1" else None,
             "round": {"iterations": args.serve_round,
                       "launch": "persistent" if args.serve_persistent else "per pass"},
             "requests": len(reqs), "failed": fails, "makespan_s": t_end,
             "latency_ms": {"p50": percentile(lat, 50) * 1e3, "p99": percentile(lat, 99) * 1e3,
                            "mean": sum(lat) / len(lat) * 1e3},
-            "iterations_mean": its / len(reqs),
+            "iterations_mean": its / len(reqs), "passes_mean": passes / len(reqs),
             "cell_iters_per_s": cell_it / t_end, "slots": args.slots,
             "budget_gb": args.budget_gb}
 
@@ -687,6 +693,8 @@ def main():
     ap.add_argument("--serve-method", default="bicgstab2", choices=["bicgstab2", "cg1"],
                     help="serve: cg1 = the (symmetric) heat requests iterate with CG with one "
                          "reduction")
+    ap.add_argument("--serve-cg1-max-cells", type=int, default=0,
+                    help="serve with --serve-method cg1: larger requests keep BiCGStab (0: none)")
     ap.add_argument("--serve-persistent", type=int, default=0, choices=[0, 1],
                     help="serve: 1 = each round is one cooperative launch per precision")
     ap.add_argument("--no-profile", action="store_true",

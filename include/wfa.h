@@ -260,7 +260,11 @@ enum {
                                   diverges when ||r|| grows 1000-fold; it is
                                   then repeated once, stopped at the iteration
                                   of its smallest residual, and that
-                                  correction is applied.)                      */
+                                  correction is applied.)                      */,
+  WFA_OPT_CG1_MAX_CELLS = 14   /* server only: with WFA_OPT_METHOD =
+                                  WFA_METHOD_CG1, symmetric requests of more
+                                  cells than this keep BiCGStab; 0 = no limit
+                                  (default)                                    */
 };
 int wfa_grid_set_option(wfa_grid* g, int option, int64_t value);
 
@@ -345,6 +349,11 @@ int wfa_server_create(void* arena, size_t arena_bytes, int max_slots, void* stre
  *                        a round; other requests keep BiCGStab.  A round with
  *                        a CG request resident makes one launch per pass
  *                        whatever WFA_OPT_PERSISTENT says;
+ *   WFA_OPT_CG1_MAX_CELLS  0 (default) or the largest request (in cells)
+ *                        that WFA_METHOD_CG1 applies to: latency-bound small
+ *                        grids gain from CG's one pass per iteration, while
+ *                        bandwidth-bound large ones move fewer bytes with
+ *                        BiCGStab;
  *   WFA_OPT_PERSISTENT   1: each round is one cooperative launch per
  *                        precision, with grid barriers in place of the
  *                        per-pass kernel boundaries (bitwise the same

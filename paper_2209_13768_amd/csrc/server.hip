@@ -146,6 +146,7 @@ struct wfa_server {
   int chunk = 4;      // iterations per round (WFA_OPT_CHECK_EVERY)
   int persistent = 0; // 1: a round is one cooperative launch per precision (WFA_OPT_PERSISTENT)
   int method = WFA_METHOD_BICGSTAB2;  // WFA_OPT_METHOD: _CG1 for symmetric requests
+  int64_t cg1_max_cells = 0;          // WFA_OPT_CG1_MAX_CELLS (0: no limit)
   int ry = 0;        // rows per wave of every resident solve's tiling
   std::thread worker;
 };
@@ -667,6 +668,10 @@ extern "C" int wfa_server_set_option(wfa_server* sv, int option, int64_t value) 
         return set_error(WFA_ERR_INVALID, "server method must be WFA_METHOD_BICGSTAB2 or _CG1");
       sv->method = (int)value;
       return WFA_OK;
+    case WFA_OPT_CG1_MAX_CELLS:
+      if (value < 0) return set_error(WFA_ERR_INVALID, "cell limit must be >= 0");
+      sv->cg1_max_cells = value;
+      return WFA_OK;
     case WFA_OPT_CHECK_EVERY:
       if (value < 1 || value > 1024)
         return set_error(WFA_ERR_INVALID, "iterations per round must be in [1, 1024]");
@@ -703,7 +708,9 @@ extern "C" int wfa_submit(wfa_server* sv, int nx, int ny, int nz, const wfa_coef
       return set_error(sv->worker_error, "server failed: %s", sv->worker_msg);
     }
     r->ticket = sv->next_ticket++;
-    r->cg1 = sv->method == WFA_METHOD_CG1 && c->u[0] == 0.0 && c->u[1] == 0.0 && c->u[2] == 0.0;
+    const int64_t cells = (int64_t)nx * ny * nz;
+    r->cg1 = sv->method == WFA_METHOD_CG1 && c->u[0] == 0.0 && c->u[1] == 0.0 &&
+             c->u[2] == 0.0 && (sv->cg1_max_cells == 0 || cells <= sv->cg1_max_cells);
     sv->reqs[r->ticket] = r;
     sv->queue.push_back(r);
     ++sv->inflight;

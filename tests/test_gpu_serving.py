@@ -136,7 +136,8 @@ def test_server_options_are_validated(wfa):
     sv = wfa.Server(1 << 26, max_slots=2)
     for opt, val in ((wfa.OPT_PERSISTENT, 2), (wfa.OPT_CHECK_EVERY, 0),
                      (wfa.OPT_CHECK_EVERY, 1025), (wfa.OPT_PROFILE, 1),
-                     (wfa.OPT_METHOD, wfa.METHOD_CG), (wfa.OPT_METHOD, 9)):
+                     (wfa.OPT_METHOD, wfa.METHOD_CG), (wfa.OPT_METHOD, 9),
+                     (wfa.OPT_CG1_MAX_CELLS, -1)):
         with pytest.raises(wfa.WfaError):
             sv.set_option(opt, val)
     sv.set_option(wfa.OPT_CHECK_EVERY, 8)
@@ -198,3 +199,15 @@ def test_cg1_requests_served(wfa, oracle_mod):
         alone, _ = _serve(wfa, [reqs[q]], 1 << 30, slots=1, precision=[precs[q]], tol=[tols[q]],
                           options=opts)
         assert np.array_equal(alone[0], mix[q]), reqs[q]
+    # a cell limit: heat requests above it keep BiCGStab, bitwise as in the
+    # all-BiCGStab server; those at or below it are the CG results above
+    limit = min(r.nx * r.ny * r.nz for r in heat) + 1
+    got, ginfo = _serve(wfa, reqs, 1 << 30, slots=8, precision=precs, tol=tols,
+                        options={**opts, wfa.OPT_CG1_MAX_CELLS: limit})
+    n_cg = 0
+    for rq, a, r0, b in zip(reqs, mix, ref, got):
+        prob = rq.problem()
+        small = prob.nx * prob.ny * prob.nz <= limit and all(v == 0.0 for v in prob.u)
+        n_cg += small
+        assert np.array_equal(b, a if small else r0), rq
+    assert n_cg == 1
