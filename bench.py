@@ -725,7 +725,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the solver has no "
-                          "multi-GPU path (see DESIGN.md for how it would shard)",
+                          "multi-GPU path",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 

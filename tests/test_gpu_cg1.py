@@ -289,3 +289,33 @@ def test_cg1_heat_refinement_matches_oracle(wfa, oracle_mod):
     infos = g.timestep(T, 3, tol=1e-12, maxit=1000)
     assert all(i.status == wfa.OK and i.refinements >= 2 for i in infos)
     assert rel_l2(to_np(T), To) <= 3 * 14 * 2e-12
+
+
+EDGE_SHAPES = [(1, 1, 1), (1, 7, 3), (65, 3, 2), (7, 1, 40), (33, 17, 5), (200, 9, 33)]
+EDGE_VARIANTS = {
+    "cell_mixed": dict(cell=True, bc_kind=inputs.MIXED_BC_KIND),
+    "const_zeroflux": dict(cell=False, bc_kind=(ZEROFLUX,) * 6),
+}
+
+
+@pytest.mark.parametrize("shape", EDGE_SHAPES, ids=lambda s: "x".join(map(str, s)))
+@pytest.mark.parametrize("name", sorted(EDGE_VARIANTS))
+def test_cg1_degenerate_and_ragged_grids(wfa, oracle_mod, shape, name):
+    """Single cells, single rows and columns, ragged tiles, all faces
+    zero-flux: converged solves agree with the oracle's, and on grids with
+    more than a few cells the first two iterates do too."""
+    prob = inputs.random_problem(330, *shape, **EDGE_VARIANTS[name])
+    o = oracle_mod.Oracle(prob)
+    b = o.rhs(prob.T0)
+    xo, io = o.cg1(b, prob.T0, 1e-13, 5000)
+    g = wfa.Grid.from_problem(prob, precision=wfa.F64)
+    x, info = g.solve(g.field(b), g.field(prob.T0), tol=1e-13, maxit=5000, method="cg1")
+    assert info.status == wfa.OK and io.status == 0
+    assert rel_l2(to_np(x), xo) <= 1e-11
+    if prob.cells >= 8:
+        xk, _ = o.cg1(b, prob.T0, 1e-300, 2)
+        bound = max(FP64_TOL, 100 * _sensitivity(o, b, prob.T0, 2))
+        x2, i2 = g.solve(g.field(b), g.field(prob.T0), tol=1e-300, maxit=2, method="cg1",
+                         check=False)
+        assert i2.iterations == 2
+        assert rel_l2(to_np(x2), xk) <= bound
