@@ -279,19 +279,20 @@ double copy_probe(const void* src, void* dst, size_t bytes, int reps, hipStream_
   *err = hipEventCreate(&e0);
   if (*err != hipSuccess) return 0.0;
   *err = hipEventCreate(&e1);
-  if (*err != hipSuccess) { hipEventDestroy(e0); return 0.0; }
+  if (*err != hipSuccess) { (void)hipEventDestroy(e0); return 0.0; }
   const int blocks = 256 * 32;  // measured: the fastest of 2048, 4096 and 8192 workgroups
   hipLaunchKernelGGL(k_copy, dim3(blocks), dim3(kThreads), 0, s, n16, (const u32x4*)src, (u32x4*)dst);
-  hipEventRecord(e0, s);
-  for (int i = 0; i < reps; ++i)
+  *err = hipEventRecord(e0, s);
+  for (int i = 0; *err == hipSuccess && i < reps; ++i)
     hipLaunchKernelGGL(k_copy, dim3(blocks), dim3(kThreads), 0, s, n16, (const u32x4*)src,
                        (u32x4*)dst);
-  hipEventRecord(e1, s);
-  *err = hipEventSynchronize(e1);
+  if (*err == hipSuccess) *err = hipGetLastError();
+  if (*err == hipSuccess) *err = hipEventRecord(e1, s);
+  if (*err == hipSuccess) *err = hipEventSynchronize(e1);
   float ms = 0.f;
   if (*err == hipSuccess) *err = hipEventElapsedTime(&ms, e0, e1);
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   if (*err != hipSuccess || ms <= 0.f) return 0.0;
   return 2.0 * (double)n16 * 16.0 * reps / (ms * 1e-3) / 1e9;
 }
