@@ -663,3 +663,25 @@ def test_cg1_dense_direct_solve_and_stop_rule(oracle_mod, shape):
     # b = 0 gives x = 0 at once
     x0, iz = o.cg1(np.zeros_like(b), p.T0, 1e-10, 10)
     assert iz.status == oracle_mod.OK and iz.iterations == 0 and not x0.any()
+
+
+def test_cg1_finite_termination_on_random_small_grids(oracle_mod):
+    """On random small symmetric grids (shapes, diffusivities and boundary
+    kinds drawn per case) the one-reduction CG reaches the dense solution,
+    and in exact arithmetic it would within n iterations: with n + 10 it
+    meets 1e-12 of the dense solve.  A dropped term or a wrong step length
+    in the recurrences stalls it far from there."""
+    rng = np.random.default_rng(163)
+    for case in range(12):
+        shape = tuple(int(v) for v in rng.integers(1, 6, size=3))
+        bc = tuple(int(v) for v in rng.integers(0, 2, size=6))
+        cell = bool(case % 2)
+        p = inputs.random_problem(200 + case, *shape, cell=cell, bc_kind=bc)
+        o = oracle_mod.Oracle(p)
+        A = dense_by_columns(o)
+        b = o.rhs(p.T0)
+        x_ref = np.linalg.solve(A, b.ravel()).reshape(p.shape)
+        n = int(np.prod(shape))
+        x, info = o.cg1(b, p.T0, 1e-15, n + 10)
+        assert info.status in (oracle_mod.OK, oracle_mod.NOCONV), (case, info)
+        assert rel_l2(x, x_ref) <= 1e-12, (case, shape, bc, cell)
