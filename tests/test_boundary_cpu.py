@@ -57,6 +57,12 @@ def test_workspace_bytes_and_validation(libwfa):
     rc = libwfa.wfa_grid_create(4, 4, 4, ctypes.byref(c), ctypes.c_void_p(256), 1 << 30,
                                 ctypes.byref(out))
     assert rc == wfa.ERR_INVALID and "kappa" in wfa.last_error()
+    # an empty grid is rejected
+    c.mode = wfa.COEF_CONST
+    for dims in ((0, 4, 4), (4, 0, 4), (4, 4, 0), (-1, 4, 4)):
+        rc = libwfa.wfa_grid_create(*dims, ctypes.byref(c), ctypes.c_void_p(256), 1 << 30,
+                                    ctypes.byref(out))
+        assert rc == wfa.ERR_INVALID, dims
 
 
 def test_grid_descriptor_host_only(libwfa):
@@ -74,6 +80,9 @@ def test_grid_descriptor_host_only(libwfa):
     assert tx == 64 and ty % 4 == 0 and 1 <= zc <= 256
     assert blocks == (256 // tx) * (-(-256 // ty)) * (-(-256 // zc))
     assert libwfa.wfa_grid_set_option(out, wfa.OPT_METHOD, 5) == wfa.ERR_INVALID
+    assert libwfa.wfa_grid_set_option(out, wfa.OPT_METHOD, wfa.METHOD_CG1) == wfa.OK
+    # a server-only option is not a grid option
+    assert libwfa.wfa_grid_set_option(out, wfa.OPT_CG1_MAX_CELLS, 1000) == wfa.ERR_INVALID
     assert libwfa.wfa_grid_set_option(out, wfa.OPT_ZCHUNK, 32) == wfa.OK
     assert libwfa.wfa_grid_tiling(out, *[ctypes.byref(q) for q in v]) == wfa.OK
     assert v[2].value == 32
