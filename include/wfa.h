@@ -17,8 +17,9 @@
  *                   A[P,P] += D + max(F,0), b[P] += (D + max(-F,0))*value
  *   zero-flux face: no term.
  * and A[P,P] starts at 1.  The system is solved with BiCGStab (van der Vorst
- * 1992), or with classic conjugate gradients (the paper's solver, section
- * 1.1.2) for the symmetric pure-diffusion case.
+ * 1992), or with conjugate gradients (the paper's solver, section 1.1.2;
+ * classic, or reorganised to one reduction per iteration) for the symmetric
+ * pure-diffusion case.
  *
  * Conventions
  *   - Fields are dense arrays of nx*ny*nz values, x fastest:
@@ -53,7 +54,9 @@ extern "C" {
                                   tol <= 0, maxit < 1, bad option            */
 #define WFA_ERR_NOMEM     -2   /* workspace or arena too small               */
 #define WFA_ERR_HIP       -3   /* HIP runtime error (text in wfa_last_error) */
-#define WFA_ERR_BREAKDOWN -4   /* more than WFA_MAX_RESTARTS restarts         */
+#define WFA_ERR_BREAKDOWN -4   /* more than WFA_MAX_RESTARTS BiCGStab restarts,
+                                  or a CG step length with a non-positive
+                                  denominator (A not positive definite)      */
 #define WFA_ERR_NOCONV    -5   /* maxit reached; x holds the last iterate    */
 #define WFA_ERR_NONFINITE -6   /* NaN/Inf in the data or a Krylov scalar     */
 
@@ -95,7 +98,8 @@ typedef struct {
 
 typedef struct {
   int32_t status;        /* final code of the solve (WFA_OK, NOCONV, ...)      */
-  int32_t iterations;    /* full iterations (BiCGStab: 2 operator products)   */
+  int32_t iterations;    /* full iterations (BiCGStab: 2 operator products;
+                            CG: 1)                                            */
   int32_t refinements;   /* WFA_F32_IR64: outer FP64 refinement steps         */
   int32_t restarts;      /* breakdown restarts from the true residual          */
   double  rel_res_recursive; /* recursive ||r|| / ||b|| at exit (FP32_IR64:
