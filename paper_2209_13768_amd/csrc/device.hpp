@@ -14,6 +14,8 @@
 // diag starts at 1.  (A x)_P = diag x_P - sum_f coupling_f x_N.
 #pragma once
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 #include <stdint.h>
 
 namespace wfa {
@@ -105,9 +107,14 @@ __device__ __forceinline__ float fma_t(float a, float b, float c) { return __bui
 // contraction), so every kernel that applies the operator -- one pass per
 // phase, persistent, batched, several explicit steps per pass -- rounds
 // identically.
+// kz: with `carry`, the z- face's harmonic mean on entry (the previous
+// plane's z+ face: the same two diffusivities, and the products of two FP32
+// values are exact, so the value is the one this call would form); the z+
+// face's on exit.
 template <typename T, bool CELL>
 __device__ __forceinline__ T cell_apply(const Op<T>& op, T c, const T nb[6], T kP,
-                                        const T kN[6], uint32_t inside, T& dg) {
+                                        const T kN[6], uint32_t inside, T& dg, T& kz,
+                                        bool carry) {
 #pragma clang fp contract(off)
   T diag = T(1), acc = T(0);
 #pragma unroll
@@ -115,7 +122,9 @@ __device__ __forceinline__ T cell_apply(const Op<T>& op, T c, const T nb[6], T k
     if (inside & (1u << f)) {
       T d_out, d_in;  // D + max(F,0), D + max(-F,0)
       if (CELL) {
-        const T kf = T(2) * kP * kN[f] * pos_rcp(kP + kN[f]);  // harmonic mean
+        const T kf = (f == 4 && carry) ? kz
+                                       : T(2) * kP * kN[f] * pos_rcp(kP + kN[f]);  // harmonic mean
+        if (f == 5) kz = kf;
         d_out = fma_t(op.cD, kf, op.out[f]);
         d_in = fma_t(op.cD, kf, op.in[f]);
       } else {
@@ -131,6 +140,13 @@ __device__ __forceinline__ T cell_apply(const Op<T>& op, T c, const T nb[6], T k
   dg = diag;
   const T y = fma_t(diag, c, -acc);
   return op.jac ? y * pos_rcp(diag) : y;
+}
+
+template <typename T, bool CELL>
+__device__ __forceinline__ T cell_apply(const Op<T>& op, T c, const T nb[6], T kP,
+                                        const T kN[6], uint32_t inside, T& dg) {
+  T kz = T(0);
+  return cell_apply<T, CELL>(op, c, nb, kP, kN, inside, dg, kz, false);
 }
 
 // Dirichlet contribution of cell P to the right-hand side.
@@ -401,6 +417,15 @@ struct TileShape {
   static_assert(NHALO <= kThreads, "halo must fit one cell per thread");
 };
 
+// Phases opt in to carrying the z face coefficient with a static member
+// kCarryZ = true; the others do not.
+template <class Ph, class = void>
+struct carry_z { static constexpr bool value = false; };
+template <class Ph>
+struct carry_z<Ph, std::void_t<decltype(Ph::kCarryZ)>> {
+  static constexpr bool value = Ph::kCarryZ;
+};
+
 template <typename T, bool CELL, int RY, class Ph>
 __device__ __forceinline__ void march_tile(const Geo& g, const Op<T>& op,
                                            const float* __restrict__ kappa, int tile,
@@ -491,6 +516,15 @@ __device__ __forceinline__ void march_tile(const Geo& g, const Op<T>& op,
   T hc = T(0);
   float kh = 1.f;
   ERaw ec[RY];
+  // A phase that opts in (kCarryZ) carries each cell's z+ face coefficient
+  // to the next plane's z- face: one harmonic mean less per cell, the same
+  // value bit for bit.  It pays in the passes with few streams; in the
+  // fused update pass the extra registers cost more than it saves.
+  constexpr bool CZ = carry_z<Ph>::value;
+  T kz[RY];                 // z+ face coefficient of the plane just computed
+  bool carry = false;       // kz holds the next plane's z- face
+#pragma unroll
+  for (int r = 0; r < RY; ++r) kz[r] = T(0);
 
   // plane k0 - 1 (own cells only) and plane k0 (own + halo), staged directly
 #pragma unroll
@@ -587,7 +621,11 @@ __device__ __forceinline__ void march_tile(const Geo& g, const Op<T>& op,
         }
         const uint32_t ins = ins_xy[r] | ins_z;
         T dg;
-        const T Au = cell_apply<T, CELL>(op, Ph::val(uc[r]), nb, (T)kcv[r], kn6, ins, dg);
+        T Au;
+        if constexpr (CZ)
+          Au = cell_apply<T, CELL>(op, Ph::val(uc[r]), nb, (T)kcv[r], kn6, ins, dg, kz[r], carry);
+        else
+          Au = cell_apply<T, CELL>(op, Ph::val(uc[r]), nb, (T)kcv[r], kn6, ins, dg);
         ph.epilogue((size_t)k * plane + poff[r], uc[r], Au, (T)kcv[r], ins, ec[r], dg, acc);
       }
     }
@@ -599,6 +637,7 @@ __device__ __forceinline__ void march_tile(const Geo& g, const Op<T>& op,
       ec[r] = en[r];
     }
     hc = hn; kh = khn;
+    carry = true;
     buf ^= 1;
   };
 
