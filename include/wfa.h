@@ -289,6 +289,21 @@ int wfa_kernel_stats(wfa_grid* g, int kernel, int64_t* launches, double* ms,
  * the number of workgroups of one phase launch. */
 int wfa_grid_tiling(wfa_grid* g, int* tx, int* ty, int* zc, int* blocks);
 
+/* Address of one of the grid's Krylov vectors inside the caller's workspace,
+ * for inspection (tests, debugging); nothing is copied.  The vector holds
+ * nx*ny*nz values of the grid's Krylov type (double on WFA_F64 grids, float
+ * on WFA_F32 and WFA_F32_IR64 grids, whose Krylov vectors are the inner FP32
+ * solve's) and whatever the last solve left there.  The double-buffered
+ * pairs are those of the solve that wrote them last: BiCGStab (either
+ * organisation) writes p and v = A p into (P0, V0) or (P1, V1), alternately;
+ * CG with one reduction writes r and w = A r into (R, V0) or (R1, V1).
+ * Errors: WFA_ERR_INVALID (null grid or ptr, unknown vector). */
+enum {
+  WFA_VEC_R = 0, WFA_VEC_RHAT = 1, WFA_VEC_T = 2, WFA_VEC_P0 = 3, WFA_VEC_P1 = 4,
+  WFA_VEC_V0 = 5, WFA_VEC_V1 = 6, WFA_VEC_B = 7, WFA_VEC_R1 = 8, WFA_VEC_COUNT = 9
+};
+int wfa_grid_vector(wfa_grid* g, int which, void** ptr);
+
 /* ---- tile-shape autotuner ------------------------------------------------------
  * The stencil passes march 64-cell-wide tiles of 4 x (rows per wave) rows
  * along z, zc planes per workgroup.  wfa_autotune times `iters` iterations

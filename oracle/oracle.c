@@ -312,13 +312,19 @@ double orc_true_relres(const orc_problem* p, const double* b, const double* x)
  *   r_out  optional: the recursively updated residual at exit
  *   tol    stop when ||r|| <= tol * ||b|| after a full iteration
  *   maxit  number of full iterations (each = two products with A)
+ *   force_bd  n > 0: take sigma of full iteration n as exactly zero (once),
+ *          so that the restart path runs on demand; 0: never
  * Shadow residual r^ = r0.  Exactly-zero rho, sigma or omega restarts the
- * method from the true residual b - A x (at most ORC_MAX_RESTARTS times; the
- * iteration count continues).  A non-finite Krylov scalar stops with
- * ORC_NONFINITE.  tt == 0 means s == 0: the half step is the solution.
+ * method from the true residual b - A x, with r^ reset to that residual (at
+ * most ORC_MAX_RESTARTS times).  The iteration count continues across a
+ * restart and counts completed iterations only: one that breaks down on rho
+ * or sigma, before its update of x, is not counted, while a zero omega comes
+ * after the update and its iteration counts.  A non-finite Krylov scalar
+ * stops with ORC_NONFINITE.  tt == 0 means s == 0: the half step is the
+ * solution.
  */
 static int bicgstab_core(const orc_problem* p, int jacobi, const double* b_in, double* x,
-                         double tol, int maxit, double* r_out, orc_info* info)
+                         double tol, int maxit, int force_bd, double* r_out, orc_info* info)
 {
   const long n = cells(p);
   const size_t bytes = sizeof(double) * (size_t)n;
@@ -365,14 +371,15 @@ restart:
     ++it;
     const double rho = dot(p, rh, r);
     if (!isfinite(rho)) { status = ORC_NONFINITE; goto done; }
-    if (rho == 0.0) goto do_restart;
+    if (rho == 0.0) goto broken;
     const double beta = (rho / rho_prev) * (alpha / omega);
 #pragma omp parallel for schedule(static)
     for (long c = 0; c < n; ++c) pv[c] = r[c] + beta * (pv[c] - omega * v[c]);
     krylov_apply(p, jacobi, pv, v);
-    const double sigma = dot(p, rh, v);
+    double sigma = dot(p, rh, v);
+    if (force_bd > 0 && it == force_bd) { sigma = 0.0; force_bd = 0; }
     if (!isfinite(sigma)) { status = ORC_NONFINITE; goto done; }
-    if (sigma == 0.0) goto do_restart;
+    if (sigma == 0.0) goto broken;
     alpha = rho / sigma;
 #pragma omp parallel for schedule(static)
     for (long c = 0; c < n; ++c) s[c] = r[c] - alpha * v[c];
@@ -399,6 +406,8 @@ restart:
     if (rnorm <= tol * bn) { status = ORC_OK; goto done; }
     if (omega == 0.0) goto do_restart;
     continue;
+  broken:
+    --it;                                /* ended before its update of x */
   do_restart:
     if (++restarts > ORC_MAX_RESTARTS) { status = ORC_BREAKDOWN; goto done; }
     goto restart;
@@ -421,7 +430,14 @@ done:
 int orc_bicgstab(const orc_problem* p, const double* b, double* x,
                  double tol, int maxit, double* r_out, orc_info* info)
 {
-  return bicgstab_core(p, 0, b, x, tol, maxit, r_out, info);
+  return bicgstab_core(p, 0, b, x, tol, maxit, 0, r_out, info);
+}
+
+/* orc_bicgstab with sigma of full iteration force_bd taken as zero (once). */
+int orc_bicgstab_forced(const orc_problem* p, const double* b, double* x, double tol,
+                        int maxit, int force_bd, double* r_out, orc_info* info)
+{
+  return bicgstab_core(p, 0, b, x, tol, maxit, force_bd, r_out, info);
 }
 
 /*
@@ -432,7 +448,7 @@ int orc_bicgstab(const orc_problem* p, const double* b, double* x,
 int orc_bicgstab_jacobi(const orc_problem* p, const double* b, double* x,
                         double tol, int maxit, double* r_out, orc_info* info)
 {
-  return bicgstab_core(p, 1, b, x, tol, maxit, r_out, info);
+  return bicgstab_core(p, 1, b, x, tol, maxit, 0, r_out, info);
 }
 
 /*
@@ -452,10 +468,14 @@ int orc_bicgstab_jacobi(const orc_problem* p, const double* b, double* x,
  * alpha uses the exact rho of pass 1; beta the predicted one.  Breakdown
  * (exact zero rho, sigma or omega) restarts from b - A x as in
  * orc_bicgstab; a zero omega is applied (x += alpha p, r = s) before the
- * restart; tt == 0 (s == 0) ends with x + alpha p.
+ * restart; tt == 0 (s == 0) ends with x + alpha p.  Iterations are counted
+ * when their update has been applied, as in orc_bicgstab.  force_bd = n > 0
+ * takes sigma of full iteration n as exactly zero (once); 0: never.  A
+ * restart takes r^ = r again for the r0 shadow and keeps the hashed field.
  */
 int orc_bicgstab2_shadow(const orc_problem* p, const double* b, double* x, double tol,
-                         int maxit, int hashed_shadow, double* r_out, orc_info* info)
+                         int maxit, int hashed_shadow, int force_bd, double* r_out,
+                         orc_info* info)
 {
   const long n = cells(p);
   const size_t bytes = sizeof(double) * (size_t)n;
@@ -507,7 +527,7 @@ restart:
       }
     }
     orc_apply(p, pv, v);
-    const double sigma = dot(p, rh, v);
+    double sigma = dot(p, rh, v);
     if (!first) {
       ++it;
       const double rho_exact = dot(p, rh, r);
@@ -520,6 +540,7 @@ restart:
       if (rho_exact == 0.0) goto do_restart;
       rho = rho_exact;
     }
+    if (force_bd > 0 && it + 1 == force_bd) { sigma = 0.0; force_bd = 0; }
     if (!isfinite(sigma)) { status = ORC_NONFINITE; goto done; }
     if (sigma == 0.0) goto do_restart;
     alpha = rho / sigma;
@@ -571,7 +592,7 @@ done:
 int orc_bicgstab2(const orc_problem* p, const double* b, double* x, double tol,
                   int maxit, double* r_out, orc_info* info)
 {
-  return orc_bicgstab2_shadow(p, b, x, tol, maxit, 0, r_out, info);
+  return orc_bicgstab2_shadow(p, b, x, tol, maxit, 0, 0, r_out, info);
 }
 
 /*

@@ -95,7 +95,9 @@ def load(path: str | None = None) -> ctypes.CDLL:
     lib.orc_cg1.argtypes = [P, D, D, ctypes.c_double, ctypes.c_int, D, I]
     lib.orc_bicgstab2.argtypes = [P, D, D, ctypes.c_double, ctypes.c_int, D, I]
     lib.orc_bicgstab2_shadow.argtypes = [P, D, D, ctypes.c_double, ctypes.c_int, ctypes.c_int,
-                                         D, I]
+                                         ctypes.c_int, D, I]
+    lib.orc_bicgstab_forced.argtypes = [P, D, D, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                        D, I]
     lib.orc_shadow.argtypes = [ctypes.c_long, D]
     lib.orc_bicgstab_jacobi.argtypes = [P, D, D, ctypes.c_double, ctypes.c_int, D, I]
     lib.orc_timestep.argtypes = [P, D, ctypes.c_int, ctypes.c_double, ctypes.c_int, I]
@@ -183,20 +185,29 @@ class Oracle:
                         info.rel_res_recursive, info.rel_res_true)
         return (x, out, r) if want_r else (x, out)
 
-    def bicgstab(self, b, x0, tol: float, maxit: int, want_r: bool = False):
-        return self._krylov(self.lib.orc_bicgstab, b, x0, tol, maxit, want_r)
+    def bicgstab(self, b, x0, tol: float, maxit: int, want_r: bool = False,
+                 force_breakdown: int = 0):
+        """Textbook BiCGStab (oracle.c).  force_breakdown = n > 0 takes sigma
+        of full iteration n as exactly zero, once, so that the method
+        restarts there."""
+        if not force_breakdown:
+            return self._krylov(self.lib.orc_bicgstab, b, x0, tol, maxit, want_r)
+        fn = self.lib.orc_bicgstab_forced
+
+        def forced(p, bp, xp, tol_, maxit_, rp, ip):
+            return fn(p, bp, xp, tol_, maxit_, int(force_breakdown), rp, ip)
+        return self._krylov(forced, b, x0, tol, maxit, want_r)
 
     def bicgstab2(self, b, x0, tol: float, maxit: int, want_r: bool = False,
-                  hashed_shadow: bool = False):
+                  hashed_shadow: bool = False, force_breakdown: int = 0):
         """BiCGStab with two reductions per iteration (oracle.c); with
         hashed_shadow the shadow residual is the index-hashed field of
-        shadow() instead of r0."""
-        if not hashed_shadow:
-            return self._krylov(self.lib.orc_bicgstab2, b, x0, tol, maxit, want_r)
+        shadow() instead of r0.  force_breakdown as for bicgstab."""
         fn = self.lib.orc_bicgstab2_shadow
 
         def with_shadow(p, bp, xp, tol_, maxit_, rp, ip):
-            return fn(p, bp, xp, tol_, maxit_, 1, rp, ip)
+            return fn(p, bp, xp, tol_, maxit_, 1 if hashed_shadow else 0,
+                      int(force_breakdown), rp, ip)
         return self._krylov(with_shadow, b, x0, tol, maxit, want_r)
 
     def shadow(self):

@@ -296,6 +296,13 @@ extern "C" int wfa_grid_tiling(wfa_grid* g, int* tx, int* ty, int* zc, int* bloc
   return WFA_OK;
 }
 
+extern "C" int wfa_grid_vector(wfa_grid* g, int which, void** ptr) {
+  if (!g || !ptr) return set_error(WFA_ERR_INVALID, "grid or ptr is NULL");
+  if (which < 0 || which >= kVecs) return set_error(WFA_ERR_INVALID, "no vector %d", which);
+  *ptr = g->vec[which];
+  return WFA_OK;
+}
+
 // ---------------------------------------------------------------------------
 // profiling
 // ---------------------------------------------------------------------------

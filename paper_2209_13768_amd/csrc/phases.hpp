@@ -32,6 +32,34 @@ template <typename T> __device__ __forceinline__ void st_once(T* p, T v) { *p = 
   __device__ auto value_own(const Raw& q) const { return val(combine(q)); }
 
 // ============================================================================
+// staged Krylov updates
+// ============================================================================
+// A staged value is computed once for the cell that stores it (combine_own)
+// and again by every neighbouring tile that reads the cell on its halo
+// (combine).  Both copies must round the same way, or the operator would be
+// applied to a vector that differs from the stored one at tile edges.  The
+// updates are therefore written with explicit fused multiply-adds, with
+// contraction off, so that no call site is left to the compiler's choice.
+// y - a x
+template <typename T>
+__device__ __forceinline__ T minus_ax(T y, T a, T x) {
+#pragma clang fp contract(off)
+  return fma_t(-a, x, y);
+}
+// p' = r' + beta (p - omega v)
+template <typename T>
+__device__ __forceinline__ T next_p(T rn, T p, T v, T beta, T omega) {
+#pragma clang fp contract(off)
+  return fma_t(beta, minus_ax(p, omega, v), rn);
+}
+// x' = x + alpha p + omega s, summed in that order
+template <typename T>
+__device__ __forceinline__ T next_x(T x, T p, T s, T alpha, T omega) {
+#pragma clang fp contract(off)
+  return fma_t(omega, s, fma_t(alpha, p, x));
+}
+
+// ============================================================================
 // finalizers (thread 0 of the last workgroup)
 // ============================================================================
 __device__ __forceinline__ bool fin_ok(double v) { return isfinite(v); }
@@ -350,7 +378,7 @@ struct PhA {
     return {r[i], p[i], v[i]};
   }
   __device__ T combine(const Raw& q) const {
-    return first ? q.r : q.r + beta * (q.p - omega * q.v);
+    return first ? q.r : next_p(q.r, q.p, q.v, beta, omega);
   }
   __device__ ORaw fetch_own(size_t i) const {
     if (first) return {r[i], T(0), T(0), ld_once(rh + i)};
@@ -358,13 +386,11 @@ struct PhA {
   }
   // p' is stored as soon as it is staged
   __device__ St combine_own(const ORaw& q, size_t i, double (&)[NV]) const {
-    const T pn = first ? q.r : q.r + beta * (q.p - omega * q.v);
+    const T pn = combine(Raw{q.r, q.p, q.v});
     st_once(p_out + i, pn);
     return {pn, q.rh};
   }
-  __device__ T value_own(const ORaw& q) const {
-    return first ? q.r : q.r + beta * (q.p - omega * q.v);
-  }
+  __device__ T value_own(const ORaw& q) const { return combine(Raw{q.r, q.p, q.v}); }
   __device__ ERaw efetch(size_t) const { return {}; }
   __device__ void epilogue(size_t i, const St& u, T Au, T, uint32_t, const ERaw&, T dg,
                            double (&acc)[NV]) const {
@@ -388,7 +414,7 @@ struct PhB {
   WFA_PLAIN_OWN_STAGE
   __device__ void bind(const Scalars* sc) { alpha = (T)sc->alpha; }
   __device__ Raw fetch(size_t i) const { return {r[i], v[i]}; }
-  __device__ T combine(const Raw& q) const { return q.r - alpha * q.v; }
+  __device__ T combine(const Raw& q) const { return minus_ax(q.r, alpha, q.v); }
   __device__ ERaw efetch(size_t) const { return {}; }
   __device__ void epilogue(size_t i, T s, T Au, T, uint32_t, const ERaw&, T dg,
                            double (&acc)[NV]) const {
@@ -421,7 +447,7 @@ struct PhCgA {
     if (first) return {r[i], T(0)};
     return {r[i], d[i]};
   }
-  __device__ T combine(const Raw& z) const { return first ? z.r : z.r + beta * z.d; }
+  __device__ T combine(const Raw& z) const { return first ? z.r : fma_t(beta, z.d, z.r); }
   __device__ ERaw efetch(size_t) const { return {}; }
   __device__ void epilogue(size_t i, T u, T Au, T, uint32_t, const ERaw&, T dg,
                            double (&acc)[NV]) const {
@@ -516,8 +542,8 @@ struct PhAC {
   }
   __device__ T combine(const Raw& q) const {
     if (first) return q.r;
-    const T rn = (q.r - alpha * q.v) - omega * q.t;
-    return rn + beta * (q.p - omega * q.v);
+    const T rn = minus_ax(minus_ax(q.r, alpha, q.v), omega, q.t);
+    return next_p(rn, q.p, q.v, beta, omega);
   }
   __device__ ORaw fetch_own(size_t i) const {
     const T sh = hashed ? hashed_shadow<T>(i) : ld_once(rh + i);
@@ -533,10 +559,10 @@ struct PhAC {
       rn = q.r;
       pn = q.r;
     } else {
-      const T s = q.r - alpha * q.v;
-      rn = s - omega * q.t;
-      pn = rn + beta * (q.p - omega * q.v);
-      st_once(x + i, q.x + alpha * q.p + omega * s);
+      const T s = minus_ax(q.r, alpha, q.v);
+      rn = minus_ax(s, omega, q.t);
+      pn = next_p(rn, q.p, q.v, beta, omega);
+      st_once(x + i, next_x(q.x, q.p, s, alpha, omega));
     }
     st_once(r_out + i, rn);
     st_once(p_out + i, pn);
@@ -574,7 +600,7 @@ struct PhB2 {
   WFA_PLAIN_OWN_STAGE
   __device__ void bind(const Scalars* sc) { alpha = (T)sc->alpha; }
   __device__ Raw fetch(size_t i) const { return {r[i], v[i]}; }
-  __device__ T combine(const Raw& q) const { return q.r - alpha * q.v; }
+  __device__ T combine(const Raw& q) const { return minus_ax(q.r, alpha, q.v); }
   __device__ ERaw efetch(size_t i) const {
     return {hashed ? hashed_shadow<T>(i) : ld_once(rh + i)};
   }
@@ -746,10 +772,10 @@ __device__ __forceinline__ bool aligned16(const void* a, const void* b, const vo
 template <typename T>
 __device__ __forceinline__ void phase_c_elem(T& x, T p, T& r, T v, T t, T rh, T alpha, T omega,
                                              bool xz, double (&acc)[2]) {
-  const T s = r - alpha * v;
+  const T s = minus_ax(r, alpha, v);
   const T xo = xz ? T(0) : x;
-  x = xo + alpha * p + omega * s;
-  const T rn = s - omega * t;
+  x = next_x(xo, p, s, alpha, omega);
+  const T rn = minus_ax(s, omega, t);
   r = rn;
   acc[0] += (double)rh * (double)rn;
   acc[1] += (double)rn * (double)rn;
@@ -809,8 +835,8 @@ __device__ __forceinline__ void cg_b_range(size_t n, int blk, int blocks, T* __r
       const VT da = ((const VT*)d)[e], qa = ((const VT*)q)[e];
 #pragma unroll
       for (int c = 0; c < N; ++c) {
-        xa.v[c] += alpha * da.v[c];
-        ra.v[c] = ra.v[c] - alpha * qa.v[c];
+        xa.v[c] = fma_t(alpha, da.v[c], xa.v[c]);
+        ra.v[c] = minus_ax(ra.v[c], alpha, qa.v[c]);
         acc[0] += (double)ra.v[c] * (double)ra.v[c];
       }
       xv[e] = xa;
@@ -819,8 +845,8 @@ __device__ __forceinline__ void cg_b_range(size_t n, int blk, int blocks, T* __r
     done = nv * N;
   }
   for (size_t e = done + (size_t)blk * kThreads + threadIdx.x; e < n; e += stride) {
-    x[e] += alpha * d[e];
-    const T rn = r[e] - alpha * q[e];
+    x[e] = fma_t(alpha, d[e], x[e]);
+    const T rn = minus_ax(r[e], alpha, q[e]);
     r[e] = rn;
     acc[0] += (double)rn * (double)rn;
   }

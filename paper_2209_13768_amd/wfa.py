@@ -27,6 +27,7 @@ OPT_EXPLICIT_FUSE, OPT_SHADOW, OPT_FORCE_DIVERGE, OPT_CG1_MAX_CELLS = 11, 12, 13
 K_APPLY, K_INIT, K_PHASE_A, K_PHASE_B, K_PHASE_C, K_RESIDUAL, K_PROMOTE = 0, 1, 2, 3, 4, 5, 6
 K_CG_A, K_CG_B, K_PERSISTENT, K_PHASE_AC, K_PHASE_B2, K_EXPLICIT = 7, 8, 9, 10, 11, 12
 K_EXPLICIT_FUSED, K_CG1, K_COUNT = 13, 14, 15
+VEC_R, VEC_RHAT, VEC_T, VEC_P0, VEC_P1, VEC_V0, VEC_V1, VEC_B, VEC_R1 = range(9)
 KERNEL_NAMES = ("apply", "init", "phase_a", "phase_b", "phase_c", "residual", "promote",
                 "cg_a", "cg_b", "persistent", "phase_ac", "phase_b2", "explicit", "explicit_fused",
                 "cg1")
@@ -37,7 +38,8 @@ PRECISIONS = {"f64": F64, "f32": F32, "f32_ir64": F32_IR64}
 EXPORTS = (
     "wfa_workspace_bytes", "wfa_grid_create", "wfa_grid_destroy", "wfa_stencil_apply",
     "wfa_rhs", "wfa_explicit_step", "wfa_bicgstab_solve", "wfa_bicgstab2_solve", "wfa_cg_solve", "wfa_cg1_solve", "wfa_timestep", "wfa_true_residual",
-    "wfa_grid_set_option", "wfa_kernel_stats", "wfa_grid_tiling", "wfa_stream_probe",
+    "wfa_grid_set_option", "wfa_kernel_stats", "wfa_grid_tiling", "wfa_grid_vector",
+    "wfa_stream_probe",
     "wfa_server_create", "wfa_server_set_option", "wfa_submit", "wfa_poll", "wfa_server_drain",
     "wfa_server_destroy",
     "wfa_last_error", "wfa_version", "wfa_autotune", "wfa_tune_save", "wfa_tune_load",
@@ -125,6 +127,7 @@ def lib() -> ctypes.CDLL:
     L.wfa_kernel_stats.argtypes = [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(dbl),
                                    ctypes.POINTER(dbl), i32]
     L.wfa_grid_tiling.argtypes = [vp] + [ctypes.POINTER(i32)] * 4
+    L.wfa_grid_vector.argtypes = [vp, i32, ctypes.POINTER(vp)]
     L.wfa_stream_probe.argtypes = [vp, vp, sz, i32, ctypes.POINTER(dbl), vp]
     L.wfa_server_create.argtypes = [vp, sz, i32, vp, ctypes.POINTER(vp)]
     L.wfa_server_set_option.argtypes = [vp, i32, i64]
@@ -325,6 +328,18 @@ class Grid:
         v = [ctypes.c_int() for _ in range(4)]
         _check(lib().wfa_grid_tiling(self._h, *[ctypes.byref(q) for q in v]))
         return tuple(q.value for q in v)
+
+    def vector(self, which: int):
+        """A view (no copy) of one of the grid's Krylov vectors inside its
+        workspace (wfa_grid_vector), shape (nz, ny, nx)."""
+        torch = _torch()
+        ptr = ctypes.c_void_p()
+        _check(lib().wfa_grid_vector(self._h, int(which), ctypes.byref(ptr)))
+        dt = torch.float64 if self.precision == F64 else torch.float32
+        off = ptr.value - self.workspace.data_ptr()
+        nbytes = self.n * (8 if dt == torch.float64 else 4)
+        assert 0 <= off and off + nbytes <= self.workspace.numel()
+        return self.workspace[off:off + nbytes].view(dt).view(self.shape)
 
 
 def tune_save(path: str):

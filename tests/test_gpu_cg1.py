@@ -20,11 +20,9 @@ import pytest
 from paper_2209_13768_amd import inputs
 from paper_2209_13768_amd.inputs import DIRICHLET, ZEROFLUX
 from tests.oracle_helpers import rel_l2
+from tests.parity_bars import FP32_TOL, FP64_TOL, check, sensitivity, trajectory_bound
 
 pytestmark = pytest.mark.gpu
-
-FP64_TOL = 1e-12
-FP32_TOL = 1e-5
 
 
 @pytest.fixture(scope="module")
@@ -60,11 +58,7 @@ def _sensitivity(o, b, x0, k):
     by one ulp in a random direction.  On the nearly all-zero-flux grid the
     recurrences amplify rounding of x0 far more than rounding of b (by 1e3 at
     k = 20), so both are taken."""
-    xk, _ = o.cg1(b, x0, 1e-300, k)
-    xi = np.random.default_rng(0).choice([-1.0, 1.0], size=b.shape)
-    xb, _ = o.cg1(b * (1 + 2.0 ** -52 * xi), x0, 1e-300, k)
-    xx, _ = o.cg1(b, x0 * (1 + 2.0 ** -52 * xi), 1e-300, k)
-    return max(rel_l2(xb, xk), rel_l2(xx, xk))
+    return sensitivity(lambda bb, xx: o.cg1(bb, xx, 1e-300, k)[0], b, x0, seeds=(0,))
 
 
 @pytest.mark.parametrize("k", [1, 2, 5, 10, 20])
@@ -75,12 +69,13 @@ def test_cg1_trajectory_fp64(wfa, oracle_mod, name, k):
     b = o.rhs(prob.T0)
     xo, io = o.cg1(b, prob.T0, 1e-300, k)
     assert io.iterations == k
-    bound = max(FP64_TOL, 100 * _sensitivity(o, b, prob.T0, k))
+    sx = _sensitivity(o, b, prob.T0, k)
+    bound = trajectory_bound(sx, k + 1)     # k iterations after w0 = A r0
     g = wfa.Grid.from_problem(prob, precision=wfa.F64)
     x, info = g.solve(g.field(b), g.field(prob.T0), tol=1e-300, maxit=k, method="cg1",
                       check=False)
     assert info.status == wfa.ERR_NOCONV and info.iterations == k
-    assert rel_l2(to_np(x), xo) <= bound
+    check(f"cg1 f64 {name} k={k} x", rel_l2(to_np(x), xo), bound, sx)
     # the recursive residual norm the library reports (relative to ||b||) is
     # the oracle's; a wrong reduction would move it at O(1)
     assert abs(info.rel_res_recursive - io.rel_res_recursive) <= 1e-8
@@ -314,8 +309,9 @@ def test_cg1_degenerate_and_ragged_grids(wfa, oracle_mod, shape, name):
     assert rel_l2(to_np(x), xo) <= 1e-11
     if prob.cells >= 8:
         xk, _ = o.cg1(b, prob.T0, 1e-300, 2)
-        bound = max(FP64_TOL, 100 * _sensitivity(o, b, prob.T0, 2))
+        sx = _sensitivity(o, b, prob.T0, 2)
         x2, i2 = g.solve(g.field(b), g.field(prob.T0), tol=1e-300, maxit=2, method="cg1",
                          check=False)
         assert i2.iterations == 2
-        assert rel_l2(to_np(x2), xk) <= bound
+        check(f"cg1 f64 edge {name} {'x'.join(map(str, shape))} k=2 x", rel_l2(to_np(x2), xk),
+              trajectory_bound(sx, 3), sx)

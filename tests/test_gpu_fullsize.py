@@ -23,6 +23,7 @@ import pytest
 
 from paper_2209_13768_amd import inputs
 from tests.oracle_helpers import rel_l2
+from tests.parity_bars import check, sensitivity, trajectory_bound
 
 pytestmark = pytest.mark.gpu
 
@@ -49,12 +50,10 @@ def convdiff256():
 
 
 def _sensitivity(o, b, x0, k):
-    """How far the oracle's own k-th iterate moves when b is perturbed by one
-    ulp in a random direction."""
-    xk, _ = o.bicgstab2(b, x0, 1e-300, k, hashed_shadow=True)
-    xi = np.random.default_rng(0).choice([-1.0, 1.0], size=b.shape)
-    xp, _ = o.bicgstab2(b * (1 + 2.0 ** -52 * xi), x0, 1e-300, k, hashed_shadow=True)
-    return rel_l2(xp, xk)
+    """How far the oracle's own k-th iterate moves when b (and x0) is
+    perturbed by one ulp in a random direction."""
+    return sensitivity(lambda bb, xx: o.bicgstab2(bb, xx, 1e-300, k, hashed_shadow=True)[0],
+                       b, x0, seeds=(0,))
 
 
 def test_convdiff256_operator(wfa, oracle_mod, convdiff256):
@@ -77,13 +76,14 @@ def test_convdiff256_first_iterates(wfa, oracle_mod, convdiff256, k):
     o = oracle_mod.Oracle(prob)
     b = o.rhs(prob.T0)
     xo, io = o.bicgstab2(b, prob.T0, 1e-300, k, hashed_shadow=True)
-    bound = max(FP64_TOL, 100 * _sensitivity(o, b, prob.T0, k))
+    sx = _sensitivity(o, b, prob.T0, k)
+    bound = trajectory_bound(sx, 2 * k)
     g = wfa.Grid.from_problem(prob, precision=wfa.F64)
     g.set_option(wfa.OPT_SHADOW, 1)
     x, info = g.solve(g.field(b), g.field(prob.T0), tol=1e-300, maxit=k, method="bicgstab2",
                       check=False)
     assert info.status == wfa.ERR_NOCONV and info.iterations == k == io.iterations
-    assert rel_l2(_np(x), xo) <= bound
+    check(f"convdiff256 hashed bicgstab2 f64 k={k} x", rel_l2(_np(x), xo), bound, sx)
     g32 = wfa.Grid.from_problem(prob, precision=wfa.F32)
     g32.set_option(wfa.OPT_SHADOW, 1)
     x32, _ = g32.solve(g32.field(b), g32.field(prob.T0), tol=1e-300, maxit=k,

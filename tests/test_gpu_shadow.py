@@ -6,7 +6,8 @@ import pytest
 
 from paper_2209_13768_amd import inputs
 from tests.oracle_helpers import rel_l2
-from tests.test_gpu_parity import FP32_TOL, FP64_TOL, VARIANTS, to_np
+from tests.parity_bars import FP32_TOL, FP64_TOL, check, sensitivity, trajectory_bound
+from tests.test_gpu_parity import VARIANTS, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -26,16 +27,11 @@ def _grid(wfa, prob, precision):
     return g
 
 
-def _sensitivity(o, b, x0, k, eps=2.0 ** -52, seeds=(0, 1)):
-    """How far the oracle's own k-th iterate moves under a rounding-level
-    perturbation of b (BiCGStab amplifies rounding)."""
-    xk, _ = o.bicgstab2(b, x0, 1e-300, k, hashed_shadow=True)
-    dx = 0.0
-    for sd in seeds:
-        xi = np.random.default_rng(sd).choice([-1.0, 1.0], size=b.shape)
-        xp, _ = o.bicgstab2(b * (1 + eps * xi), x0, 1e-300, k, hashed_shadow=True)
-        dx = max(dx, rel_l2(xp, xk))
-    return dx
+def _sensitivity(o, b, x0, k):
+    """How far the oracle's own k-th iterate moves under a one-ulp
+    perturbation of b (and x0): BiCGStab amplifies rounding."""
+    return sensitivity(lambda bb, xx: o.bicgstab2(bb, xx, 1e-300, k, hashed_shadow=True)[0],
+                       b, x0)
 
 
 @pytest.mark.parametrize("k", [1, 2, 5, 10, 20])
@@ -49,7 +45,9 @@ def test_hashed_shadow_trajectory_fp64(wfa, oracle_mod, name, k):
     g = _grid(wfa, prob, wfa.F64)
     x, info = g.solve(g.field(b), g.field(), tol=1e-300, maxit=k, method="bicgstab2")
     assert info.status == wfa.ERR_NOCONV and info.iterations == k == io.iterations
-    assert rel_l2(to_np(x), xo) <= max(FP64_TOL, 100 * _sensitivity(o, b, x0, k))
+    sx = _sensitivity(o, b, x0, k)
+    check(f"hashed bicgstab2 f64 {name} k={k} x", rel_l2(to_np(x), xo), trajectory_bound(sx, 2 * k),
+          sx)
     # a different shadow vector gives different iterates: the option took effect
     xr, _ = o.bicgstab2(b, x0, 1e-300, k)
     if k >= 2:

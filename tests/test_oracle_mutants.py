@@ -77,6 +77,31 @@ MUTANTS = [
      "memcpy(rh, r, bytes);"),
     ("dot_drops_last_plane", "for (int k = 0; k < nz; ++k) total += part[k];",
      "for (int k = 0; k + 1 < nz; ++k) total += part[k];"),
+    ("true_relres_zero", "return bn > 0.0 ? rn / bn : rn;", "return 0.0;"),
+    ("true_relres_squared", "return bn > 0.0 ? rn / bn : rn;",
+     "return bn > 0.0 ? (rn / bn) * (rn / bn) : rn;"),
+    ("true_relres_absolute", "return bn > 0.0 ? rn / bn : rn;", "return rn;"),
+    ("true_relres_residual_sign", "for (long c = 0; c < n; ++c) r[c] = b[c] - r[c];\n}\n\n/*\n * The operator",
+     "for (long c = 0; c < n; ++c) r[c] = b[c] + r[c];\n}\n\n/*\n * The operator"),
+    ("restart_breaks_down",
+     "  do_restart:\n    if (++restarts > ORC_MAX_RESTARTS) { status = ORC_BREAKDOWN; goto done; }\n"
+     "    goto restart;\n  }\n  status = ORC_NOCONV;",
+     "  do_restart:\n    if (++restarts > 0) { status = ORC_BREAKDOWN; goto done; }\n"
+     "    goto restart;\n  }\n  status = ORC_NOCONV;"),
+    ("restart_keeps_old_shadow", "  memcpy(rh, r, bytes);\n  memset(pv, 0, bytes);",
+     "  if (restarts == 0) memcpy(rh, r, bytes);\n  memset(pv, 0, bytes);"),
+    ("restart_keeps_direction", "  memset(pv, 0, bytes);\n  memset(v, 0, bytes);",
+     "  if (restarts == 0) { memset(pv, 0, bytes); memset(v, 0, bytes); }"),
+    ("restart_counts_cut_iteration", "    --it;                                /* ended before its update of x */\n",
+     ""),
+    ("bicgstab2_restart_breaks_down",
+     "    if (++restarts > ORC_MAX_RESTARTS) { status = ORC_BREAKDOWN; goto done; }\n"
+     "    goto restart;\n  }\n\ndone:",
+     "    if (++restarts > 0) { status = ORC_BREAKDOWN; goto done; }\n"
+     "    goto restart;\n  }\n\ndone:"),
+    ("bicgstab2_restart_keeps_old_shadow",
+     "if (hashed_shadow) orc_shadow(n, rh);\n  else memcpy(rh, r, bytes);",
+     "if (hashed_shadow) orc_shadow(n, rh);\n  else if (restarts == 0) memcpy(rh, r, bytes);"),
 ]
 
 

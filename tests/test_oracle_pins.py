@@ -685,3 +685,136 @@ def test_cg1_finite_termination_on_random_small_grids(oracle_mod):
         x, info = o.cg1(b, p.T0, 1e-15, n + 10)
         assert info.status in (oracle_mod.OK, oracle_mod.NOCONV), (case, info)
         assert rel_l2(x, x_ref) <= 1e-12, (case, shape, bc, cell)
+
+
+# ------------------------------------------------- true relative residual
+def _mode_eigenvalue(shape, modes, alpha, dt, h):
+    return 1.0 + dt * alpha / h**2 * sum(4 * np.sin(np.pi * m / (2 * (n + 1)))**2
+                                         for m, n in zip(modes, shape))
+
+
+@pytest.mark.parametrize("shape,mv,mw,eps", [
+    ((5, 6, 7), (1, 1, 1), (2, 3, 1), 1e-3),
+    ((8, 4, 3), (3, 2, 2), (1, 1, 1), 0.25),
+    ((16, 9, 11), (2, 1, 4), (5, 7, 3), 1e-6),
+])
+def test_true_relres_closed_form(oracle_mod, shape, mv, mw, eps):
+    """||b - A x|| / ||b|| of section 1.1.2's A x = b in closed form: with v
+    and w sine-product eigenmodes of pure diffusion (eigenvalues lv, lw),
+    b = lv v and x = v + eps w give b - A x = -eps lw w.  A sine product with
+    0 < m_d <= n_d has squared norm prod_d (n_d + 1) / 2 whatever its modes,
+    so the ratio is exactly eps lw / lv."""
+    nx, ny, nz = shape
+    alpha, dt = 1.0, 1e-2
+    p = const_problem(nx, ny, nz, alpha=alpha, dt=dt)
+    o = oracle_mod.Oracle(p)
+    h = p.h
+    v, w = sine_mode(nx, ny, nz, *mv), sine_mode(nx, ny, nz, *mw)
+    lv = _mode_eigenvalue(shape, mv, alpha, dt, h)
+    lw = _mode_eigenvalue(shape, mw, alpha, dt, h)
+    want = eps * lw / lv
+    got = o.true_relres(lv * v, v + eps * w)
+    assert abs(got - want) <= 1e-9 * want + 1e-15 * lw / lv
+    # b = 0: the absolute residual norm ||A x||, here lw ||w||
+    got0 = o.true_relres(np.zeros(p.shape), w)
+    want0 = lw * np.sqrt(np.prod([(n + 1) / 2.0 for n in shape]))
+    assert abs(got0 - want0) <= 1e-12 * want0
+    # x the exact solution: residual at rounding level
+    assert o.true_relres(lv * v, v) <= 1e-14
+
+
+@pytest.mark.parametrize("u,bc", [
+    ((0.0, 0.0, 0.0), (DIRICHLET,) * 6),
+    ((1.0, 0.5, 0.25), inputs.MIXED_BC_KIND),
+    ((-2.0, 3.0, -1.0), (ZEROFLUX, DIRICHLET, DIRICHLET, ZEROFLUX, ZEROFLUX, DIRICHLET)),
+])
+def test_true_relres_against_kronecker_matrix(oracle_mod, u, bc):
+    """The same ratio from the Kronecker-sum matrix (assembled here, not by
+    the oracle) and numpy's norms, on 4x4x4 grids with random b and x."""
+    n = 4
+    alpha, dt = 0.9, 3e-2
+    p = const_problem(n, n, n, alpha=alpha, dt=dt, u=u, bc_kind=bc)
+    o = oracle_mod.Oracle(p)
+    h = p.h
+    D = dt * alpha / h**2
+    T = [_axis_operator(n, D, dt * u[a] / h, bc[2 * a], bc[2 * a + 1]) for a in range(3)]
+    I = sp.identity(n)
+    A = (sp.identity(n**3) + sp.kron(I, sp.kron(I, T[0])) + sp.kron(I, sp.kron(T[1], I))
+         + sp.kron(T[2], sp.kron(I, I))).toarray()
+    rng = np.random.default_rng(301)
+    for scale in (1.0, 1e-3):
+        b = rng.standard_normal(p.shape)
+        x = np.linalg.solve(A, b.ravel()).reshape(p.shape) + scale * rng.standard_normal(p.shape)
+        want = np.linalg.norm(b.ravel() - A @ x.ravel()) / np.linalg.norm(b.ravel())
+        assert abs(o.true_relres(b, x) - want) <= 1e-12 * want
+
+
+def test_true_relres_scale_invariance(oracle_mod):
+    """A ratio: scaling b and x by one power of two changes nothing, bit for
+    bit; scaling x alone by 2 changes the residual of x = 0 not at all."""
+    p = inputs.random_problem(302, 7, 6, 5, cell=True, u=(1.0, -0.5, 0.25))
+    o = oracle_mod.Oracle(p)
+    b = o.rhs(p.T0)
+    x = p.T0
+    r1 = o.true_relres(b, x)
+    assert r1 > 0.0
+    assert o.true_relres(b * 2.0**37, x * 2.0**37) == r1
+    assert o.true_relres(b, np.zeros(p.shape)) == 1.0
+
+
+# ------------------------------------------------- breakdown restart (R8)
+def _textbook_with_restart(apply, b, x0, k, n, shadow=None):
+    """k completed iterations of textbook BiCGStab when sigma of iteration n
+    is taken as zero: n - 1 iterations from x0, then a fresh start from that
+    iterate (new residual; r^ = that residual unless a fixed shadow field is
+    given) for the remaining k - n + 1.  Restated independently here."""
+    def run(x, m):
+        rh = shadow if shadow is not None else b - apply(x)
+        return _textbook_bicgstab(apply, b, x, rh, m) if m > 0 else x
+    if k < n:
+        return run(x0, k)
+    return run(run(x0, n - 1), k - n + 1)
+
+
+@pytest.mark.parametrize("form", ["textbook", "two_reduction", "two_reduction_hashed"])
+@pytest.mark.parametrize("n", [1, 4])
+def test_forced_restart_follows_textbook(oracle_mod, form, n):
+    """A breakdown at iteration n restarts from b - A x_{n-1}: the iterates
+    that follow are those of a fresh textbook BiCGStab from x_{n-1}, and the
+    cut iteration is not counted."""
+    p = inputs.random_problem(303, 12, 10, 9, cell=True, u=(1.0, 0.5, 0.25),
+                              bc_kind=inputs.MIXED_BC_KIND)
+    o = oracle_mod.Oracle(p)
+    b = o.rhs(p.T0)
+    shadow = o.shadow() if form == "two_reduction_hashed" else None
+    for k in sorted({max(n - 1, 1), n, n + 1, n + 4}):
+        want = _textbook_with_restart(o.apply, b, p.T0.copy(), k, n, shadow)
+        if form == "textbook":
+            x, info = o.bicgstab(b, p.T0, 1e-300, k, force_breakdown=n)
+        else:
+            x, info = o.bicgstab2(b, p.T0, 1e-300, k, force_breakdown=n,
+                                  hashed_shadow=shadow is not None)
+        assert info.status == oracle_mod.NOCONV and info.iterations == k, (k, info)
+        assert info.restarts == (1 if k >= n else 0), (k, info)
+        assert rel_l2(x, want) <= 1e-12, (form, n, k)
+        # the restart really took another path than the unforced solve (a
+        # restart at iteration 1 starts from x0 again: the same path)
+        if n > 1 and k >= n + 1:
+            plain = _textbook_with_restart(o.apply, b, p.T0.copy(), k, 10**9, shadow)
+            assert rel_l2(x, plain) > 1e-8
+
+
+@pytest.mark.parametrize("form", ["textbook", "two_reduction", "two_reduction_hashed"])
+def test_forced_restart_reaches_dense_solution(oracle_mod, form):
+    p = inputs.random_problem(304, 4, 4, 4, cell=True, u=(3.0, -2.0, 1.0))
+    o = oracle_mod.Oracle(p)
+    A = dense_by_columns(o)
+    b = o.rhs(p.T0)
+    x_ref = np.linalg.solve(A, b.ravel()).reshape(p.shape)
+    if form == "textbook":
+        x, info = o.bicgstab(b, p.T0, 1e-14, 400, force_breakdown=3)
+    else:
+        x, info = o.bicgstab2(b, p.T0, 1e-14, 400, force_breakdown=3,
+                              hashed_shadow=form.endswith("hashed"))
+    assert info.status == oracle_mod.OK and info.restarts == 1
+    assert rel_l2(x, x_ref) <= 1e-12
