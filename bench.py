@@ -1,31 +1,40 @@
-"""Benchmark: BiCGStab cell-iterations/s and HBM-roofline fraction on one MI355X.
+"""Benchmark: BiCGStab cell-iterations/s and HBM-roofline fraction on one
+MI355X, with p50/p99 solve latency of a served request stream.
 
-Default workload (a "step" = one backward-Euler time step = one BiCGStab
-solve of the whole grid): 256^3 convection-diffusion, FP64, log-normal
-per-cell diffusivity (mu 0, sigma 1), velocity (1, 0.5, 0.25) with
-first-order upwind, dt 1e-2, x- Dirichlet 1 / x+ Dirichlet 0 / y, z
-zero-flux, BiCGStab to a relative residual of 1e-8, solved with the
-two-reduction organisation of BiCGStab and a shadow residual hashed from
-the cell index (--shadow r0 stores r^ = r0 instead); the r^ = r0 form and
-the textbook three-pass BiCGStab are timed on the same steps for
-comparison.  Inputs are synthetic and seeded
-(paper_2209_13768_amd.inputs.convdiff).
+Default workload (headline): one backward-Euler step of pure diffusion on a
+512 x 512 x 1024 grid (268M cells) in FP32, smooth 8-mode per-cell
+diffusivity in [0.5, 2], dt 1, Dirichlet 0 on every face, exactly 500
+BiCGStab iterations (two-reduction organisation, shadow residual hashed from
+the cell index; paper_2209_13768_amd.inputs.poisson_large).  A "step" is
+that whole solve (right-hand side, initial residual, 500 iterations, FP64
+true residual) restarted from the same T0, so that every step does the same
+work.
 
-Prints one JSON line.  `value` = cells x BiCGStab iterations / seconds over
-the K timed steps (inputs resident in HBM, HIP-event timing on the solve
-stream, plain launches).  `roofline` is for the kernel with the largest
-share of GPU time; its average duration comes from HIP events around every
-launch of that kernel while the same K steps run again from the same
-initial field; `traffic` is the HBM bytes per launch measured
-with rocprofv3 counters (profiles/) when they were taken from the current
-kernel sources, else null.  `cpu_baseline` times the FP64 CPU oracle on a
-bounded sample of the same workload on this host.
+Prints one JSON line:
+  value      cells x iterations / seconds over all K timed steps (HIP events
+             on the solve stream around the K steps; inputs resident in HBM);
+  roofline   the dominant kernel's algorithmic bytes per launch over its mean
+             duration, from HIP events around every launch inside the same
+             timed steps; traffic = HBM bytes per launch from rocprofv3
+             counters (profiles/) when taken from the current kernel
+             sources, else null;
+  t_eff      the paper's effective-bandwidth figure (section 3.1.3):
+             A_eff = 2 D_u + D_k over the step time;
+  oracle     the error against the FP64 oracle (after 10 iterations, the
+             same method) and the oracle-evaluated true residual at exit;
+  compare    the 256^3 FP64 convection-diffusion time integration (50 steps
+             to 1e-8), the 32^3 heat workload (10 steps), the 384^3 FP32-in-
+             FP64 refinement against plain FP64 (to 1e-10), CG with one
+             reduction on the headline grid, each with its error against the
+             oracle;
+  solve_latency_ms  p50/p99 of the 2000-request serving stream (200/s, grids
+             32..192 per axis, FP32 in FP64 refinement to 1e-10);
+  cpu_baseline  the FP64 oracle timed on this host: 10 iterations of the
+             headline solve on every core, and 1 iteration on one core.
 
-Other workloads (--workload): heat32 (32^3, 10 steps), poisson_large
-(512x512x1024 FP32, 500 iterations), mixed384 (FP32 inside FP64 refinement
-vs FP64), serve (Poisson request stream through the batching server),
-explicit (forward-time steps, one and several per pass), apply (the
-operator alone).  --method cg and cg1 apply to the symmetric workloads.
+Other workloads (--workload): convdiff (256^3 time steps, the round-one
+headline), heat32, poisson_large (headline grid, other methods), mixed384,
+serve, explicit, apply, ceilings (HBM copy ceilings).
 """
 import argparse
 import hashlib
@@ -38,7 +47,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_convdiff256_f64.json")
+TRAFFIC_FILES = {
+    "headline": os.path.join(ROOT, "profiles", "traffic_poisson512x512x1024_f32.json"),
+    "convdiff": os.path.join(ROOT, "profiles", "traffic_convdiff256_f64.json"),
+}
+HEADLINE_ITERS = 500
 
 
 # The files that define the single-grid solver kernels and their launch
@@ -68,11 +81,11 @@ def library_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed counter summary,
-    if it was taken from the current kernel sources."""
+def load_traffic(kernel: str, workload: str = "convdiff"):
+    """HBM bytes per launch of `kernel` from the committed counter summary of
+    `workload`, if it was taken from the current kernel sources."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(TRAFFIC_FILES[workload]) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
@@ -150,7 +163,7 @@ def summarize_counters(fetch_csv: str, write_csv: str, workload: str, commands: 
                                 "write_kib": round(write["copy"][0], 1),
                                 "fetch_factor": round(f_fetch, 4), "write_factor": round(f_write, 4)},
            "kernels": kernels}
-    with open(TRAFFIC_FILE, "w") as f:
+    with open(TRAFFIC_FILES[workload], "w") as f:
         json.dump(out, f, indent=1)
         f.write("\n")
     return out
@@ -525,9 +538,10 @@ def run_mixed384(args, torch, inputs, wfa):
     return out
 
 
-def run_serve(args, torch, inputs, wfa):
+def run_serve(args, torch, inputs, wfa, keep_fields=False):
     """Poisson request stream (200/s) of heat-step solves on grids with dims
-    in {32,...,192}, FP32 inside FP64 refinement to 1e-10."""
+    in {32,...,192}, FP32 inside FP64 refinement to 1e-10.  keep_fields: the
+    result also carries the solved device fields (key "_fields")."""
     reqs = inputs.request_stream(count=args.requests)
     prec = wfa.PRECISIONS[args.serve_precision]
     fields = []
@@ -565,7 +579,8 @@ def run_serve(args, torch, inputs, wfa):
         cg = args.serve_method == "cg1" and (limit == 0 or cells <= limit)
         passes += info.iterations * (1 if cg else 2)
     sv.close()
-    return {"workload": f"serve_{args.requests}req_200rps", "precision": args.serve_precision,
+    extra = {"_fields": fields} if keep_fields else {}
+    return {**extra, "workload": f"serve_{args.requests}req_200rps", "precision": args.serve_precision,
             "method": args.serve_method,
             "cg1_max_cells": args.serve_cg1_max_cells if args.serve_method == "cg1" else None,
             "round": {"iterations": args.serve_round,
@@ -648,6 +663,472 @@ def run_explicit(args, torch, inputs, wfa):
     return out
 
 
+# ---------------------------------------------------------------------------
+# headline: 512 x 512 x 1024 FP32, 500 fixed iterations per step
+# ---------------------------------------------------------------------------
+_T_START = time.perf_counter()
+
+
+def progress(msg: str) -> None:
+    """One line per finished phase on stderr (the JSON line goes to stdout)."""
+    print(f"[bench {time.perf_counter() - _T_START:7.1f} s] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_info() -> dict:
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cores": usable}
+
+
+def rel_l2(a, b) -> float:
+    import numpy as np
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    nb = float(np.linalg.norm(b))
+    return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
+
+
+def kernel_table(g, wfa) -> dict:
+    kernels = {}
+    for k, name in enumerate(wfa.KERNEL_NAMES):
+        n, ms, by = g.kernel_stats(k)
+        if n:
+            kernels[name] = {"launches": n, "ms_total": round(ms, 3),
+                             "us_avg": round(ms / n * 1e3, 2), "alg_bytes_per_launch": by,
+                             "gbps": round(by / (ms / n * 1e-3) / 1e9, 1)}
+    return kernels
+
+
+def copy_ceiling(torch, wfa, nbytes: int = COPY_PROBE_BYTES) -> dict:
+    """The measured copy ceilings on this GPU: the library's nontemporal copy
+    kernel and hipMemcpyAsync device-to-device (torch's copy_), GB/s read +
+    written."""
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    src.fill_(1)
+    kern = wfa.bandwidth_probe(wfa.PROBE_COPY, src, dst, reps=10)
+    dst.copy_(src)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(10):
+        dst.copy_(src)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    memcpy = 2.0 * nbytes * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    return {"copy_kernel_gbps": round(kern, 1), "memcpy_d2d_gbps": round(memcpy, 1)}
+
+
+def oracle_sample(prob, T0_32, iters: int):
+    """The FP64 oracle (test infrastructure) on the headline solve: `iters`
+    iterations of the same method (two-reduction BiCGStab, hashed shadow)
+    from the same FP32-rounded T0, on every core, then one iteration on one
+    core.  Returns (cpu_baseline, x_iters)."""
+    import numpy as np
+    import oracle
+    o = oracle.Oracle(prob)
+    T0 = T0_32.astype(np.float64)
+    b = o.rhs(T0)
+    threads = oracle.num_threads()
+    t0 = time.perf_counter()
+    x, info = o.bicgstab2(b, T0, 1e-300, iters, hashed_shadow=True)
+    dt = time.perf_counter() - t0
+    # one core: one iteration on the first 128 z-planes of the same fields
+    # (the oracle streams every vector through memory, so its rate per cell
+    # does not depend on the grid's depth)
+    nzs = min(128, prob.nz)
+    slab = prob.with_(nz=nzs, kappa=prob.kappa[:nzs].copy(), T0=T0[:nzs].copy())
+    os_ = oracle.Oracle(slab)
+    bs = os_.rhs(slab.T0)
+    oracle.set_num_threads(1)
+    t1 = time.perf_counter()
+    _, info1 = os_.bicgstab2(bs, slab.T0, 1e-300, 1, hashed_shadow=True)
+    dt1 = time.perf_counter() - t1
+    oracle.set_num_threads(threads)
+    del os_, bs
+    base = {
+        "value": prob.cells * info.iterations / dt,
+        "unit": "cell-iters/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"{info.iterations} iterations of the headline solve (two-reduction BiCGStab, "
+                  f"hashed shadow, FP64) on the full {prob.nx}x{prob.ny}x{prob.nz} grid, "
+                  f"including the initial residual and the final true residual, {dt:.1f} s",
+        "one_core": {"value": slab.cells * info1.iterations / dt1, "cores": 1,
+                     "sample": f"1 iteration of the same solve on the first {nzs} z-planes "
+                               f"({slab.nx}x{slab.ny}x{nzs}), including the initial and "
+                               f"final residual products, {dt1:.1f} s"},
+        **cpu_info(),
+    }
+    return base, x, o, b
+
+
+def leg_c2(args, torch, inputs, wfa, oracle_mod):
+    """256^3 convection-diffusion, FP64, the 50-step time integration to 1e-8
+    (two-reduction BiCGStab, hashed shadow), with the oracle-evaluated true
+    residual of every step's result and the first iterates against the
+    oracle's."""
+    import numpy as np
+    prob = inputs.convdiff(n=256)
+    g = wfa.Grid.from_problem(prob, precision=wfa.F64)
+    g.set_option(wfa.OPT_METHOD, METHODS["bicgstab2"])
+    g.set_option(wfa.OPT_SHADOW, 1)
+    o = oracle_mod.Oracle(prob)
+    T = g.field(prob.T0)
+    g.timestep(T, 1, tol=1e-8, maxit=20000, check=False)      # warm-up
+    T = g.field(prob.T0)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    infos, worst, Tprev = [], 0.0, prob.T0
+    total_ms = 0.0
+    for k in range(args.c2_steps):
+        torch.cuda.synchronize()
+        e0.record(stream)
+        infos += g.timestep(T, 1, tol=1e-8, maxit=20000, check=False)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        total_ms += e0.elapsed_time(e1)
+        Tn = T.cpu().numpy()
+        if k < 3 or k == args.c2_steps - 1:   # the oracle's operator on this step's system
+            worst = max(worst, o.true_relres(o.rhs(Tprev), Tn))
+        Tprev = Tn
+        if (k + 1) % 10 == 0:
+            progress(f"c2: {k + 1} steps")
+    iters = sum(i.iterations for i in infos)
+    b = o.rhs(prob.T0)
+    first = {}
+    for k in (1, 2):
+        xo, _ = o.bicgstab2(b, prob.T0, 1e-300, k, hashed_shadow=True)
+        x, _ = g.solve(g.field(b), g.field(prob.T0), tol=1e-300, maxit=k, method="bicgstab2",
+                       check=False)
+        first[f"k{k}"] = rel_l2(x.cpu().numpy(), xo)
+    return {"workload": "convdiff_256^3_f64", "steps": args.c2_steps, "tol": 1e-8,
+            "method": "bicgstab2", "shadow": "hashed",
+            "value": prob.cells * iters / (total_ms * 1e-3),
+            "ms_per_step": total_ms / args.c2_steps, "iterations_per_step": iters / args.c2_steps,
+            "status_ok_steps": sum(1 for i in infos if i.status == wfa.OK),
+            "rel_res_true_max": max(i.rel_res_true for i in infos),
+            "oracle": {"rel_res_true_oracle_operator_max": worst,
+                       "checked_steps": sorted({1, 2, 3, args.c2_steps}),
+                       "first_iterates_rel_l2": first,
+                       "note": "cond ~1e5: a converged x is fixed only to ~cond*tol, so the "
+                               "gate is the oracle-evaluated true residual <= tol"}}
+
+
+def leg_c1(args, torch, inputs, wfa, oracle_mod):
+    """32^3 heat, FP64, 10 steps to 1e-10, against the oracle's 10 steps."""
+    prob = inputs.heat_32()
+    g = wfa.Grid.from_problem(prob, precision=wfa.F64)
+    g.set_option(wfa.OPT_METHOD, METHODS["bicgstab2"])
+    T = g.field(prob.T0)
+    g.timestep(T, 2, tol=1e-10, maxit=1000)
+    T = g.field(prob.T0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = g.timestep(T, 10, tol=1e-10, maxit=1000)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    iters = sum(i.iterations for i in infos)
+    o = oracle_mod.Oracle(prob)
+    To, _ = o.timestep(prob.T0, 10, 1e-10, 1000)
+    return {"workload": "heat_32^3_f64_10steps", "ms_per_step": dt / 10 * 1e3,
+            "us_per_iteration": dt / iters * 1e6, "iterations": iters,
+            "oracle": {"rel_l2_vs_oracle": rel_l2(T.cpu().numpy(), To),
+                       "bound_cond_2tol": 13.6 * 2 * 1e-10}}
+
+
+def leg_c4(args, torch, inputs, wfa, oracle_mod):
+    """384^3 convection-diffusion (u x4), one step to 1e-10: FP32 inside FP64
+    refinement (inner tolerance 1e-3) against plain FP64, both two-reduction
+    BiCGStab with r^ = r0; oracle-evaluated true residuals."""
+    prob = inputs.convdiff_384()
+    o = oracle_mod.Oracle(prob)
+    b = o.rhs(prob.T0)
+    out = {"workload": "mixed_384^3_u4_tol1e-10"}
+    ref = None
+    for name, prec, itol in (("f64", wfa.F64, None), ("f32_ir64", wfa.F32_IR64, 1e-3)):
+        g = wfa.Grid.from_problem(prob, precision=prec)
+        g.set_option(wfa.OPT_METHOD, METHODS["bicgstab2"])
+        if itol is not None:
+            g.set_option(wfa.OPT_IR_INNER_TOL, int(round(itol * 1e12)))
+        T = g.field(prob.T0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = g.timestep(T, 1, tol=1e-10, maxit=100000, check=False)[0]
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        Tn = T.cpu().numpy()
+        rec = {"seconds": dt, "iterations": info.iterations, "refinements": info.refinements,
+               "status": info.status, "rel_res_true": info.rel_res_true,
+               "rel_res_true_oracle_operator": o.true_relres(b, Tn)}
+        if ref is None:
+            ref = Tn
+        else:
+            rec["rel_l2_vs_f64"] = rel_l2(Tn, ref)
+        out[name] = rec
+        del g, T
+    out["speedup_f32_ir64"] = out["f64"]["seconds"] / out["f32_ir64"]["seconds"]
+    return out
+
+
+def leg_cg1(args, torch, prob, wfa):
+    """CG with one reduction (the paper's solver, one pass per iteration) on
+    the headline grid: 500 iterations, HIP-event timed."""
+    g = wfa.Grid.from_problem(prob, precision=wfa.F32)
+    g.set_option(wfa.OPT_METHOD, METHODS["cg1"])
+    g.set_option(wfa.OPT_CHECK_EVERY, HEADLINE_ITERS + 1)
+    T0 = g.field(prob.T0)
+    T = g.field(prob.T0)
+    g.timestep(T, 1, tol=1e-300, maxit=50, check=False)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps, its = 3, 0
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        T.copy_(T0)
+        its += g.timestep(T, 1, tol=1e-300, maxit=HEADLINE_ITERS, check=False)[0].iterations
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    del g
+    return {"workload": "poisson_512x512x1024_f32_500it", "method": "cg1",
+            "value": prob.cells * its / (ms * 1e-3), "ms_per_step": ms / reps,
+            "alg_bytes_per_cell_iter": 10 * 4 + 4}
+
+
+def leg_serve(args, torch, inputs, wfa, oracle_mod):
+    """The 2000-request stream: p50/p99 latency (arrival to completion),
+    throughput, and for a sample of 50 requests the oracle-evaluated true
+    residual and, for those up to 64^3 cells, the distance to the oracle's
+    own solve."""
+    import numpy as np
+    args.requests = getattr(args, "requests", 2000)
+    out = run_serve(args, torch, inputs, wfa, keep_fields=True)
+    fields = out.pop("_fields")
+    reqs = inputs.request_stream(count=args.requests)
+    rng = np.random.default_rng(7)
+    sample = sorted(rng.choice(len(reqs), size=min(50, len(reqs)), replace=False).tolist())
+    worst_res, worst_err, n_err = 0.0, 0.0, 0
+    for q in sample:
+        prob = reqs[q].problem()
+        o = oracle_mod.Oracle(prob)
+        b = o.rhs(prob.T0)
+        x = fields[q].cpu().numpy()
+        worst_res = max(worst_res, o.true_relres(b, x))
+        if prob.cells <= 64 ** 3:
+            xo, _ = o.bicgstab(b, prob.T0, 1e-12, 2000)
+            worst_err = max(worst_err, rel_l2(x, xo))
+            n_err += 1
+    out["oracle"] = {"sampled_requests": len(sample),
+                     "rel_res_true_oracle_operator_max": worst_res,
+                     "rel_l2_vs_oracle_max": worst_err, "compared_requests": n_err,
+                     "note": "tol 1e-10; the heat operators have cond <= ~450, so the bound "
+                             "cond * 2 * tol is <= ~1e-7"}
+    return out
+
+
+def run_headline(args, torch, inputs, wfa):
+    import numpy as np
+    prob = inputs.poisson_large()
+    g = wfa.Grid.from_problem(prob, precision=wfa.F32)
+    g.set_option(wfa.OPT_METHOD, METHODS["bicgstab2"])
+    g.set_option(wfa.OPT_SHADOW, 1)
+    g.set_option(wfa.OPT_CHECK_EVERY, HEADLINE_ITERS + 1)   # one host check per solve
+    T0 = g.field(prob.T0)
+    T = g.field(prob.T0)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        T.copy_(T0)
+        return g.timestep(T, 1, tol=1e-300, maxit=HEADLINE_ITERS, check=False)[0]
+
+    progress("headline inputs resident")
+    for _ in range(args.warmup):
+        step()
+    progress(f"{args.warmup} warm-up steps done")
+    # the timed steps, with HIP events around every launch on the solve
+    # stream (the host never waits on them inside the steps)
+    profile = not args.no_profile
+    g.set_option(wfa.OPT_PROFILE, 1 if profile else 0)
+    for k in range(wfa.K_COUNT):
+        g.kernel_stats(k, reset=True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    infos = []
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        infos.append(step())
+    e1.record(stream)
+    torch.cuda.synchronize()
+    total_ms = e0.elapsed_time(e1)
+    iters = sum(i.iterations for i in infos)
+    value = prob.cells * iters / (total_ms * 1e-3)
+    progress(f"{args.steps} timed steps done: {value:.4g} cell-iters/s")
+    kernels = kernel_table(g, wfa) if profile else {}
+    g.set_option(wfa.OPT_PROFILE, 0)
+    # what the per-launch events cost: two more steps without them
+    plain = None
+    if profile:
+        torch.cuda.synchronize()
+        e0.record(stream)
+        pit = sum(step().iterations for _ in range(2))
+        e1.record(stream)
+        torch.cuda.synchronize()
+        plain = prob.cells * pit / (e0.elapsed_time(e1) * 1e-3)
+    x500 = T.cpu().numpy()
+    roofline = None
+    ceiling = copy_ceiling(torch, wfa)
+    if profile:
+        dom = max(kernels, key=lambda k: kernels[k]["ms_total"])
+        achieved = kernels[dom]["gbps"]
+        best = max(ceiling.values())
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+                    "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                    "traffic": load_traffic(dom, "headline"),
+                    "measured": "HIP events around every launch on the solve stream inside "
+                                "the timed steps",
+                    "copy_ceiling_gbps": ceiling, "frac_of_best_copy": round(achieved / best, 4)}
+    streams = 12                    # two-reduction, hashed shadow: 9 + 3 vector streams
+    alg_cell_iter = streams * 4 + 2 * 4
+    whole = alg_cell_iter * prob.cells * iters / (total_ms * 1e-3) / 1e9
+    # the paper's effective bandwidth (section 3.1.3): A_eff = 2 D_u + D_k
+    # with the updated fields D_u = {x, r, p, v, t} and the read-only ones
+    # D_k = {r^, kappa}: (2 * 5 + 2) * w bytes per cell and iteration
+    a_eff = (2 * 5 + 2) * 4
+    t_eff = a_eff * prob.cells * iters / (total_ms * 1e-3) / 1e9
+    line = {
+        "metric": "BiCGStab cell-iters/s and % HBM roofline on 1 MI355X; p50/p99 solve latency",
+        "value": value,
+        "unit": "cell-iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": total_ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "poisson_512x512x1024_f32_500it", "grid": [512, 512, 1024],
+                   "cells": prob.cells, "precision": "f32",
+                   "iterations_per_step": HEADLINE_ITERS, "method": "bicgstab2",
+                   "shadow": "hashed",
+                   "physics": "pure diffusion, 8-mode smooth kappa in [0.5,2], dt=1, "
+                              "Dirichlet 0, T0~U[0,1)",
+                   "step": "one backward-Euler step restarted from T0: rhs + initial residual "
+                           "+ 500 iterations + FP64 true residual"},
+        "iterations": [i.iterations for i in infos],
+        "value_without_launch_events": plain,
+        "alg_bytes_per_cell_iter": alg_cell_iter,
+        "whole_step_gbps": round(whole, 1),
+        "whole_step_frac": round(whole / HBM_PEAK_GBPS, 4),
+        "t_eff": {"a_eff_bytes_per_cell_iter": a_eff, "gbps": round(t_eff, 1),
+                  "frac": round(t_eff / HBM_PEAK_GBPS, 4)},
+        "roofline": roofline,
+        "kernels": kernels,
+        "kernel_source_hash": kernel_source_hash(),
+    }
+    legs = [] if args.legs == "none" else args.legs.split(",")
+    oracle_mod = None
+    if not args.no_cpu or legs:
+        import oracle as oracle_mod
+    # error against the FP64 oracle: the GPU's 10th iterate against the
+    # oracle's (same method, same x0 and b); the oracle's operator on the
+    # 500-iteration result
+    ora = {"rel_res_true_500": max(i.rel_res_true for i in infos),
+           "rel_res_recursive_500": infos[-1].rel_res_recursive}
+    if not args.no_cpu:
+        T0_32 = T0.cpu().numpy()
+        base, x10o, o, b = oracle_sample(prob, T0_32, 10)
+        progress("oracle sample done")
+        line["cpu_baseline"] = base
+        x10, _ = g.solve(g.field(b), g.field(T0_32), tol=1e-300, maxit=10, method="bicgstab2",
+                         check=False)
+        ora["rel_l2_x10_vs_oracle"] = rel_l2(x10.cpu().numpy(), x10o)
+        ora["rel_res_true_500_oracle_operator"] = o.true_relres(b, x500)
+        ora["note"] = ("FP32 against the FP64 oracle: cond ~1e6 here, so cond * 6e-8 >> 1e-5 and "
+                       "no 1e-5 gate applies (the tests gate the first iterates); the 500-"
+                       "iteration FP32 iterate does not reduce the residual at this condition "
+                       "number, the workload measures bandwidth")
+        del o, b, x10o
+    line["oracle"] = ora
+    del g, T, T0
+    torch.cuda.empty_cache()
+    compare = {}
+    if "cg1" in legs:
+        compare["cg1"] = leg_cg1(args, torch, prob, wfa)
+        progress("leg cg1 done")
+    if "c2" in legs:
+        compare["c2"] = leg_c2(args, torch, inputs, wfa, oracle_mod)
+        progress("leg c2 done")
+    if "c1" in legs:
+        compare["c1"] = leg_c1(args, torch, inputs, wfa, oracle_mod)
+        progress("leg c1 done")
+    if "c4" in legs:
+        compare["c4"] = leg_c4(args, torch, inputs, wfa, oracle_mod)
+        progress("leg c4 done")
+    if "serve" in legs:
+        sv = leg_serve(args, torch, inputs, wfa, oracle_mod)
+        progress("leg serve done")
+        compare["serve"] = sv
+        line["solve_latency_ms"] = {"p50": sv["latency_ms"]["p50"], "p99": sv["latency_ms"]["p99"],
+                                    "source": f"serving stream, {sv['requests']} requests at "
+                                              "200/s, arrival to completion"}
+    line["compare"] = compare
+    return line
+
+
+def run_ceilings(args, torch, inputs, wfa):
+    """HBM bandwidth ceilings: the library's probe kernels (copy, 16 and 32
+    bytes per lane, nontemporal and plain; read only; write only) over 1 and
+    4 GiB with 2048 to 16384 workgroups, and hipMemcpyAsync device to device."""
+    out = {"workload": "hbm_ceilings", "results": []}
+    for gib in (1, 4):
+        nbytes = gib << 30
+        src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        src.fill_(1)
+        dst.fill_(0)
+        for kind, name in enumerate(wfa.PROBE_NAMES):
+            for blocks in (2048, 4096, 8192, 16384):
+                gbps = wfa.bandwidth_probe(kind, src, dst, reps=10, blocks=blocks)
+                out["results"].append({"bytes": nbytes, "kind": name, "blocks": blocks,
+                                       "gbps": round(gbps, 1)})
+        stream = torch.cuda.current_stream()
+        dst.copy_(src)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(10):
+            dst.copy_(src)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        out["results"].append({"bytes": nbytes, "kind": "hipMemcpyAsync_d2d", "blocks": None,
+                               "gbps": round(2.0 * nbytes * 10 / (e0.elapsed_time(e1) * 1e-3)
+                                             / 1e9, 1)})
+        del src, dst
+        torch.cuda.empty_cache()
+    best = {}
+    for r in out["results"]:
+        key = f"{r['kind']}_{r['bytes'] >> 30}GiB"
+        best[key] = max(best.get(key, 0.0), r["gbps"])
+    out["best"] = best
+    return out
+
+
 METHODS = {"bicgstab": 0, "cg": 1, "bicgstab2": 2, "cg1": 3}
 STREAMS = {"bicgstab": 17, "cg": 10, "bicgstab2": 14, "cg1": 10}
 
@@ -662,11 +1143,11 @@ def streams_of(args) -> int:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="convdiff",
-                    choices=["convdiff", "heat32", "poisson_large", "mixed384", "serve", "explicit",
-                             "apply"])
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="headline",
+                    choices=["headline", "convdiff", "heat32", "poisson_large", "mixed384", "serve",
+                             "explicit", "apply", "ceilings"])
     ap.add_argument("--method", default="bicgstab2",
                     choices=["bicgstab", "bicgstab2", "cg", "cg1"],
                     help="cg, cg1 (one reduction per iteration): the symmetric workloads only "
@@ -697,6 +1178,13 @@ def main():
                     help="serve with --serve-method cg1: larger requests keep BiCGStab (0: none)")
     ap.add_argument("--serve-persistent", type=int, default=0, choices=[0, 1],
                     help="serve: 1 = each round is one cooperative launch per precision")
+    ap.add_argument("--legs", default="c2,c1,c4,cg1,serve",
+                    help="headline: comma-separated comparison legs to run (c2 = 256^3 FP64 "
+                         "time integration, c1 = 32^3 heat, c4 = 384^3 refinement vs FP64, cg1 = "
+                         "CG with one reduction on the headline grid, serve = request stream); "
+                         "'none' for the headline alone")
+    ap.add_argument("--c2-steps", type=int, default=50,
+                    help="headline: steps of the 256^3 FP64 time integration leg")
     ap.add_argument("--no-profile", action="store_true",
                     help="time without per-launch events (no roofline)")
     ap.add_argument("--probe-copy", action="store_true",
@@ -736,8 +1224,8 @@ def main():
     torch.cuda.set_device(0)
     if args.probe_copy:
         print(json.dumps({"copy_probe_gbps": wfa.stream_probe(COPY_PROBE_BYTES, 1)}), file=sys.stderr)
-    run = {"convdiff": run_convdiff, "heat32": run_heat32, "poisson_large": run_poisson_large,
-           "apply": run_apply,
+    run = {"headline": run_headline, "convdiff": run_convdiff, "heat32": run_heat32,
+           "poisson_large": run_poisson_large, "apply": run_apply, "ceilings": run_ceilings,
            "mixed384": run_mixed384, "serve": run_serve, "explicit": run_explicit}[args.workload]
     print(json.dumps(run(args, torch, inputs, wfa)))
 

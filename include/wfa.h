@@ -333,9 +333,32 @@ int wfa_tune_load(const char* path);
 int wfa_tune_clear(void);
 
 /* Achievable HBM bandwidth probe: copies `bytes` (multiple of 16) from src
- * to dst `reps` times on `stream` and returns GB/s (read + write bytes). */
+ * to dst `reps` times on `stream` and returns GB/s (read + write bytes).
+ * The same as wfa_bandwidth_probe(WFA_PROBE_COPY, 0, ...). */
 int wfa_stream_probe(const void* src, void* dst, size_t bytes, int reps, double* gbps,
                      void* stream);
+
+/* Bandwidth ceilings of the part, the measured reference for the section
+ * 3.1.3 effective-bandwidth figures: `reps` launches (after one untimed
+ * launch) of one access pattern over `bytes` with `blocks` workgroups of 256
+ * threads (0 = 8192), timed with events on `stream`; *gbps = bytes moved
+ * (read + written) per second / 1e9.  Synchronises `stream`.
+ *   WFA_PROBE_COPY        dst = src, nontemporal loads and stores, 16 B per lane
+ *   WFA_PROBE_COPY_PLAIN  the same with plain loads and stores
+ *   WFA_PROBE_COPY32      nontemporal, 32 contiguous bytes per lane
+ *   WFA_PROBE_READ        reads src only (nontemporal); may write the first
+ *                         4096 bytes of dst
+ *   WFA_PROBE_WRITE       writes dst only (nontemporal); src unused
+ * bytes: a multiple of 16 (32 for COPY32), at least 4096 for READ; src and
+ * dst: device buffers of `bytes` bytes, 16-byte (COPY32: 32-byte) aligned.
+ * Errors: WFA_ERR_INVALID (bad kind, size, alignment or null pointer),
+ * WFA_ERR_HIP. */
+enum {
+  WFA_PROBE_COPY = 0, WFA_PROBE_COPY_PLAIN = 1, WFA_PROBE_COPY32 = 2, WFA_PROBE_READ = 3,
+  WFA_PROBE_WRITE = 4
+};
+int wfa_bandwidth_probe(int kind, int blocks, const void* src, void* dst, size_t bytes, int reps,
+                        double* gbps, void* stream);
 
 /* ---- serving ------------------------------------------------------------------ */
 

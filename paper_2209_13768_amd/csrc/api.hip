@@ -1361,12 +1361,26 @@ extern "C" int wfa_true_residual(wfa_grid* g, const void* b, const void* x, doub
 
 extern "C" int wfa_stream_probe(const void* src, void* dst, size_t bytes, int reps, double* gbps,
                                 void* stream) {
-  if (!src || !dst || !gbps || reps < 1 || bytes < 16 || (bytes % 16) != 0)
-    return set_error(WFA_ERR_INVALID, "bad stream probe arguments");
-  if ((((uintptr_t)src) | ((uintptr_t)dst)) & 15)
-    return set_error(WFA_ERR_INVALID, "probe buffers must be 16-byte aligned");
+  return wfa_bandwidth_probe(WFA_PROBE_COPY, 0, src, dst, bytes, reps, gbps, stream);
+}
+
+extern "C" int wfa_bandwidth_probe(int kind, int blocks, const void* src, void* dst, size_t bytes,
+                                   int reps, double* gbps, void* stream) {
+  if (kind < WFA_PROBE_COPY || kind > WFA_PROBE_WRITE)
+    return set_error(WFA_ERR_INVALID, "unknown probe kind %d", kind);
+  const bool reads = kind != WFA_PROBE_WRITE;
+  const size_t unit = kind == WFA_PROBE_COPY32 ? 32 : 16;
+  if ((reads && !src) || !dst || !gbps || reps < 1 || bytes < unit || (bytes % unit) != 0 ||
+      blocks < 0 || blocks > (1 << 20))
+    return set_error(WFA_ERR_INVALID, "bad bandwidth probe arguments");
+  if (kind == WFA_PROBE_READ && bytes < (size_t)kThreads * 16)
+    return set_error(WFA_ERR_INVALID, "read probe needs at least %d bytes", kThreads * 16);
+  if ((((uintptr_t)src) | ((uintptr_t)dst)) & (unit - 1))
+    return set_error(WFA_ERR_INVALID, "probe buffers must be %zu-byte aligned", unit);
+  // measured: 8192 workgroups the fastest of 2048, 4096 and 8192 for the copy
+  const int nb = blocks ? blocks : 256 * 32;
   hipError_t e = hipSuccess;
-  *gbps = copy_probe(src, dst, bytes, reps, (hipStream_t)stream, &e);
+  *gbps = bandwidth_probe(kind, nb, src, dst, bytes, reps, (hipStream_t)stream, &e);
   if (e != hipSuccess) return set_error(WFA_ERR_HIP, "probe: %s", hipGetErrorString(e));
   return WFA_OK;
 }

@@ -109,7 +109,9 @@ hipError_t launch_persistent_bicgstab(const Launch<T>& L, T* x, T* r, const T* r
                                       T* v0, T* v1, T* t, int iters, int parity,
                                       GridBarrier* bar);
 
-double copy_probe(const void* src, void* dst, size_t bytes, int reps, hipStream_t s,
-                  hipError_t* err);
+// HBM bandwidth probe of one kind (WFA_PROBE_*): GB/s over `reps` launches
+// of `blocks` workgroups.
+double bandwidth_probe(int kind, int blocks, const void* src, void* dst, size_t bytes, int reps,
+                       hipStream_t s, hipError_t* err);
 
 }  // namespace wfa

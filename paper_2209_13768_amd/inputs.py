@@ -20,6 +20,8 @@ from __future__ import annotations
 
 from dataclasses import dataclass, field, replace
 
+import os
+
 import numpy as np
 
 DIRICHLET, ZEROFLUX = 0, 1
@@ -106,12 +108,26 @@ def smooth_kappa(nx: int, ny: int, nz: int, rng: np.random.Generator, modes: int
     z = (np.arange(nz) + 1) * h
     total = float(sum(amps))
     kappa = np.empty((nz, ny, nx), dtype=np.float32)
-    for kz in range(nz):                     # one plane at a time: bounded memory
-        s = np.zeros((ny, nx))
-        for km, am, ph in zip(ks, amps, phis):
-            s += am * np.sin(2 * np.pi * (km[0] * x[None, :] + km[1] * y[:, None]
-                                          + km[2] * z[kz]) + ph)
-        kappa[kz] = np.exp2(s / total).astype(np.float32)
+
+    def planes(k0: int, k1: int) -> None:
+        for kz in range(k0, k1):             # one plane at a time: bounded memory
+            s = np.zeros((ny, nx))
+            for km, am, ph in zip(ks, amps, phis):
+                s += am * np.sin(2 * np.pi * (km[0] * x[None, :] + km[1] * y[:, None]
+                                              + km[2] * z[kz]) + ph)
+            kappa[kz] = np.exp2(s / total).astype(np.float32)
+
+    # planes are independent and each is computed the same way whichever
+    # thread takes it (numpy releases the GIL inside these array operations)
+    workers = max(1, min(16, os.cpu_count() or 1, nz // 8))
+    if workers == 1:
+        planes(0, nz)
+    else:
+        from concurrent.futures import ThreadPoolExecutor
+        cuts = [nz * w // workers for w in range(workers + 1)]
+        with ThreadPoolExecutor(workers) as ex:
+            for f in [ex.submit(planes, cuts[w], cuts[w + 1]) for w in range(workers)]:
+                f.result()
     return kappa
 
 

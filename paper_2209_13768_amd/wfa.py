@@ -28,6 +28,8 @@ K_APPLY, K_INIT, K_PHASE_A, K_PHASE_B, K_PHASE_C, K_RESIDUAL, K_PROMOTE = 0, 1, 
 K_CG_A, K_CG_B, K_PERSISTENT, K_PHASE_AC, K_PHASE_B2, K_EXPLICIT = 7, 8, 9, 10, 11, 12
 K_EXPLICIT_FUSED, K_CG1, K_COUNT = 13, 14, 15
 VEC_R, VEC_RHAT, VEC_T, VEC_P0, VEC_P1, VEC_V0, VEC_V1, VEC_B, VEC_R1 = range(9)
+PROBE_COPY, PROBE_COPY_PLAIN, PROBE_COPY32, PROBE_READ, PROBE_WRITE = range(5)
+PROBE_NAMES = ("copy_nt16", "copy_plain16", "copy_nt32", "read_nt16", "write_nt16")
 KERNEL_NAMES = ("apply", "init", "phase_a", "phase_b", "phase_c", "residual", "promote",
                 "cg_a", "cg_b", "persistent", "phase_ac", "phase_b2", "explicit", "explicit_fused",
                 "cg1")
@@ -39,7 +41,7 @@ EXPORTS = (
     "wfa_workspace_bytes", "wfa_grid_create", "wfa_grid_destroy", "wfa_stencil_apply",
     "wfa_rhs", "wfa_explicit_step", "wfa_bicgstab_solve", "wfa_bicgstab2_solve", "wfa_cg_solve", "wfa_cg1_solve", "wfa_timestep", "wfa_true_residual",
     "wfa_grid_set_option", "wfa_kernel_stats", "wfa_grid_tiling", "wfa_grid_vector",
-    "wfa_stream_probe",
+    "wfa_stream_probe", "wfa_bandwidth_probe",
     "wfa_server_create", "wfa_server_set_option", "wfa_submit", "wfa_poll", "wfa_server_drain",
     "wfa_server_destroy",
     "wfa_last_error", "wfa_version", "wfa_autotune", "wfa_tune_save", "wfa_tune_load",
@@ -129,6 +131,7 @@ def lib() -> ctypes.CDLL:
     L.wfa_grid_tiling.argtypes = [vp] + [ctypes.POINTER(i32)] * 4
     L.wfa_grid_vector.argtypes = [vp, i32, ctypes.POINTER(vp)]
     L.wfa_stream_probe.argtypes = [vp, vp, sz, i32, ctypes.POINTER(dbl), vp]
+    L.wfa_bandwidth_probe.argtypes = [i32, i32, vp, vp, sz, i32, ctypes.POINTER(dbl), vp]
     L.wfa_server_create.argtypes = [vp, sz, i32, vp, ctypes.POINTER(vp)]
     L.wfa_server_set_option.argtypes = [vp, i32, i64]
     L.wfa_submit.argtypes = [vp, i32, i32, i32, ctypes.POINTER(Coeffs), vp, dbl, i32,
@@ -363,6 +366,19 @@ def stream_probe(nbytes: int = 1 << 30, reps: int = 10, stream=None) -> float:
     g = ctypes.c_double()
     _check(lib().wfa_stream_probe(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
                                   nbytes, int(reps), ctypes.byref(g), _stream_ptr(stream)))
+    return g.value
+
+
+def bandwidth_probe(kind: int, src, dst, reps: int = 10, blocks: int = 0, stream=None) -> float:
+    """GB/s of one access pattern (PROBE_*) over the device tensors src and
+    dst (same size in bytes; src unused by PROBE_WRITE)."""
+    nbytes = dst.numel() * dst.element_size()
+    if src.numel() * src.element_size() != nbytes or not (src.is_cuda and dst.is_cuda):
+        raise ValueError("src and dst must be CUDA tensors of the same size in bytes")
+    g = ctypes.c_double()
+    _check(lib().wfa_bandwidth_probe(int(kind), int(blocks), ctypes.c_void_p(src.data_ptr()),
+                                     ctypes.c_void_p(dst.data_ptr()), nbytes, int(reps),
+                                     ctypes.byref(g), _stream_ptr(stream)))
     return g.value
 
 

@@ -69,11 +69,20 @@ def test_counter_means_leave_out_skipped_dispatches(tmp_path):
 
 def test_traffic_figures_gated_by_source_hash(tmp_path, monkeypatch):
     path = tmp_path / "traffic.json"
-    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(path))
-    assert bench.load_traffic("phase_ac") is None          # no file
+    monkeypatch.setitem(bench.TRAFFIC_FILES, "headline", str(path))
+    assert bench.load_traffic("phase_ac", "headline") is None          # no file
     body = {"kernels": {"phase_ac": {"hbm_bytes_per_launch": 123}}}
     path.write_text(json.dumps(dict(body, source_hash="0" * 16)))
-    assert bench.load_traffic("phase_ac") is None          # other sources
+    assert bench.load_traffic("phase_ac", "headline") is None          # other sources
     path.write_text(json.dumps(dict(body, source_hash=bench.kernel_source_hash())))
-    assert bench.load_traffic("phase_ac") == 123
-    assert bench.load_traffic("phase_b2") is None
+    assert bench.load_traffic("phase_ac", "headline") == 123
+    assert bench.load_traffic("phase_b2", "headline") is None
+
+
+def test_gpus_other_than_one_refused():
+    import subprocess
+    import sys
+    res = subprocess.run([sys.executable, bench.__file__, "--gpus", "2"], capture_output=True,
+                         text=True, timeout=120)
+    assert res.returncode == 2
+    assert "one GPU" in res.stdout
