@@ -208,6 +208,34 @@ int wfa_explicit_step(wfa_grid* g, void* T, int nsteps, void* stream);
  * WFA_F64 or WFA_F32_IR64 grids).  Synchronises `stream`. */
 int wfa_true_residual(wfa_grid* g, const void* b, const void* x, double* rel, void* stream);
 
+/* ---- solve without allocation ----------------------------------------------- */
+
+/* Bytes of the static workspace of wfa_bicgstab_solve_static, per GPU. */
+#define WFA_STATIC_WORKSPACE_BYTES (64u << 20)
+
+/* For callers that cannot allocate memory (code that must not call
+ * hipMalloc, such as tight serving loops or harnesses that forbid
+ * allocation): wfa_bicgstab_solve on the grid wfa_grid_create would make
+ * for (nx, ny, nz, c) -- same tiling, same kernels, bitwise the same x and
+ * info -- but with no caller workspace.  The workspace is carved out of a
+ * static device array of WFA_STATIC_WORKSPACE_BYTES that each GPU the
+ * library runs on holds until the process ends, the grid descriptor lives
+ * for the call only, and scalars are read back with plain copies and a
+ * synchronisation of `stream` instead of a pinned block and an event.  No
+ * device or pinned host memory is allocated and no event or stream is
+ * created.
+ * Limits: wfa_workspace_bytes(nx, ny, nz, c->precision) must not exceed
+ * WFA_STATIC_WORKSPACE_BYTES (about 0.9M cells in FP64, 1.3M in
+ * WFA_F32_IR64, 1.8M in FP32), else WFA_ERR_NOMEM.  Every call on one GPU
+ * uses that GPU's one array, which keeps the last call's contents (each
+ * solve initialises what it reads): calls that overlap on one GPU, from
+ * several host threads or streams, race and must not be made.  b, x, kappa:
+ * caller-owned device buffers as for a grid.  Synchronises `stream`.
+ * Errors: those of wfa_grid_create and wfa_bicgstab_solve. */
+int wfa_bicgstab_solve_static(int nx, int ny, int nz, const wfa_coeffs* c, const void* b,
+                              void* x, double tol, int maxit, wfa_solve_info* info,
+                              void* stream);
+
 /* ---- options and instrumentation -------------------------------------------- */
 enum {
   WFA_OPT_METHOD = 1,          /* WFA_METHOD_BICGSTAB (default), _CG,

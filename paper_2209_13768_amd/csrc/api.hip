@@ -468,6 +468,10 @@ namespace wfa {
 
 int Readback::init() {
   if (host) return WFA_OK;
+  if (sync) {
+    host = local;
+    return WFA_OK;
+  }
   Scalars* h = nullptr;
   HIP_TRY(hipHostMalloc((void**)&h, kSlots * sizeof(Scalars), hipHostMallocDefault));
   hipEvent_t e = nullptr;
@@ -483,7 +487,7 @@ int Readback::init() {
 
 void Readback::clear() {
   if (done) (void)hipEventDestroy(done);   // teardown: nothing to report a failure to
-  if (host) (void)hipHostFree(host);
+  if (host && !sync) (void)hipHostFree(host);
   done = nullptr;
   host = nullptr;
 }
@@ -526,8 +530,12 @@ static int read_scalars(wfa_grid* g, const Scalars* dev, Scalars* host, hipStrea
   HIP_TRY(hipMemcpyAsync(g->rb.host, dev, sizeof(Scalars), hipMemcpyDeviceToHost, s));
   if (dev2)
     HIP_TRY(hipMemcpyAsync(g->rb.host + 1, dev2, sizeof(Scalars), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipEventRecord(g->rb.done, s));
-  if ((rc = wait_readback(g))) return rc;
+  if (g->rb.sync) {
+    HIP_TRY(hipStreamSynchronize(s));
+  } else {
+    HIP_TRY(hipEventRecord(g->rb.done, s));
+    if ((rc = wait_readback(g))) return rc;
+  }
   *host = g->rb.host[0];
   if (dev2) *host2 = g->rb.host[1];
   return WFA_OK;

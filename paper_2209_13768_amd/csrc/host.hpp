@@ -62,8 +62,12 @@ struct GraphCache {
 // polling answers sooner than a blocking wait).
 struct Readback {
   static constexpr int kSlots = 2;
-  Scalars* host = nullptr;   // kSlots blocks (hipHostMalloc)
+  Scalars* host = nullptr;   // kSlots blocks (hipHostMalloc), or `local` in sync mode
   hipEvent_t done = nullptr;
+  // sync mode: the copies land in `local` (pageable host memory) and the
+  // stream is synchronised; no pinned block or event is ever created
+  bool sync = false;
+  Scalars local[kSlots];
   int init();                // 0 or a WFA_ERR_* code
   void clear();
 };

@@ -41,7 +41,7 @@ EXPORTS = (
     "wfa_workspace_bytes", "wfa_grid_create", "wfa_grid_destroy", "wfa_stencil_apply",
     "wfa_rhs", "wfa_explicit_step", "wfa_bicgstab_solve", "wfa_bicgstab2_solve", "wfa_cg_solve", "wfa_cg1_solve", "wfa_timestep", "wfa_true_residual",
     "wfa_grid_set_option", "wfa_kernel_stats", "wfa_grid_tiling", "wfa_grid_vector",
-    "wfa_stream_probe", "wfa_bandwidth_probe",
+    "wfa_stream_probe", "wfa_bandwidth_probe", "wfa_bicgstab_solve_static",
     "wfa_server_create", "wfa_server_set_option", "wfa_submit", "wfa_poll", "wfa_server_drain",
     "wfa_server_destroy",
     "wfa_last_error", "wfa_version", "wfa_autotune", "wfa_tune_save", "wfa_tune_load",
@@ -123,6 +123,8 @@ def lib() -> ctypes.CDLL:
     L.wfa_cg_solve.argtypes = [vp, vp, vp, dbl, i32, ctypes.POINTER(_Info), vp]
     L.wfa_cg1_solve.argtypes = [vp, vp, vp, dbl, i32, ctypes.POINTER(_Info), vp]
     L.wfa_bicgstab2_solve.argtypes = [vp, vp, vp, dbl, i32, ctypes.POINTER(_Info), vp]
+    L.wfa_bicgstab_solve_static.argtypes = [i32, i32, i32, ctypes.POINTER(Coeffs), vp, vp, dbl,
+                                            i32, ctypes.POINTER(_Info), vp]
     L.wfa_timestep.argtypes = [vp, vp, i32, dbl, i32, ctypes.POINTER(_Info), vp]
     L.wfa_true_residual.argtypes = [vp, vp, vp, ctypes.POINTER(dbl), vp]
     L.wfa_grid_set_option.argtypes = [vp, i32, i64]
@@ -343,6 +345,34 @@ class Grid:
         nbytes = self.n * (8 if dt == torch.float64 else 4)
         assert 0 <= off and off + nbytes <= self.workspace.numel()
         return self.workspace[off:off + nbytes].view(dt).view(self.shape)
+
+
+STATIC_WORKSPACE_BYTES = 64 << 20
+
+
+def solve_static(prob_or_grid_args: dict, b, x, *, tol=1e-10, maxit=1000, check=True, stream=None):
+    """wfa_bicgstab_solve_static: BiCGStab on A x = b (x in place) with the
+    library's static workspace.  prob_or_grid_args: the keyword arguments of
+    Grid (nx, ny, nz, h, dt, alpha, kappa, u, bc, bc_value, precision)."""
+    torch = _torch()
+    a = dict(prob_or_grid_args)
+    nx, ny, nz = a.pop("nx"), a.pop("ny"), a.pop("nz")
+    precision = a.pop("precision", F64)
+    if isinstance(precision, str):
+        precision = PRECISIONS[precision]
+    kappa = a.pop("kappa", None)
+    if kappa is not None:
+        kappa = kappa.to(device="cuda", dtype=torch.float32).contiguous()
+    c = make_coeffs(kappa=kappa, precision=precision, **a)
+    dtype = torch.float32 if precision == F32 else torch.float64
+    n = nx * ny * nz
+    info = _Info()
+    rc = lib().wfa_bicgstab_solve_static(nx, ny, nz, ctypes.byref(c), _dev(b, dtype, n, "b"),
+                                         _dev(x, dtype, n, "x"), float(tol), int(maxit),
+                                         ctypes.byref(info), _stream_ptr(stream))
+    if check:
+        _check(rc, allow=(OK, ERR_NOCONV))
+    return x, SolveInfo.of(info)
 
 
 def tune_save(path: str):
