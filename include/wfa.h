@@ -341,8 +341,12 @@ int wfa_grid_vector(wfa_grid* g, int which, void** ptr);
  * table under (nx, ny, nz, precision, coefficient mode).  Grids created
  * afterwards with that key start with the recorded tiling, so a grid's
  * tiling -- and with it the order of its reductions -- depends on its key
- * only.  x and b are caller-owned device fields of the grid's vector type
- * (FP64 for WFA_F32_IR64) and are overwritten.  Synchronises `stream`.
+ * only.  Each candidate's cost per iteration is the time of a 2*iters solve
+ * minus that of an iters solve, over the iterations they differ by; a solve
+ * that its numbers stop early (non-finite values or breakdown, as a
+ * diverging FP32 solve may) is timed over the iterations it ran.  x and b
+ * are caller-owned device fields of the grid's vector type (FP64 for
+ * WFA_F32_IR64) and are overwritten.  Synchronises `stream`.
  * The solver options of the grid are left as they were. */
 typedef struct {
   int32_t ry, zc;              /* chosen rows per wave and z planes per workgroup */

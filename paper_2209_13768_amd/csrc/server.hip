@@ -354,7 +354,9 @@ int advance(wfa_server* sv, Request* r) {
     // IR: the outer block holds the FP64 residual of the last refinement;
     // plain precisions: the true residual went to the aux block
     const Scalars& a = g.prec == WFA_F32_IR64 ? hs[0] : hs[2];
-    const double rel = a.bb > 0.0 ? sqrt(a.rr / a.bb) : sqrt(a.rr);
+    // b = 0 under refinement: x = 0 was filled in, the residual is zero
+    const double rel = g.prec == WFA_F32_IR64 && a.status == ST_BZERO ? 0.0
+                       : a.bb > 0.0 ? sqrt(a.rr / a.bb) : sqrt(a.rr);
     int code = r->code;
     if (g.prec == WFA_F32_IR64 && a.status == ST_CONV) code = WFA_OK;
     retire(sv, r, code, rel);
@@ -363,8 +365,18 @@ int advance(wfa_server* sv, Request* r) {
   if (g.prec == WFA_F32_IR64) {
     const Scalars& o = hs[0];
     const Scalars& in = hs[1];
+    if (o.status == ST_BZERO) {
+      // x = 0 solves A x = 0.  The fill runs on the server's stream; the
+      // request retires when the next round's readback, queued behind it,
+      // comes back, so a caller never sees T before the fill has run.
+      launch_fill<double>(g.n, (double*)r->T, 0.0, sv->stream);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return fail(sv, "fill", e);
+      r->code = WFA_OK;
+      r->phase = R_FINAL;
+      return WFA_OK;
+    }
     if (o.status != ST_RUN) {
-      if (o.status == ST_BZERO) launch_fill<double>(g.n, (double*)r->T, 0.0, sv->stream);
       retire(sv, r, code_of(o.status), o.bb > 0.0 ? sqrt(o.rr / o.bb) : 0.0);
       return WFA_OK;
     }

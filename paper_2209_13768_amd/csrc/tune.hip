@@ -103,9 +103,13 @@ struct OptionGuard {
   }
 };
 
-// Seconds of one solve of exactly `iters` iterations from x = 0.
+// Milliseconds of one solve of up to `iters` iterations from x = 0, and the
+// iterations it ran.  The timing needs no particular numerics: a solve that
+// the numbers stop early (non-finite values, or breakdown, e.g. a diverging
+// FP32 solve) is still a timing of the iterations it ran, so every solver
+// outcome is accepted; only HIP and argument errors end the tuning.
 int time_solve(wfa_grid* g, void* x, const void* b, int iters, hipStream_t s, hipEvent_t e0,
-               hipEvent_t e1, double* ms) {
+               hipEvent_t e1, double* ms, int* its) {
   const bool f32 = g->prec == WFA_F32;
   if (f32) hipLaunchKernelGGL(k_zero<float>, dim3(blocks_for(g->n)), dim3(kThreads), 0, s, g->n, (float*)x);
   else hipLaunchKernelGGL(k_zero<double>, dim3(blocks_for(g->n)), dim3(kThreads), 0, s, g->n, (double*)x);
@@ -115,7 +119,9 @@ int time_solve(wfa_grid* g, void* x, const void* b, int iters, hipStream_t s, hi
     return set_error(WFA_ERR_HIP, "autotune: %s", hipGetErrorString(e));
   wfa_solve_info info{};
   const int rc = solve_any(g, b, x, false, 1e-300, iters, &info, s);
-  if (rc != WFA_OK && rc != WFA_ERR_NOCONV) return rc;
+  if (rc != WFA_OK && rc != WFA_ERR_NOCONV && rc != WFA_ERR_NONFINITE && rc != WFA_ERR_BREAKDOWN)
+    return rc;
+  *its = info.iterations;
   if ((e = hipEventRecord(e1, s)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess)
     return set_error(WFA_ERR_HIP, "autotune: %s", hipGetErrorString(e));
   float t = 0.f;
@@ -151,17 +157,25 @@ int autotune_impl(wfa_grid* g, int method, void* x, void* b, int iters, wfa_tune
     if (dup) continue;
     seen.push_back(shape);
     double t1 = 0.0, t2 = 0.0;
-    int rc = time_solve(g, x, b, iters, s, e0, e1, &t1);  // also warms the kernels
-    if (!rc) rc = time_solve(g, x, b, iters, s, e0, e1, &t1);
-    if (!rc) rc = time_solve(g, x, b, 2 * iters, s, e0, e1, &t2);
+    int i1 = 0, i2 = 0;
+    int rc = time_solve(g, x, b, iters, s, e0, e1, &t1, &i1);  // also warms the kernels
+    if (!rc) rc = time_solve(g, x, b, iters, s, e0, e1, &t1, &i1);
+    if (!rc) rc = time_solve(g, x, b, 2 * iters, s, e0, e1, &t2, &i2);
     if (rc) return rc;
-    const double us = (t2 - t1) * 1e3 / iters;
+    // cost per iteration without the set-up passes: the difference of the
+    // two solves over the iterations they differ by; if the numbers stopped
+    // both at the same iteration, the longer solve's mean instead
+    double us;
+    if (i2 > i1) us = (t2 - t1) * 1e3 / (i2 - i1);
+    else if (i2 > 0) us = t2 * 1e3 / i2;
+    else continue;                      // nothing ran (b = 0 or x already converged)
     if (q == 0) default_us = us;
     if (best < 0 || us < best_us) {
       best = (int)q;
       best_us = us;
     }
   }
+  if (best < 0) return set_error(WFA_ERR_INVALID, "autotune: no candidate ran an iteration");
   // record the tile shape itself (the default rule resolved to numbers)
   apply_tiling(g, cands[best].first, cands[best].second);
   const int ry = g->tl.ry, zc = g->tl.geo.zc;

@@ -211,3 +211,38 @@ def test_cg1_requests_served(wfa, oracle_mod):
         n_cg += small
         assert np.array_equal(b, a if small else r0), rq
     assert n_cg == 1
+
+
+@pytest.mark.parametrize("precision", ["f32_ir64", "f64"])
+def test_served_zero_rhs_request(wfa, precision):
+    """b = 0 (Dirichlet faces at 1 and T = -(their boundary terms), so T is
+    not zero): the request ends with x = 0, and by the time poll reports it
+    done the zero field is in T, beside ordinary requests in the same mix."""
+    import torch
+    prec = wfa.PRECISIONS[precision]
+    n = (40, 36, 28)
+    h = inputs.grid_spacing(*n)
+    kw = dict(h=h, dt=1e-3, alpha=1.0, bc_value=(1.0,) * 6)
+    g = wfa.Grid(*n, precision=wfa.F64, **kw)
+    bterm = g.rhs(g.field())                 # boundary terms of T = 0
+    assert bterm.abs().max().item() > 0.0
+    sv = wfa.Server(1 << 30, max_slots=4)
+    others = []
+    for rq in _requests(DIMS[:2]):
+        prob = rq.problem()
+        T = torch.from_numpy(prob.T0).to("cuda", torch.float64)
+        others.append(sv.submit_problem(prob, T, precision=prec, tol=1e-10, maxit=20000))
+    T = (-bterm).contiguous()
+    t = sv.submit(T, precision=prec, tol=1e-10, maxit=20000, **kw)
+    while True:
+        code, info = sv.poll(t)
+        if code != wfa.PENDING:
+            break
+    # read T on torch's stream right after poll: the fill must already be done
+    assert code == wfa.OK, (code, info)
+    assert not bool(T.any().item())
+    assert info.iterations == 0 and info.rel_res_true == 0.0
+    sv.drain()
+    for q in others:
+        assert sv.poll(q)[0] == wfa.OK
+    sv.close()

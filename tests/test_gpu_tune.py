@@ -88,3 +88,21 @@ def test_server_uses_tuned_plane_depth(wfa, tmp_path):
     g0.timestep(T0, 1, tol=1e-10, maxit=20000)
     assert not np.array_equal(T0.cpu().numpy(), T.cpu().numpy())
     wfa.tune_clear()
+
+
+@pytest.mark.parametrize("iters", [20, 150])
+def test_autotune_fp32_convection_diffusion_256(wfa, iters):
+    """The 256^3 convection-diffusion grid in FP32: the timed solves may stop
+    early on their own numbers (a diverging FP32 BiCGStab), which must not
+    end the tuning; every candidate is timed and one is chosen."""
+    prob = inputs.convdiff(n=256)
+    g = wfa.Grid.from_problem(prob, precision=wfa.F32)
+    g.set_option(wfa.OPT_METHOD, wfa.METHOD_BICGSTAB2)
+    g.set_option(wfa.OPT_SHADOW, 1)
+    res = g.autotune("bicgstab2", iters=iters)
+    assert res["ry"] in (1, 2, 4) and 1 <= res["zc"] <= 64
+    assert res["candidates"] >= 20
+    assert 0.0 < res["us_per_iter"] <= res["us_per_iter_default"]
+    # a sane cost: 56 bytes per cell and iteration at no more than 8 TB/s
+    assert res["us_per_iter"] >= 56 * prob.cells / 8e12 * 1e6
+    wfa.tune_clear()
