@@ -97,7 +97,8 @@ def load_traffic(kernel: str, workload: str = "convdiff"):
 
 # rocprofv3 kernel names -> the names bench.py and the library's kernel
 # statistics use
-KERNEL_PATTERNS = (("PhAC<", "phase_ac"), ("PhB2<", "phase_b2"), ("PhA<", "phase_a"),
+KERNEL_PATTERNS = (("PhAC<", "phase_ac"), ("k_phase_act<", "phase_ac"), ("PhB2<", "phase_b2"),
+                   ("PhA<", "phase_a"),
                    ("PhB<", "phase_b"), ("k_phase_c<", "phase_c"), ("PhInit<", "init"),
                    ("PhResid<", "residual"), ("PhCgA<", "cg_a"), ("k_cg_b<", "cg_b"),
                    ("PhCg1<", "cg1"),
@@ -167,6 +168,34 @@ def summarize_counters(fetch_csv: str, write_csv: str, workload: str, commands: 
         json.dump(out, f, indent=1)
         f.write("\n")
     return out
+
+
+def summarize_pmc(csvs: list, title: str, commands: list) -> str:
+    """Markdown table of the mean of every counter per working dispatch, by
+    kernel, from rocprofv3 --pmc counter_collection.csv files (one counter
+    set per file)."""
+    import csv
+    names, per = [], {}
+    for path in csvs:
+        with open(path) as f:
+            for row in csv.DictReader(f):
+                c = row["Counter_Name"]
+                if c not in names:
+                    names.append(c)
+        for c in names:
+            for k, (mean, n) in counter_means(path, c).items():
+                per.setdefault(k, {})[c] = (mean, n)
+    lines = [f"# {title}", "", "Commands (run from the repository root on one MI355X):", "",
+             "```", *commands, "```", "",
+             f"Kernel sources hash (bench.kernel_source_hash): `{kernel_source_hash()}`", "",
+             "Mean per working dispatch (dispatches under a fifth of the kernel's 90th "
+             "percentile, passes skipped after the solve stopped, left out).", "",
+             "| counter | " + " | ".join(sorted(per)) + " |",
+             "|---|" + "---:|" * len(per)]
+    for c in names:
+        row = [f"{per[k][c][0]:.4g}" if c in per[k] else "" for k in sorted(per)]
+        lines.append(f"| {c} | " + " | ".join(row) + " |")
+    return "\n".join(lines) + "\n"
 
 
 def summarize_trace(stats_csv: str, title: str, command: str) -> str:
@@ -946,6 +975,7 @@ def run_headline(args, torch, inputs, wfa):
     g = wfa.Grid.from_problem(prob, precision=wfa.F32)
     g.set_option(wfa.OPT_METHOD, METHODS["bicgstab2"])
     g.set_option(wfa.OPT_SHADOW, 1)
+    g.set_option(wfa.OPT_RECOMPUTE_T, args.recompute_t)
     g.set_option(wfa.OPT_CHECK_EVERY, HEADLINE_ITERS + 1)   # one host check per solve
     T0 = g.field(prob.T0)
     T = g.field(prob.T0)
@@ -1002,7 +1032,9 @@ def run_headline(args, torch, inputs, wfa):
                     "measured": "HIP events around every launch on the solve stream inside "
                                 "the timed steps",
                     "copy_ceiling_gbps": ceiling, "frac_of_best_copy": round(achieved / best, 4)}
-    streams = 12                    # two-reduction, hashed shadow: 9 + 3 vector streams
+    # two-reduction, hashed shadow: 9 + 3 vector streams, or 8 + 2 when pass 1
+    # forms t again instead of pass 2 storing it
+    streams = 10 if args.recompute_t else 12
     alg_cell_iter = streams * 4 + 2 * 4
     whole = alg_cell_iter * prob.cells * iters / (total_ms * 1e-3) / 1e9
     # the paper's effective bandwidth (section 3.1.3): A_eff = 2 D_u + D_k
@@ -1026,7 +1058,7 @@ def run_headline(args, torch, inputs, wfa):
         "config": {"workload": "poisson_512x512x1024_f32_500it", "grid": [512, 512, 1024],
                    "cells": prob.cells, "precision": "f32",
                    "iterations_per_step": HEADLINE_ITERS, "method": "bicgstab2",
-                   "shadow": "hashed",
+                   "shadow": "hashed", "recompute_t": bool(args.recompute_t),
                    "physics": "pure diffusion, 8-mode smooth kappa in [0.5,2], dt=1, "
                               "Dirichlet 0, T0~U[0,1)",
                    "step": "one backward-Euler step restarted from T0: rhs + initial residual "
@@ -1183,6 +1215,9 @@ def main():
                          "time integration, c1 = 32^3 heat, c4 = 384^3 refinement vs FP64, cg1 = "
                          "CG with one reduction on the headline grid, serve = request stream); "
                          "'none' for the headline alone")
+    ap.add_argument("--recompute-t", type=int, default=0, choices=[0, 1],
+                    help="two-reduction BiCGStab: 1 = pass 1 forms t = A s again instead of "
+                         "pass 2 storing it (bitwise the same iterates, two streams fewer)")
     ap.add_argument("--c2-steps", type=int, default=50,
                     help="headline: steps of the 256^3 FP64 time integration leg")
     ap.add_argument("--no-profile", action="store_true",
@@ -1196,11 +1231,19 @@ def main():
                          "file the roofline line reads")
     ap.add_argument("--counter-commands", nargs="*", default=[],
                     help="with --summarize-counters: the commands that made the two files")
+    ap.add_argument("--summarize-pmc", nargs="+", metavar="CSV",
+                    help="no GPU work: print a markdown table of the per-dispatch means of the "
+                         "counters in rocprofv3 --pmc counter_collection.csv files (title and "
+                         "commands from --pmc-title and --counter-commands)")
+    ap.add_argument("--pmc-title", default="rocprofv3 counters")
     ap.add_argument("--summarize-trace", nargs=3, metavar=("STATS_CSV", "TITLE", "COMMAND"),
                     help="no GPU work: print a markdown summary of a rocprofv3 --kernel-trace "
                          "--stats kernel_stats.csv")
     args = ap.parse_args()
 
+    if args.summarize_pmc:
+        print(summarize_pmc(args.summarize_pmc, args.pmc_title, args.counter_commands), end="")
+        return
     if args.summarize_trace:
         print(summarize_trace(*args.summarize_trace), end="")
         return

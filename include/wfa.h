@@ -293,6 +293,13 @@ enum {
                                   then repeated once, stopped at the iteration
                                   of its smallest residual, and that
                                   correction is applied.)                      */,
+  WFA_OPT_RECOMPUTE_T = 15,    /* two-reduction BiCGStab (also the inner solve
+                                  of WFA_F32_IR64): 1 = pass 1 forms t = A s
+                                  again from r and v on a two-cell halo, and
+                                  pass 2 stores no t, two vector streams fewer
+                                  per iteration; the iterates are bitwise
+                                  those of 0, t stored by pass 2 and read by
+                                  pass 1 (default 0)                          */
   WFA_OPT_CG1_MAX_CELLS = 14   /* server only: with WFA_OPT_METHOD =
                                   WFA_METHOD_CG1, symmetric requests of more
                                   cells than this keep BiCGStab; 0 = no limit

@@ -171,6 +171,7 @@ void grid_setup(wfa_grid* g, int nx, int ny, int nz, const wfa_coeffs* c, char* 
   g->graph = 0;
   g->fuse = 0;
   g->shadow = 0;
+  g->recompute_t = 0;
   g->tl = make_tiling(nx, ny, nz, w, 0, 0);
   g->tl32 = make_tiling(nx, ny, nz, 4, 0, 0);
 }
@@ -264,6 +265,10 @@ extern "C" int wfa_grid_set_option(wfa_grid* g, int option, int64_t value) {
     case WFA_OPT_SHADOW:
       if (value != 0 && value != 1) return set_error(WFA_ERR_INVALID, "shadow mode must be 0 or 1");
       g->shadow = (int)value;
+      return WFA_OK;
+    case WFA_OPT_RECOMPUTE_T:
+      if (value != 0 && value != 1) return set_error(WFA_ERR_INVALID, "recompute flag must be 0 or 1");
+      g->recompute_t = (int)value;
       return WFA_OK;
     case WFA_OPT_GRAPH:
       if (value < -1 || value > 1) return set_error(WFA_ERR_INVALID, "graph mode must be -1, 0 or 1");
@@ -389,10 +394,13 @@ static double bytes_per_cell(const wfa_grid* g, int kernel) {
     case WFA_K_CG_A: return 4 * wi + k;
     case WFA_K_CG_B: return 6 * wi;
     case WFA_K_PERSISTENT: return 17 * wi + 2 * k;
-    case WFA_K_PHASE_AC: return (g->shadow ? 9 : 10) * wi + k;
+    // pass 1 reads r, v, t, p, x (+ r^) and writes x, r', p', v'; with
+    // recompute_t it forms t instead of reading it
+    case WFA_K_PHASE_AC: return ((g->shadow ? 9 : 10) - (g->recompute_t ? 1 : 0)) * wi + k;
     case WFA_K_EXPLICIT: return 2 * w + k;
     case WFA_K_EXPLICIT_FUSED: return 2 * w;  // one read, one write per pass
-    case WFA_K_PHASE_B2: return (g->shadow ? 3 : 4) * wi + k;
+    // pass 2 reads r', v' (+ r^) and writes t, unless pass 1 forms t again
+    case WFA_K_PHASE_B2: return ((g->shadow ? 3 : 4) - (g->recompute_t ? 1 : 0)) * wi + k;
     case WFA_K_CG1: return 10 * wi + k;  // r w s p x read; r' w' s' p x written
     default: return 0.0;
   }
@@ -813,6 +821,22 @@ static int iterate_bicgstab2(wfa_grid* g, const Launch<T>& L, T* x, T** r, T* rh
                              bool restartable, ChunkTail* tail, int hint) {
   int par = *par_io;
   int rc = WFA_OK;
+  // With recompute_t pass 1 forms t = A s again and pass 2 stores nothing:
+  // bitwise the same iterates, two vector streams fewer per iteration.
+  const bool recompute = g->recompute_t != 0;
+  auto pass_pair = [&](const Launch<T>& Lp, int pp) {
+    {
+      ProfScope ps(g, WFA_K_PHASE_AC, Lp.stream);
+      if (recompute)
+        launch_phase_act<T>(Lp, r[pp], v[pp], p[pp], rh, x, r[pp ^ 1], p[pp ^ 1], v[pp ^ 1]);
+      else
+        launch_phase_ac<T>(Lp, r[pp], v[pp], t, p[pp], rh, x, r[pp ^ 1], p[pp ^ 1], v[pp ^ 1]);
+    }
+    {
+      ProfScope ps(g, WFA_K_PHASE_B2, Lp.stream);
+      launch_phase_b2<T>(Lp, r[pp ^ 1], v[pp ^ 1], rh, recompute ? nullptr : t);
+    }
+  };
   while (h->status == ST_RUN) {
     if (h->restart) {
       if (!restartable) break;
@@ -830,28 +854,18 @@ static int iterate_bicgstab2(wfa_grid* g, const Launch<T>& L, T* x, T** r, T* rh
     int q = 0;
     if (use_graph(g) && m >= kGraphIters) {
       uint64_t key[GraphCache::kKey];
-      graph_key<T>(key, g, L, 1, par, {x, r[0], r[1], rh, p[0], p[1], v[0], v[1], t});
+      graph_key<T>(key, g, L, recompute ? 4 : 1, par,
+                   {x, r[0], r[1], rh, p[0], p[1], v[0], v[1], t});
       const int p0 = par;
       rc = replay<T>(g, L, key, m / kGraphIters, [&](const Launch<T>& Lc) {
         int pp = p0;
-        for (int k = 0; k < kGraphIters; ++k, pp ^= 1) {
-          launch_phase_ac<T>(Lc, r[pp], v[pp], t, p[pp], rh, x, r[pp ^ 1], p[pp ^ 1], v[pp ^ 1]);
-          launch_phase_b2<T>(Lc, r[pp ^ 1], v[pp ^ 1], rh, t);
-        }
+        for (int k = 0; k < kGraphIters; ++k, pp ^= 1) pass_pair(Lc, pp);
       });
       if (rc) return rc;
       q = m - m % kGraphIters;
     }
     for (; q < m; ++q) {
-      {
-        ProfScope ps(g, WFA_K_PHASE_AC, L.stream);
-        launch_phase_ac<T>(L, r[par], v[par], t, p[par], rh, x, r[par ^ 1], p[par ^ 1],
-                           v[par ^ 1]);
-      }
-      {
-        ProfScope ps(g, WFA_K_PHASE_B2, L.stream);
-        launch_phase_b2<T>(L, r[par ^ 1], v[par ^ 1], rh, t);
-      }
+      pass_pair(L, par);
       par ^= 1;
     }
     if ((rc = check_launch("bicgstab2"))) return rc;

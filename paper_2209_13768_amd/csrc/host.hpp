@@ -104,6 +104,7 @@ struct wfa_grid {
   wfa::Tiling tl32;      // tiling of FP32 inner vectors
   int method, persistent, profile, force_bd, check_every, zchunk, ry, jacobi, graph, fuse;
   int shadow;  // two-reduction BiCGStab: 0 r^ = r0 (stored), 1 index-hashed r^
+  int recompute_t;  // two-reduction BiCGStab: pass 1 forms t = A s again (not stored)
   double ir_inner_tol;
   int force_div;         // n > 0: the next IR solve's first inner solve diverges at n
   int hint_iters;        // iterations of the last converged (inner) solve: first chunk size

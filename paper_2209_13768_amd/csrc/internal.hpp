@@ -68,9 +68,15 @@ void launch_phase_c(const Launch<T>& L, T* x, const T* p, T* r, const T* v, cons
 template <typename T>
 void launch_phase_ac(const Launch<T>& L, const T* r, const T* v, const T* t, const T* p,
                      const T* rh, T* x, T* r_out, T* p_out, T* v_out);
-// pass 2: s = r - alpha v; t = A s; (t,s), (t,t), (rh,s), (rh,t)
+// pass 2: s = r - alpha v; t = A s; (t,s), (t,t), (rh,s), (rh,t); t is
+// stored unless t == nullptr (pass 1 then forms it again: launch_phase_act)
 template <typename T>
 void launch_phase_b2(const Launch<T>& L, const T* r, const T* v, const T* rh, T* t);
+// Pass 1 with t = A s formed again from r and v instead of read (the same
+// stores and sums, bitwise, as launch_phase_ac with the t pass 2 formed)
+template <typename T>
+void launch_phase_act(const Launch<T>& L, const T* r, const T* v, const T* p, const T* rh, T* x,
+                      T* r_out, T* p_out, T* v_out);
 // One iteration of CG with one reduction (Chronopoulos-Gear): the previous
 // update applied on the fly (p, x in place; s' into s_out, r' into r_out),
 // w' = A r' into w_out; (r', r') and (w', r') reduced.  Stage 0 (after

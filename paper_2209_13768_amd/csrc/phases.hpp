@@ -606,7 +606,7 @@ struct PhB2 {
   }
   __device__ void epilogue(size_t i, T s, T Au, T, uint32_t, const ERaw& e, T dg,
                            double (&acc)[NV]) const {
-    st_once(t + i, Au);
+    if (t) st_once(t + i, Au);   // none when pass 1 forms t again
     acc[0] += (double)Au * (double)s;
     acc[1] += (double)Au * (double)Au;
     acc[2] += (double)e.rh * (double)s;
