@@ -239,6 +239,15 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
 }
 
 // ---- reductions ---------------------------------------------------------------
+// One term of a dot product, accumulated in FP64 with a single rounding.  It
+// is an explicit fused multiply-add because, left to the compiler, whether a
+// product and the sum it feeds are fused depends on how the code around them
+// is laid out (both must sit in one basic block), so two builds of the same
+// pass could round a partial sum differently.
+__device__ __forceinline__ void dot_acc(double& a, double x, double y) {
+  a = __builtin_fma(x, y, a);
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);

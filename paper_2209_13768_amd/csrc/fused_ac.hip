@@ -311,8 +311,8 @@ k_phase_act(Geo g, Op<T> op, const float* __restrict__ kappa, ActArgs<T> a, doub
           if (!first) st_once(a.x + idx, next_x(x1[r], p1[r], s1[r], alpha, omega));
           st_once(a.r_out + idx, rn);
           st_once(a.p_out + idx, pn);
-          acc[1] += (double)rh1[r] * (double)rn;
-          acc[2] += (double)rn * (double)rn;
+          dot_acc(acc[1], (double)rh1[r], (double)rn);
+          dot_acc(acc[2], (double)rn, (double)rn);
         }
       }
       P[lo[r]] = pn;
@@ -350,7 +350,7 @@ k_phase_act(Geo g, Op<T> op, const float* __restrict__ kappa, ActArgs<T> a, doub
       T dg;
       const T Av = cell_apply<T, CELL>(op, pp0[r], nb, (T)kk0[r], kn, mo[r] | mz, dg);
       st_once(a.v_out + (size_t)k * plane + poff[r], Av);
-      acc[0] += (double)rh0[r] * (double)Av;
+      dot_acc(acc[0], (double)rh0[r], (double)Av);
     }
   };
 

@@ -218,7 +218,7 @@ k_promote(size_t n, double* __restrict__ x, const float* __restrict__ d, const S
   const double inv = sc->inv_scale;
   const size_t stride = (size_t)gridDim.x * kThreads;
   for (size_t e = (size_t)blockIdx.x * kThreads + threadIdx.x; e < n; e += stride)
-    x[e] += inv * (double)d[e];
+    x[e] = __builtin_fma(inv, (double)d[e], x[e]);   // one rounding, as written
 }
 
 template <typename T>

@@ -336,9 +336,9 @@ struct PhInit {
     T sh = rv;
     if (hashed) sh = hashed_shadow<T>(i);
     else rh[i] = rv;
-    acc[0] += (double)bv * (double)bv;
-    acc[1] += (double)rv * (double)rv;
-    acc[2] += (double)sh * (double)rv;
+    dot_acc(acc[0], (double)bv, (double)bv);
+    dot_acc(acc[1], (double)rv, (double)rv);
+    dot_acc(acc[2], (double)sh, (double)rv);
   }
 };
 
@@ -395,7 +395,7 @@ struct PhA {
   __device__ void epilogue(size_t i, const St& u, T Au, T, uint32_t, const ERaw&, T dg,
                            double (&acc)[NV]) const {
     st_once(v_out + i, Au);
-    acc[0] += (double)u.rh * (double)Au;
+    dot_acc(acc[0], (double)u.rh, (double)Au);
   }
 };
 
@@ -419,8 +419,8 @@ struct PhB {
   __device__ void epilogue(size_t i, T s, T Au, T, uint32_t, const ERaw&, T dg,
                            double (&acc)[NV]) const {
     st_once(t + i, Au);
-    acc[0] += (double)Au * (double)s;
-    acc[1] += (double)Au * (double)Au;
+    dot_acc(acc[0], (double)Au, (double)s);
+    dot_acc(acc[1], (double)Au, (double)Au);
   }
 };
 
@@ -453,7 +453,7 @@ struct PhCgA {
                            double (&acc)[NV]) const {
     d_out[i] = u;
     q[i] = Au;
-    acc[0] += (double)u * (double)Au;
+    dot_acc(acc[0], (double)u, (double)Au);
   }
 };
 
@@ -482,8 +482,8 @@ struct PhResid {
   __device__ void epilogue(size_t i, double, double Au, double, uint32_t, const ERaw& e, double dg,
                            double (&acc)[NV]) const {
     const double rv = e.b - Au;
-    acc[0] += rv * rv;
-    acc[1] += e.b * e.b;
+    dot_acc(acc[0], rv, rv);
+    dot_acc(acc[1], e.b, e.b);
     if (emit) {
       // emit == 2: the inner solve iterates on D^{-1} A, so its right-hand
       // side is D^{-1} r
@@ -492,8 +492,8 @@ struct PhResid {
       float sh = r32v;
       if (hashed) sh = hashed_shadow<float>(i);
       else rh32[i] = r32v;
-      acc[2] += (double)r32v * (double)r32v;
-      acc[3] += (double)sh * (double)r32v;
+      dot_acc(acc[2], (double)r32v, (double)r32v);
+      dot_acc(acc[3], (double)sh, (double)r32v);
     }
   }
 };
@@ -566,8 +566,8 @@ struct PhAC {
     }
     st_once(r_out + i, rn);
     st_once(p_out + i, pn);
-    acc[1] += (double)q.rh * (double)rn;
-    acc[2] += (double)rn * (double)rn;
+    dot_acc(acc[1], (double)q.rh, (double)rn);
+    dot_acc(acc[2], (double)rn, (double)rn);
     return {pn, q.rh};
   }
   __device__ T value_own(const ORaw& q) const {
@@ -577,7 +577,7 @@ struct PhAC {
   __device__ void epilogue(size_t i, const St& u, T Au, T, uint32_t, const ERaw&, T dg,
                            double (&acc)[NV]) const {
     st_once(v_out + i, Au);
-    acc[0] += (double)u.rh * (double)Au;
+    dot_acc(acc[0], (double)u.rh, (double)Au);
   }
 };
 
@@ -607,10 +607,10 @@ struct PhB2 {
   __device__ void epilogue(size_t i, T s, T Au, T, uint32_t, const ERaw& e, T dg,
                            double (&acc)[NV]) const {
     if (t) st_once(t + i, Au);   // none when pass 1 forms t again
-    acc[0] += (double)Au * (double)s;
-    acc[1] += (double)Au * (double)Au;
-    acc[2] += (double)e.rh * (double)s;
-    acc[3] += (double)e.rh * (double)Au;
+    dot_acc(acc[0], (double)Au, (double)s);
+    dot_acc(acc[1], (double)Au, (double)Au);
+    dot_acc(acc[2], (double)e.rh, (double)s);
+    dot_acc(acc[3], (double)e.rh, (double)Au);
   }
 };
 
@@ -681,7 +681,7 @@ struct PhCg1 {
       st_once(x + i, fma_t(alpha, pn, q.x));
     }
     st_once(r_out + i, rn);
-    acc[0] += (double)rn * (double)rn;
+    dot_acc(acc[0], (double)rn, (double)rn);
     return rn;
   }
   __device__ T value_own(const ORaw& q) const { return combine(Raw{q.r, q.w, q.s}); }
@@ -689,7 +689,7 @@ struct PhCg1 {
   __device__ void epilogue(size_t i, T rn, T Au, T, uint32_t, const ERaw&, T dg,
                            double (&acc)[NV]) const {
     st_once(w_out + i, Au);
-    acc[1] += (double)Au * (double)rn;
+    dot_acc(acc[1], (double)Au, (double)rn);
   }
 };
 
@@ -777,8 +777,8 @@ __device__ __forceinline__ void phase_c_elem(T& x, T p, T& r, T v, T t, T rh, T 
   x = next_x(xo, p, s, alpha, omega);
   const T rn = minus_ax(s, omega, t);
   r = rn;
-  acc[0] += (double)rh * (double)rn;
-  acc[1] += (double)rn * (double)rn;
+  dot_acc(acc[0], (double)rh, (double)rn);
+  dot_acc(acc[1], (double)rn, (double)rn);
 }
 
 // 16-byte vector loads when every stream is 16-byte aligned; the scalar
@@ -837,7 +837,7 @@ __device__ __forceinline__ void cg_b_range(size_t n, int blk, int blocks, T* __r
       for (int c = 0; c < N; ++c) {
         xa.v[c] = fma_t(alpha, da.v[c], xa.v[c]);
         ra.v[c] = minus_ax(ra.v[c], alpha, qa.v[c]);
-        acc[0] += (double)ra.v[c] * (double)ra.v[c];
+        dot_acc(acc[0], (double)ra.v[c], (double)ra.v[c]);
       }
       xv[e] = xa;
       rv[e] = ra;
@@ -848,7 +848,7 @@ __device__ __forceinline__ void cg_b_range(size_t n, int blk, int blocks, T* __r
     x[e] = fma_t(alpha, d[e], x[e]);
     const T rn = minus_ax(r[e], alpha, q[e]);
     r[e] = rn;
-    acc[0] += (double)rn * (double)rn;
+    dot_acc(acc[0], (double)rn, (double)rn);
   }
 }
 
