@@ -208,11 +208,13 @@ def summarize_trace(stats_csv: str, title: str, command: str) -> str:
     import re
     trace_csv = stats_csv.replace("kernel_stats", "kernel_trace")
     durs = {}
+    spans = []
     if trace_csv != stats_csv and os.path.exists(trace_csv):
         with open(trace_csv) as f:
             for r in csv.DictReader(f):
-                durs.setdefault(r["Kernel_Name"], []).append(
-                    (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+                t0, t1 = int(r["Start_Timestamp"]), int(r["End_Timestamp"])
+                durs.setdefault(r["Kernel_Name"], []).append((t1 - t0) / 1e3)
+                spans.append((t0, t1))
     head = "| kernel | calls | total (us) | average (us) | % |"
     rule = "|---|---:|---:|---:|---:|"
     if durs:
@@ -241,7 +243,32 @@ def summarize_trace(stats_csv: str, title: str, command: str) -> str:
                 else:
                     row += " | |"
             lines.append(row)
+    if spans:
+        busy, gaps = gpu_busy(spans)
+        lines += ["", f"GPU busy {100 * busy:.1f}% of the span from the first kernel to the last "
+                      f"(union of kernel intervals); median gap between kernels "
+                      f"{gaps['median_us']:.1f} us; {gaps['over_20us']} gaps over 20 us, "
+                      f"{gaps['over_20us_total_ms']:.1f} ms in all."]
     return "\n".join(lines) + "\n"
+
+
+def gpu_busy(spans):
+    """Fraction of [first start, last end] covered by the union of the
+    (start, end) kernel intervals (ns), and the gaps between them."""
+    spans = sorted(spans)
+    merged = []
+    for a, b in spans:
+        if merged and a <= merged[-1][1]:
+            merged[-1][1] = max(merged[-1][1], b)
+        else:
+            merged.append([a, b])
+    total = merged[-1][1] - merged[0][0]
+    covered = sum(b - a for a, b in merged)
+    gaps = [(merged[q + 1][0] - merged[q][1]) / 1e3 for q in range(len(merged) - 1)]
+    big = [g for g in gaps if g > 20.0]
+    return covered / total if total > 0 else 1.0, {
+        "median_us": sorted(gaps)[len(gaps) // 2] if gaps else 0.0,
+        "over_20us": len(big), "over_20us_total_ms": sum(big) / 1e3}
 
 
 def cpu_baseline(prob, iters: int):

@@ -3,7 +3,9 @@
 //
 // A host worker thread owns the GPU side.  Each round it
 //   1. admits queued requests in arrival order while a slot is free and the
-//      arena can hold the request's Krylov workspace;
+//      arena can hold the request's Krylov workspace (a request first in
+//      line that does not fit lets later ones that fit go ahead, a bounded
+//      number of times);
 //   2. starts new requests (right-hand side + first residual) and refines
 //      requests whose inner solve ended (FP64 update + FP64 residual);
 //   3. launches `chunk` batched BiCGStab iterations over every resident
@@ -98,6 +100,7 @@ struct Request {
   wfa_grid g{};
   int total_it = 0, refinements = 0, restarts = 0;
   int inner_cap = 0;  // > 0: repeating a diverged inner solve up to its best iterate
+  int passed_over = 0;  // later requests admitted while this one, first in line, did not fit
   int par = 0;        // buffer parity of the next iteration (0 after every (re)start)
   int cg1 = 0;        // 1: iterates with CG with one reduction (symmetric request)
   double scale = 1.0;
@@ -489,6 +492,38 @@ int build_tables(wfa_server* sv, int* n32, int* tiles32, int* pw32, int* n64, in
   return WFA_OK;
 }
 
+// Admission in arrival order while a slot and arena space are free.  A
+// request first in line that does not fit lets later requests that fit go
+// ahead, at most kMaxPassOver of them; then admission waits for it, so no
+// request waits for ever behind smaller ones.
+constexpr int kMaxPassOver = 16;
+constexpr int kAdmitScan = 64;   // queued requests looked at per round
+
+void admit(wfa_server* sv, std::vector<Request*>* admitted) {
+  Request* blocked = nullptr;  // the earliest request that did not fit
+  int scanned = 0;
+  for (auto it = sv->queue.begin(); it != sv->queue.end() && scanned < kAdmitScan; ++scanned) {
+    Request* r = *it;
+    if (blocked && blocked->passed_over >= kMaxPassOver) return;
+    int slot = -1;
+    for (int s = 0; s < sv->max_slots; ++s)
+      if (!sv->slots[s]) { slot = s; break; }
+    if (slot < 0) return;
+    size_t off = 0;
+    if (!sv->heap.alloc(r->bytes, &off)) {
+      if (!blocked) blocked = r;
+      ++it;
+      continue;
+    }
+    if (blocked) ++blocked->passed_over;
+    it = sv->queue.erase(it);
+    r->slot = slot;
+    r->off = off;
+    sv->slots[slot] = r;
+    admitted->push_back(r);
+  }
+}
+
 void worker_main(wfa_server* sv) {
   std::vector<Request*> admitted;
   while (true) {
@@ -498,20 +533,7 @@ void worker_main(wfa_server* sv) {
       std::unique_lock<std::mutex> lk(sv->mu);
       chunk = sv->chunk;
       persist = sv->persistent;
-      // admission in arrival order: slot + arena space
-      while (!sv->queue.empty()) {
-        Request* r = sv->queue.front();
-        int slot = -1;
-        for (int s = 0; s < sv->max_slots; ++s)
-          if (!sv->slots[s]) { slot = s; break; }
-        size_t off = 0;
-        if (slot < 0 || !sv->heap.alloc(r->bytes, &off)) break;
-        sv->queue.pop_front();
-        r->slot = slot;
-        r->off = off;
-        sv->slots[slot] = r;
-        admitted.push_back(r);
-      }
+      admit(sv, &admitted);
       bool any = false;
       for (auto* r : sv->slots) any = any || r != nullptr;
       if (!any && admitted.empty()) {

@@ -91,6 +91,26 @@ def test_small_budget_admits_one_at_a_time(wfa):
         assert np.array_equal(a, b)
 
 
+def test_small_requests_pass_a_head_that_does_not_fit(wfa):
+    """A request first in line that does not fit the arena lets later ones
+    that fit go ahead (a bounded number of them): with room for one large
+    workspace and a few small ones, the small requests queued behind a
+    second large one are admitted beside the first and finish before the
+    second large one, which cannot start until the first retires.  Every
+    result is bitwise the one the request gets alone."""
+    big, small = (96, 96, 64), (32, 32, 32)
+    dims = [big, big, small, small, small]
+    reqs = _requests(dims)
+    nb = wfa.workspace_bytes(*big, wfa.F32_IR64)
+    ns = wfa.workspace_bytes(*small, wfa.F32_IR64)
+    budget = nb + 3 * ns + (4 << 20)   # slot tables + one large + three small
+    got, infos = _serve(wfa, reqs, budget, slots=8)
+    assert max(i.seconds for i in infos[2:]) < infos[1].seconds
+    for rq, g in zip(reqs, got):
+        alone, _ = _serve(wfa, [rq], 1 << 30, slots=1)
+        assert np.array_equal(alone[0], g), rq
+
+
 def test_reject_request_larger_than_arena(wfa):
     import torch
     sv = wfa.Server(8 << 20, max_slots=2)
