@@ -110,6 +110,7 @@ static Op<T> make_op(const wfa_coeffs& c) {
     op.out[f] = (T)fmax(F, 0.0);
     op.bval[f] = (T)c.bc_value[f];
     if (c.bc[f] == WFA_BC_DIRICHLET) op.dir |= 1u << f;
+    if (op.in[f] != T(0) || op.out[f] != T(0)) op.conv = 1;
   }
   return op;
 }

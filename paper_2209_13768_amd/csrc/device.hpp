@@ -78,7 +78,15 @@ struct Op {
   T bval[6];       // Dirichlet ghost values
   uint32_t dir;    // bit f set: face f is Dirichlet
   uint32_t jac;    // 1: the Krylov operator is D^{-1} A (left Jacobi scaling)
+  uint32_t conv;   // 1: some face has a convective term (in[f] or out[f] != 0)
 };
+
+// The operator has neither convection nor Jacobi scaling, so cell_apply's
+// diffusion-only form gives its values bit for bit.
+template <typename T>
+__host__ __device__ inline bool diffusion_only(const Op<T>& op) {
+  return op.conv == 0 && op.jac == 0;
+}
 
 // Reciprocal of a positive normal number: the hardware estimate (relative
 // error 2^-24.4 at most, measured over sums of two FP32 diffusivities) refined
@@ -111,7 +119,12 @@ __device__ __forceinline__ float fma_t(float a, float b, float c) { return __bui
 // plane's z+ face: the same two diffusivities, and the products of two FP32
 // values are exact, so the value is the one this call would form); the z+
 // face's on exit.
-template <typename T, bool CELL>
+// GEN = false is the diffusion-only form, for an operator with no
+// convective term and no Jacobi scaling (diffusion_only(op)): with
+// in[f] = out[f] = 0 each fma(cD, kf, 0) is the product cD kf rounded once,
+// so dropping the zero terms (and the scaling select) leaves every value
+// bit for bit as GEN = true forms it, for fewer vector instructions.
+template <typename T, bool CELL, bool GEN = true>
 __device__ __forceinline__ T cell_apply(const Op<T>& op, T c, const T nb[6], T kP,
                                         const T kN[6], uint32_t inside, T& dg, T& kz,
                                         bool carry) {
@@ -125,28 +138,36 @@ __device__ __forceinline__ T cell_apply(const Op<T>& op, T c, const T nb[6], T k
         const T kf = (f == 4 && carry) ? kz
                                        : T(2) * kP * kN[f] * pos_rcp(kP + kN[f]);  // harmonic mean
         if (f == 5) kz = kf;
-        d_out = fma_t(op.cD, kf, op.out[f]);
-        d_in = fma_t(op.cD, kf, op.in[f]);
-      } else {
+        if (GEN) {
+          d_out = fma_t(op.cD, kf, op.out[f]);
+          d_in = fma_t(op.cD, kf, op.in[f]);
+        } else {
+          d_out = d_in = op.cD * kf;
+        }
+      } else if (GEN) {
         d_out = op.cD + op.out[f];
         d_in = op.cD + op.in[f];
+      } else {
+        d_out = d_in = op.cD;
       }
       diag += d_out;
       acc = fma_t(d_in, nb[f], acc);
     } else if (op.dir & (1u << f)) {
-      diag += CELL ? fma_t(op.cD, kP, op.out[f]) : op.cD + op.out[f];
+      if (GEN) diag += CELL ? fma_t(op.cD, kP, op.out[f]) : op.cD + op.out[f];
+      else diag += CELL ? op.cD * kP : op.cD;
     }
   }
   dg = diag;
   const T y = fma_t(diag, c, -acc);
+  if (!GEN) return y;
   return op.jac ? y * pos_rcp(diag) : y;
 }
 
-template <typename T, bool CELL>
+template <typename T, bool CELL, bool GEN = true>
 __device__ __forceinline__ T cell_apply(const Op<T>& op, T c, const T nb[6], T kP,
                                         const T kN[6], uint32_t inside, T& dg) {
   T kz = T(0);
-  return cell_apply<T, CELL>(op, c, nb, kP, kN, inside, dg, kz, false);
+  return cell_apply<T, CELL, GEN>(op, c, nb, kP, kN, inside, dg, kz, false);
 }
 
 // Dirichlet contribution of cell P to the right-hand side.
@@ -435,7 +456,7 @@ struct carry_z<Ph, std::void_t<decltype(Ph::kCarryZ)>> {
   static constexpr bool value = Ph::kCarryZ;
 };
 
-template <typename T, bool CELL, int RY, class Ph>
+template <typename T, bool CELL, int RY, class Ph, bool GEN = true>
 __device__ __forceinline__ void march_tile(const Geo& g, const Op<T>& op,
                                            const float* __restrict__ kappa, int tile,
                                            Ph& ph, double (&acc)[Ph::NV], T* su,
@@ -632,9 +653,10 @@ __device__ __forceinline__ void march_tile(const Geo& g, const Op<T>& op,
         T dg;
         T Au;
         if constexpr (CZ)
-          Au = cell_apply<T, CELL>(op, Ph::val(uc[r]), nb, (T)kcv[r], kn6, ins, dg, kz[r], carry);
+          Au = cell_apply<T, CELL, GEN>(op, Ph::val(uc[r]), nb, (T)kcv[r], kn6, ins, dg, kz[r],
+                                        carry);
         else
-          Au = cell_apply<T, CELL>(op, Ph::val(uc[r]), nb, (T)kcv[r], kn6, ins, dg);
+          Au = cell_apply<T, CELL, GEN>(op, Ph::val(uc[r]), nb, (T)kcv[r], kn6, ins, dg);
         ph.epilogue((size_t)k * plane + poff[r], uc[r], Au, (T)kcv[r], ins, ec[r], dg, acc);
       }
     }

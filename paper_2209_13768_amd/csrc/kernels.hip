@@ -28,7 +28,7 @@ namespace wfa {
 // ============================================================================
 // generic stencil-pass kernel
 // ============================================================================
-template <typename T, bool CELL, int RY, class Ph, class Fin>
+template <typename T, bool CELL, int RY, class Ph, class Fin, bool GEN = true>
 __global__ void __launch_bounds__(kThreads)
 k_march(Geo g, Op<T> op, const float* __restrict__ kappa, Ph ph, double* partials,
         Scalars* sc, Fin fin, const Scalars* gate, int gated, int publish) {
@@ -48,17 +48,35 @@ k_march(Geo g, Op<T> op, const float* __restrict__ kappa, Ph ph, double* partial
 #pragma unroll
   for (int q = 0; q < Ph::NV; ++q) acc[q] = 0.0;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  march_tile<T, CELL, RY>(g, op, kappa, tile, ph, acc, su, sk);
+  march_tile<T, CELL, RY, Ph, GEN>(g, op, kappa, tile, ph, acc, su, sk);
   if (publish) publish_and_finalize<Ph::NV>(acc, tile, g.ntiles, partials, sc, red, fin);
 }
 
-template <typename T, class Ph, class Fin>
+// DIFF: the phase also has a diffusion-only build, launched when the
+// operator has no convective term and no Jacobi scaling (the same values
+// with fewer vector instructions; only the two-reduction BiCGStab's passes
+// carry it, to keep the number of kernels down).
+template <typename T, class Ph, class Fin, bool DIFF = false>
 void dispatch_march(const Launch<T>& L, const Ph& ph, const Fin& fin, bool gated, bool publish,
                     const Scalars* after = nullptr) {
   const Geo g = L.tl.geo;
   dim3 grid(g.ntiles), block(kThreads);
   const int G = after ? 2 : gated ? 1 : 0, P = publish ? 1 : 0;
   const Scalars* gate = after ? after : L.sc;
+#define WFA_MARCH_G(CELLV, RYV, GENV)                                                          \
+  hipLaunchKernelGGL((k_march<T, CELLV, RYV, Ph, Fin, GENV>), grid, block, 0, L.stream, g,     \
+                     L.op, L.kappa, ph, L.partials, L.sc, fin, gate, G, P)
+  if constexpr (DIFF) {
+    if (L.cell && diffusion_only(L.op)) {
+      switch (L.tl.ry) {
+        case 1: WFA_MARCH_G(true, 1, false); break;
+        case 4: WFA_MARCH_G(true, 4, false); break;
+        default: WFA_MARCH_G(true, 2, false); break;
+      }
+      return;
+    }
+  }
+#undef WFA_MARCH_G
 #define WFA_MARCH(CELLV, RYV)                                                              \
   hipLaunchKernelGGL((k_march<T, CELLV, RYV, Ph, Fin>), grid, block, 0, L.stream, g, L.op, \
                      L.kappa, ph, L.partials, L.sc, fin, gate, G, P)
@@ -141,7 +159,7 @@ void launch_phase_ac(const Launch<T>& L, const T* r, const T* v, const T* t, con
   ph.hashed = L.shadow;
   ph.r = r; ph.v = v; ph.t = t; ph.p = p; ph.rh = rh; ph.x = x;
   ph.r_out = r_out; ph.p_out = p_out; ph.v_out = v_out;
-  dispatch_march(L, ph, FinAC{L.sc}, true, true);
+  dispatch_march<T, PhAC<T>, FinAC, true>(L, ph, FinAC{L.sc}, true, true);
 }
 
 template <typename T>
@@ -149,7 +167,7 @@ void launch_phase_b2(const Launch<T>& L, const T* r, const T* v, const T* rh, T*
   PhB2<T> ph{};
   ph.hashed = L.shadow;
   ph.r = r; ph.v = v; ph.rh = rh; ph.t = t;
-  dispatch_march(L, ph, FinB2{L.sc}, true, true);
+  dispatch_march<T, PhB2<T>, FinB2, true>(L, ph, FinB2{L.sc}, true, true);
 }
 
 template <typename T>
