@@ -81,11 +81,17 @@ struct Op {
   uint32_t conv;   // 1: some face has a convective term (in[f] or out[f] != 0)
 };
 
-// The operator has neither convection nor Jacobi scaling, so cell_apply's
-// diffusion-only form gives its values bit for bit.
+// Builds of the cell operator (cell_apply's FORM): the general one, and two
+// that leave out terms an operator does not have -- the Jacobi scaling
+// select, and also the convective terms -- for fewer vector instructions.
+// Each gives the general build's values bit for bit on the operators it is
+// chosen for (op_form).
+enum OpForm : int { kFormDiffusion = 0, kFormConvection = 1, kFormGeneral = 2 };
+
 template <typename T>
-__host__ __device__ inline bool diffusion_only(const Op<T>& op) {
-  return op.conv == 0 && op.jac == 0;
+__host__ __device__ inline int op_form(const Op<T>& op) {
+  if (op.jac) return kFormGeneral;
+  return op.conv ? kFormConvection : kFormDiffusion;
 }
 
 // Reciprocal of a positive normal number: the hardware estimate (relative
@@ -119,12 +125,12 @@ __device__ __forceinline__ float fma_t(float a, float b, float c) { return __bui
 // plane's z+ face: the same two diffusivities, and the products of two FP32
 // values are exact, so the value is the one this call would form); the z+
 // face's on exit.
-// GEN = false is the diffusion-only form, for an operator with no
-// convective term and no Jacobi scaling (diffusion_only(op)): with
-// in[f] = out[f] = 0 each fma(cD, kf, 0) is the product cD kf rounded once,
-// so dropping the zero terms (and the scaling select) leaves every value
-// bit for bit as GEN = true forms it, for fewer vector instructions.
-template <typename T, bool CELL, bool GEN = true>
+// FORM = kFormConvection leaves out the Jacobi scaling select, for an
+// operator without scaling; kFormDiffusion also the convective terms, for
+// an operator without them (op_form(op) picks): with in[f] = out[f] = 0
+// each fma(cD, kf, 0) is the product cD kf rounded once, so every value is
+// bit for bit the general build's.
+template <typename T, bool CELL, int FORM = kFormGeneral>
 __device__ __forceinline__ T cell_apply(const Op<T>& op, T c, const T nb[6], T kP,
                                         const T kN[6], uint32_t inside, T& dg, T& kz,
                                         bool carry) {
@@ -133,18 +139,19 @@ __device__ __forceinline__ T cell_apply(const Op<T>& op, T c, const T nb[6], T k
 #pragma unroll
   for (int f = 0; f < 6; ++f) {
     if (inside & (1u << f)) {
+      constexpr bool CONV = FORM != kFormDiffusion;
       T d_out, d_in;  // D + max(F,0), D + max(-F,0)
       if (CELL) {
         const T kf = (f == 4 && carry) ? kz
                                        : T(2) * kP * kN[f] * pos_rcp(kP + kN[f]);  // harmonic mean
         if (f == 5) kz = kf;
-        if (GEN) {
+        if (CONV) {
           d_out = fma_t(op.cD, kf, op.out[f]);
           d_in = fma_t(op.cD, kf, op.in[f]);
         } else {
           d_out = d_in = op.cD * kf;
         }
-      } else if (GEN) {
+      } else if (CONV) {
         d_out = op.cD + op.out[f];
         d_in = op.cD + op.in[f];
       } else {
@@ -153,21 +160,21 @@ __device__ __forceinline__ T cell_apply(const Op<T>& op, T c, const T nb[6], T k
       diag += d_out;
       acc = fma_t(d_in, nb[f], acc);
     } else if (op.dir & (1u << f)) {
-      if (GEN) diag += CELL ? fma_t(op.cD, kP, op.out[f]) : op.cD + op.out[f];
+      if (FORM != kFormDiffusion) diag += CELL ? fma_t(op.cD, kP, op.out[f]) : op.cD + op.out[f];
       else diag += CELL ? op.cD * kP : op.cD;
     }
   }
   dg = diag;
   const T y = fma_t(diag, c, -acc);
-  if (!GEN) return y;
+  if (FORM != kFormGeneral) return y;
   return op.jac ? y * pos_rcp(diag) : y;
 }
 
-template <typename T, bool CELL, bool GEN = true>
+template <typename T, bool CELL, int FORM = kFormGeneral>
 __device__ __forceinline__ T cell_apply(const Op<T>& op, T c, const T nb[6], T kP,
                                         const T kN[6], uint32_t inside, T& dg) {
   T kz = T(0);
-  return cell_apply<T, CELL, GEN>(op, c, nb, kP, kN, inside, dg, kz, false);
+  return cell_apply<T, CELL, FORM>(op, c, nb, kP, kN, inside, dg, kz, false);
 }
 
 // Dirichlet contribution of cell P to the right-hand side.
@@ -456,7 +463,7 @@ struct carry_z<Ph, std::void_t<decltype(Ph::kCarryZ)>> {
   static constexpr bool value = Ph::kCarryZ;
 };
 
-template <typename T, bool CELL, int RY, class Ph, bool GEN = true>
+template <typename T, bool CELL, int RY, class Ph, int FORM = kFormGeneral>
 __device__ __forceinline__ void march_tile(const Geo& g, const Op<T>& op,
                                            const float* __restrict__ kappa, int tile,
                                            Ph& ph, double (&acc)[Ph::NV], T* su,
@@ -653,10 +660,10 @@ __device__ __forceinline__ void march_tile(const Geo& g, const Op<T>& op,
         T dg;
         T Au;
         if constexpr (CZ)
-          Au = cell_apply<T, CELL, GEN>(op, Ph::val(uc[r]), nb, (T)kcv[r], kn6, ins, dg, kz[r],
-                                        carry);
+          Au = cell_apply<T, CELL, FORM>(op, Ph::val(uc[r]), nb, (T)kcv[r], kn6, ins, dg, kz[r],
+                                         carry);
         else
-          Au = cell_apply<T, CELL, GEN>(op, Ph::val(uc[r]), nb, (T)kcv[r], kn6, ins, dg);
+          Au = cell_apply<T, CELL, FORM>(op, Ph::val(uc[r]), nb, (T)kcv[r], kn6, ins, dg);
         ph.epilogue((size_t)k * plane + poff[r], uc[r], Au, (T)kcv[r], ins, ec[r], dg, acc);
       }
     }

@@ -28,7 +28,7 @@ namespace wfa {
 // ============================================================================
 // generic stencil-pass kernel
 // ============================================================================
-template <typename T, bool CELL, int RY, class Ph, class Fin, bool GEN = true>
+template <typename T, bool CELL, int RY, class Ph, class Fin, int FORM = kFormGeneral>
 __global__ void __launch_bounds__(kThreads)
 k_march(Geo g, Op<T> op, const float* __restrict__ kappa, Ph ph, double* partials,
         Scalars* sc, Fin fin, const Scalars* gate, int gated, int publish) {
@@ -48,35 +48,43 @@ k_march(Geo g, Op<T> op, const float* __restrict__ kappa, Ph ph, double* partial
 #pragma unroll
   for (int q = 0; q < Ph::NV; ++q) acc[q] = 0.0;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  march_tile<T, CELL, RY, Ph, GEN>(g, op, kappa, tile, ph, acc, su, sk);
+  march_tile<T, CELL, RY, Ph, FORM>(g, op, kappa, tile, ph, acc, su, sk);
   if (publish) publish_and_finalize<Ph::NV>(acc, tile, g.ntiles, partials, sc, red, fin);
 }
 
-// DIFF: the phase also has a diffusion-only build, launched when the
-// operator has no convective term and no Jacobi scaling (the same values
-// with fewer vector instructions; only the two-reduction BiCGStab's passes
-// carry it, to keep the number of kernels down).
-template <typename T, class Ph, class Fin, bool DIFF = false>
+// FORMS: the phase also has the builds of the cell operator without the
+// Jacobi scaling select and without the convective terms, launched for an
+// operator that has neither (op_form): the same values with fewer vector
+// instructions.  Only the two-reduction BiCGStab's passes on a per-cell
+// diffusivity carry them, to keep the number of kernels down.
+template <typename T, class Ph, class Fin, bool FORMS = false>
 void dispatch_march(const Launch<T>& L, const Ph& ph, const Fin& fin, bool gated, bool publish,
                     const Scalars* after = nullptr) {
   const Geo g = L.tl.geo;
   dim3 grid(g.ntiles), block(kThreads);
   const int G = after ? 2 : gated ? 1 : 0, P = publish ? 1 : 0;
   const Scalars* gate = after ? after : L.sc;
-#define WFA_MARCH_G(CELLV, RYV, GENV)                                                          \
-  hipLaunchKernelGGL((k_march<T, CELLV, RYV, Ph, Fin, GENV>), grid, block, 0, L.stream, g,     \
+#define WFA_MARCH_F(RYV, FORMV)                                                               \
+  hipLaunchKernelGGL((k_march<T, true, RYV, Ph, Fin, FORMV>), grid, block, 0, L.stream, g,     \
                      L.op, L.kappa, ph, L.partials, L.sc, fin, gate, G, P)
-  if constexpr (DIFF) {
-    if (L.cell && diffusion_only(L.op)) {
-      switch (L.tl.ry) {
-        case 1: WFA_MARCH_G(true, 1, false); break;
-        case 4: WFA_MARCH_G(true, 4, false); break;
-        default: WFA_MARCH_G(true, 2, false); break;
-      }
+#define WFA_MARCH_FORM(FORMV)                      \
+  switch (L.tl.ry) {                               \
+    case 1: WFA_MARCH_F(1, FORMV); break;          \
+    case 4: WFA_MARCH_F(4, FORMV); break;          \
+    default: WFA_MARCH_F(2, FORMV); break;         \
+  }
+  if constexpr (FORMS) {
+    if (L.cell && op_form(L.op) == kFormDiffusion) {
+      WFA_MARCH_FORM(kFormDiffusion);
+      return;
+    }
+    if (L.cell && op_form(L.op) == kFormConvection) {
+      WFA_MARCH_FORM(kFormConvection);
       return;
     }
   }
-#undef WFA_MARCH_G
+#undef WFA_MARCH_FORM
+#undef WFA_MARCH_F
 #define WFA_MARCH(CELLV, RYV)                                                              \
   hipLaunchKernelGGL((k_march<T, CELLV, RYV, Ph, Fin>), grid, block, 0, L.stream, g, L.op, \
                      L.kappa, ph, L.partials, L.sc, fin, gate, G, P)

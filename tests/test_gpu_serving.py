@@ -111,6 +111,39 @@ def test_small_requests_pass_a_head_that_does_not_fit(wfa):
         assert np.array_equal(alone[0], g), rq
 
 
+@pytest.mark.parametrize("kind", ["diffusion", "convection"])
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_operator_builds_are_bitwise_the_general_one(wfa, kind, precision):
+    """A single grid's two-reduction passes launch the cell operator's build
+    without the scaling select (no Jacobi scaling) or also without the
+    convective terms (pure diffusion); the server's batched passes always
+    run the general build.  The same step, served and on a single grid,
+    must give the same bits and the same iteration count."""
+    import torch
+    wfa.tune_clear()
+    u = (1.0, -0.5, 0.25) if kind == "convection" else (0.0, 0.0, 0.0)
+    prob = inputs.random_problem(601, 70, 45, 38, cell=True, u=u,
+                                 bc_kind=inputs.MIXED_BC_KIND)
+    prec = wfa.PRECISIONS[precision]
+    tol = 1e-5 if precision == "f32" else 1e-10
+    dtype = torch.float32 if precision == "f32" else torch.float64
+    sv = wfa.Server(1 << 30, max_slots=2)
+    Ts = torch.from_numpy(prob.T0).to("cuda", dtype)
+    ticket = sv.submit_problem(prob, Ts, precision=prec, tol=tol, maxit=5000)
+    sv.drain()
+    code, sinfo = sv.poll(ticket)
+    sv.close()
+    assert code == wfa.OK
+    g = wfa.Grid.from_problem(prob, precision=prec)
+    g.set_option(wfa.OPT_SHADOW, 1)          # the server's shadow residual
+    g.set_option(wfa.OPT_METHOD, wfa.METHOD_BICGSTAB2)
+    T = g.field(prob.T0)
+    ginfo = g.timestep(T, 1, tol=tol, maxit=5000)[0]
+    assert ginfo.status == wfa.OK
+    assert torch.equal(T, Ts), (kind, precision)
+    assert ginfo.iterations == sinfo.iterations
+
+
 def test_reject_request_larger_than_arena(wfa):
     import torch
     sv = wfa.Server(8 << 20, max_slots=2)
