@@ -609,6 +609,16 @@ def run_serve(args, torch, inputs, wfa, keep_fields=False):
     sv.set_option(wfa.OPT_CHECK_EVERY, args.serve_round)
     sv.set_option(wfa.OPT_METHOD, METHODS[args.serve_method])
     sv.set_option(wfa.OPT_CG1_MAX_CELLS, args.serve_cg1_max_cells)
+    classes = None
+    if args.serve_classes is not None:
+        classes = [int(v) for v in args.serve_classes.split(",") if v.strip()][:3]
+        bounds = classes + [0] * (3 - len(classes))
+        for opt in (wfa.OPT_SIZE_CLASS_3, wfa.OPT_SIZE_CLASS_2, wfa.OPT_SIZE_CLASS_1):
+            sv.set_option(opt, 0)
+        for opt, v in zip((wfa.OPT_SIZE_CLASS_1, wfa.OPT_SIZE_CLASS_2, wfa.OPT_SIZE_CLASS_3),
+                          bounds):
+            if v:
+                sv.set_option(opt, v)
     tickets = {}
     t_start = time.perf_counter()
     for q, rq in enumerate(reqs):
@@ -641,6 +651,8 @@ def run_serve(args, torch, inputs, wfa, keep_fields=False):
             "cg1_max_cells": args.serve_cg1_max_cells if args.serve_method == "cg1" else None,
             "round": {"iterations": args.serve_round,
                       "launch": "persistent" if args.serve_persistent else "per pass"},
+            "size_classes": ("library default (up to 96^3, 152^3, larger)" if classes is None
+                             else {"upper_bounds_cells": classes}),
             "requests": len(reqs), "failed": fails, "makespan_s": t_end,
             "latency_ms": {"p50": percentile(lat, 50) * 1e3, "p99": percentile(lat, 99) * 1e3,
                            "mean": sum(lat) / len(lat) * 1e3},
@@ -1235,6 +1247,10 @@ def main():
                          "reduction")
     ap.add_argument("--serve-cg1-max-cells", type=int, default=0,
                     help="serve with --serve-method cg1: larger requests keep BiCGStab (0: none)")
+    ap.add_argument("--serve-classes", default=None,
+                    help="serve: comma-separated upper cell-count bounds of the server's size "
+                         "classes (each class has its own worker thread and stream); '' = one "
+                         "class; default: the library's")
     ap.add_argument("--serve-persistent", type=int, default=0, choices=[0, 1],
                     help="serve: 1 = each round is one cooperative launch per precision")
     ap.add_argument("--legs", default="c2,c1,c4,cg1,serve",

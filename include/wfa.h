@@ -300,10 +300,15 @@ enum {
                                   per iteration; the iterates are bitwise
                                   those of 0, t stored by pass 2 and read by
                                   pass 1 (default 0)                          */
-  WFA_OPT_CG1_MAX_CELLS = 14   /* server only: with WFA_OPT_METHOD =
+  WFA_OPT_CG1_MAX_CELLS = 14,  /* server only: with WFA_OPT_METHOD =
                                   WFA_METHOD_CG1, symmetric requests of more
                                   cells than this keep BiCGStab; 0 = no limit
                                   (default)                                    */
+  WFA_OPT_SIZE_CLASS_1 = 16,   /* server only: upper bounds (cells) of the   */
+  WFA_OPT_SIZE_CLASS_2 = 17,   /* size classes, each served by its own host  */
+  WFA_OPT_SIZE_CLASS_3 = 18    /* thread and HIP stream; 0 = no further class
+                                  (defaults 884736, 3511808, 0: three classes,
+                                  up to 96^3, 152^3 and above)                */
 };
 int wfa_grid_set_option(wfa_grid* g, int option, int64_t value);
 
@@ -402,20 +407,26 @@ int wfa_bandwidth_probe(int kind, int blocks, const void* src, void* dst, size_t
 /* ---- serving ------------------------------------------------------------------ */
 
 /* A server owns a caller-provided device arena of arena_bytes (its HBM
- * budget) and up to max_slots resident solves.  Requests are admitted in
- * arrival order as arena space and slots free up; all resident solves
- * advance together in batched launches (continuous batching); a request
- * finishes independently of the others and its result does not depend on
- * which requests ran beside it.  Every request is solved with the
+ * budget).  Requests are split by cell count into up to four size classes
+ * (WFA_OPT_SIZE_CLASS_*); each class has its own host thread, HIP stream
+ * and up to max_slots resident solves, so small requests' rounds do not
+ * wait for large requests' passes.  Within a class, requests are admitted
+ * in arrival order as arena space and slots free up (a request first in
+ * line that does not fit lets up to 16 later ones that fit go ahead); all
+ * resident solves of a class advance together in batched launches
+ * (continuous batching); a request finishes independently of the others
+ * and its result does not depend on which requests ran beside it or in
+ * which class.  Every request is solved with the
  * two-reduction BiCGStab and the index-hashed shadow residual, as
  * wfa_timestep does with WFA_OPT_METHOD = WFA_METHOD_BICGSTAB2 and
  * WFA_OPT_SHADOW = 1; WFA_F32_IR64 requests run it as the inner solve of
- * refinement, as wfa_timestep does.  A background host
- * thread drives the GPU on `stream`.  Precision of every request:
- * c->precision.  The server also holds a pinned host mirror of its slot
- * tables and scalars and one event, freed by wfa_server_destroy.
+ * refinement, as wfa_timestep does.  The first class's thread drives
+ * the GPU on `stream`; the others on streams the server creates (default
+ * priority).  Precision of every request: c->precision.  The server also
+ * holds a pinned host mirror of its slot tables and scalars, one event per
+ * class and the class streams, freed by wfa_server_destroy.
  * Errors: WFA_ERR_INVALID, WFA_ERR_NOMEM (arena smaller than its tables),
- * WFA_ERR_HIP (the pinned mirror or the event). */
+ * WFA_ERR_HIP (the pinned mirror, an event or a stream). */
 int wfa_server_create(void* arena, size_t arena_bytes, int max_slots, void* stream,
                       wfa_server** out);
 
@@ -440,7 +451,13 @@ int wfa_server_create(void* arena, size_t arena_bytes, int max_slots, void* stre
  *                        per-pass kernel boundaries (bitwise the same
  *                        results); 0: one launch per pass (default).  A
  *                        barrier wait that times out fails the server
- *                        (WFA_ERR_HIP) instead of hanging.
+ *                        (WFA_ERR_HIP) instead of hanging.  While it is on,
+ *                        requests submitted go to the first size class,
+ *                        which alone runs cooperative rounds;
+ *   WFA_OPT_SIZE_CLASS_1..3  upper cell-count bound of size classes 1..3
+ *                        (class 4 takes the rest); 0 ends the list.
+ *                        Non-zero bounds must increase.  A request's class
+ *                        is fixed when it is submitted.
  * Errors: WFA_ERR_INVALID (null server, unknown option, value out of range). */
 int wfa_server_set_option(wfa_server* sv, int option, int64_t value);
 

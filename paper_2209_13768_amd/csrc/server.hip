@@ -12,14 +12,19 @@
 //      solve (finished or paused solves are skipped on the device);
 //   4. reads all slots' device scalar blocks with one copy and retires,
 //      refines or restarts requests.
+// Requests are split into up to kMaxLanes size classes by their cell count
+// (WFA_OPT_SIZE_CLASS_*), each served by its own worker thread, HIP stream,
+// slots and tables: a small request's rounds do not wait for a large
+// request's passes.  The arena, the options and the tickets are shared.
 // A request's arithmetic never depends on its neighbours (tiles, partial
 // sums, reduction order and decisions are per solve), so its result is the
-// same alone and in any mix.
+// same alone, in any mix and in any class.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -39,6 +44,10 @@ using namespace wfa;
 namespace {
 
 constexpr int kScalarsPerSlot = 4;
+constexpr int kMaxLanes = 4;   // size classes, each with its own worker and stream
+// Default upper bounds (cells) of the size classes: 96^3 and 152^3, i.e.
+// three classes.  Measured on a 2000-request stream of 32^3..192^3 grids.
+constexpr int64_t kDefaultClassBound[kMaxLanes - 1] = {884736, 3511808, 0};
 
 double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -101,6 +110,7 @@ struct Request {
   int total_it = 0, refinements = 0, restarts = 0;
   int inner_cap = 0;  // > 0: repeating a diverged inner solve up to its best iterate
   int passed_over = 0;  // later requests admitted while this one, first in line, did not fit
+  int lane = 0;         // size class serving the request
   int par = 0;        // buffer parity of the next iteration (0 after every (re)start)
   int cg1 = 0;        // 1: iterates with CG with one reduction (symmetric request)
   double scale = 1.0;
@@ -115,44 +125,52 @@ struct Request {
 struct wfa_server {
   char* arena;
   size_t arena_bytes;
-  int max_slots;
-  hipStream_t stream;
-  // device regions inside the arena
-  Scalars* slot_sc;          // max_slots * kScalarsPerSlot
-  SolveDesc<float>* d32;     // max_slots
-  SolveDesc<double>* d64;    // max_slots
-  int* bases;                // 4 * (max_slots + 1)
+  int max_slots;               // resident solves per size class
+  // One size class: its worker thread, stream, slots, device tables (inside
+  // the arena) and their pinned host mirrors.  The tables are uploaded and
+  // the slot scalars read back with asynchronous copies; the worker rewrites
+  // a table only after the round that uploaded it has been waited for.
+  struct Lane {
+    int id = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;         // created by the server (classes above the first)
+    Scalars* slot_sc = nullptr;      // device: max_slots * kScalarsPerSlot
+    SolveDesc<float>* d32 = nullptr;   // device: max_slots
+    SolveDesc<double>* d64 = nullptr;  // device: max_slots
+    int* bases = nullptr;            // device: 4 * (max_slots + 1)
+    GridBarrier* bar = nullptr;      // device: grid barrier of a persistent round
+    Scalars* h_sc = nullptr;         // pinned mirrors of the above
+    SolveDesc<float>* h_d32 = nullptr;
+    SolveDesc<double>* h_d64 = nullptr;
+    int* h_bases = nullptr;
+    GridBarrier* h_bar = nullptr;
+    hipEvent_t round_done = nullptr; // the round's scalar readback
+    std::condition_variable cv_work;
+    std::deque<Request*> queue;
+    std::vector<Request*> slots;
+    int ry = 0;                      // rows per wave of every resident solve's tiling
+    std::vector<char> last_d32, last_d64, last_bases;  // bytes of the last table uploads
+    std::thread worker;
+  };
+  Lane lanes[kMaxLanes];
+  int64_t class_bound[kMaxLanes - 1];  // cell-count upper bounds of the classes (0: unused)
   size_t heap_base;
   Heap heap;
-  // host mirrors, in one pinned block: the tables are uploaded and the slot
-  // scalars read back with asynchronous copies (the host rewrites a table
-  // only after the round that uploaded it has been waited for)
   void* pinned = nullptr;
-  Scalars* h_sc = nullptr;          // max_slots * kScalarsPerSlot
-  SolveDesc<float>* h_d32 = nullptr;
-  SolveDesc<double>* h_d64 = nullptr;
-  int* h_bases = nullptr;           // 4 * (max_slots + 1)
-  hipEvent_t round_done = nullptr;  // the round's scalar readback
-  GridBarrier* bar = nullptr;       // device: grid barrier of a persistent round
-  GridBarrier* h_bar = nullptr;     // pinned: its state after the round
   // requests
   std::mutex mu;
-  std::condition_variable cv_work, cv_done;
-  std::deque<Request*> queue;
+  std::condition_variable cv_done;
   std::map<uint64_t, Request*> reqs;
-  std::vector<Request*> slots;
   uint64_t next_ticket = 1;
   int inflight = 0;  // queued + resident
   bool stop = false;
-  int worker_error = WFA_OK;
+  std::atomic<int> worker_error{WFA_OK};
+  std::mutex err_mu;
   char worker_msg[256] = "";
   int chunk = 4;      // iterations per round (WFA_OPT_CHECK_EVERY)
   int persistent = 0; // 1: a round is one cooperative launch per precision (WFA_OPT_PERSISTENT)
   int method = WFA_METHOD_BICGSTAB2;  // WFA_OPT_METHOD: _CG1 for symmetric requests
   int64_t cg1_max_cells = 0;          // WFA_OPT_CG1_MAX_CELLS (0: no limit)
-  int ry = 0;        // rows per wave of every resident solve's tiling
-  std::vector<char> last_d32, last_d64, last_bases;  // bytes of the last table uploads
-  std::thread worker;
 };
 
 namespace {
@@ -164,11 +182,23 @@ size_t request_bytes(int nx, int ny, int nz, int precision) {
   return align256(wfa_workspace_bytes(nx, ny, nz, precision));
 }
 
-int fail(wfa_server* sv, const char* what, hipError_t e) {
-  snprintf(sv->worker_msg, sizeof sv->worker_msg, "%s: %s", what, hipGetErrorString(e));
-  sv->worker_error = WFA_ERR_HIP;
-  return WFA_ERR_HIP;
+// Record a worker's failure (the first one's message is kept).
+int fail_code(wfa_server* sv, int code, const char* msg) {
+  std::lock_guard<std::mutex> lk(sv->err_mu);
+  if (sv->worker_error.load() == WFA_OK) {
+    snprintf(sv->worker_msg, sizeof sv->worker_msg, "%s", msg);
+    sv->worker_error.store(code);
+  }
+  return code;
 }
+
+int fail(wfa_server* sv, const char* what, hipError_t e) {
+  char msg[256];
+  snprintf(msg, sizeof msg, "%s: %s", what, hipGetErrorString(e));
+  return fail_code(sv, WFA_ERR_HIP, msg);
+}
+
+wfa_server::Lane& lane_of(wfa_server* sv, const Request* r) { return sv->lanes[r->lane]; }
 
 // A persistent round's waits are bounded: a barrier wait that gives up (after
 // about this many polls of a few cycles' sleep each) makes every wave leave,
@@ -176,26 +206,26 @@ int fail(wfa_server* sv, const char* what, hipError_t e) {
 constexpr int kRoundSpinLimit = 1 << 22;
 
 // Host-to-device copy of a table; remembers the first failure.
-int put(wfa_server* sv, void* dst, const void* src, size_t bytes) {
-  const hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, sv->stream);
+int put(wfa_server* sv, hipStream_t st, void* dst, const void* src, size_t bytes) {
+  const hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st);
   return e == hipSuccess ? WFA_OK : fail(sv, "table upload", e);
 }
 
 // Upload a table only when its bytes differ from the last upload: between
 // admissions, refinements and retirements the resident set's tables repeat
 // from round to round, and each copy is a dependent step on the stream.
-int put_changed(wfa_server* sv, void* dst, const void* src, size_t bytes,
+int put_changed(wfa_server* sv, hipStream_t st, void* dst, const void* src, size_t bytes,
                 std::vector<char>* last) {
   if (last->size() == bytes && memcmp(last->data(), src, bytes) == 0) return WFA_OK;
-  const int rc = put(sv, dst, src, bytes);
+  const int rc = put(sv, st, dst, src, bytes);
   if (rc == WFA_OK) last->assign((const char*)src, (const char*)src + bytes);
   else last->clear();
   return rc;
 }
 
 // Sets `count` consecutive device scalar blocks from kernel arguments.
-int put_scalars(wfa_server* sv, Scalars* dst, const Scalars* h, int count) {
-  for (int k = 0; k < count; ++k) launch_set_scalars(dst + k, h[k], sv->stream);
+int put_scalars(wfa_server* sv, hipStream_t st, Scalars* dst, const Scalars* h, int count) {
+  for (int k = 0; k < count; ++k) launch_set_scalars(dst + k, h[k], st);
   const hipError_t e = hipGetLastError();
   return e == hipSuccess ? WFA_OK : fail(sv, "scalar upload", e);
 }
@@ -240,12 +270,12 @@ SolveDesc<T> make_desc(Request* r, T* x) {
 // or the BiCGStab initialisation (plain).
 int start_request(wfa_server* sv, Request* r) {
   wfa_grid& g = r->g;
-  hipStream_t s = sv->stream;
+  hipStream_t s = lane_of(sv, r).stream;
   r->par = 0;  // the first residual goes to the parity-0 buffer
   if (g.prec == WFA_F32_IR64) {
     Scalars h2[2] = {fresh(r->tol, r->maxit), fresh(1e-4, ir_inner_maxit(r->maxit, 0))};
     h2[1].guard = kIrGuard;
-    if (int rc = put_scalars(sv, g.sc, h2, 2)) return rc;
+    if (int rc = put_scalars(sv, s, g.sc, h2, 2)) return rc;
     Launch<double> L{g.tl, g.op64, g.c.mode == WFA_COEF_CELL, (const float*)g.c.kappa,
                      g.partials, g.sc, s};
     launch_rhs<double>(L, (const double*)r->T, g.b64);
@@ -254,7 +284,7 @@ int start_request(wfa_server* sv, Request* r) {
                             kServerShadow);
   } else {
     const Scalars h = fresh(r->tol, r->maxit);
-    if (int rc = put_scalars(sv, g.sc, &h, 1)) return rc;
+    if (int rc = put_scalars(sv, s, g.sc, &h, 1)) return rc;
     if (g.prec == WFA_F64) {
       Launch<double> L{g.tl, g.op64, g.c.mode == WFA_COEF_CELL, (const float*)g.c.kappa,
                        g.partials, g.sc, s};
@@ -278,7 +308,7 @@ int start_request(wfa_server* sv, Request* r) {
 // IR: apply the inner correction and compute the next FP64 residual.
 int refine_request(wfa_server* sv, Request* r, double scale_next, bool promote) {
   wfa_grid& g = r->g;
-  hipStream_t s = sv->stream;
+  hipStream_t s = lane_of(sv, r).stream;
   if (promote) launch_promote(g.n, g.tl.pw_blocks, (double*)r->T, g.d32, g.sc_in, s);
   Scalars h2[2] = {fresh(r->tol, r->maxit),
                    fresh(1e-4, r->inner_cap > 0 ? r->inner_cap : ir_inner_maxit(r->maxit, r->total_it))};
@@ -287,7 +317,7 @@ int refine_request(wfa_server* sv, Request* r, double scale_next, bool promote) 
   ho.scale = scale_next; ho.inv_scale = 1.0 / scale_next;
   hi.scale = scale_next; hi.inv_scale = 1.0 / scale_next;
   hi.guard = r->inner_cap > 0 ? 0.0 : kIrGuard;
-  if (int rc = put_scalars(sv, g.sc, h2, 2)) return rc;
+  if (int rc = put_scalars(sv, s, g.sc, h2, 2)) return rc;
   Launch<double> L{g.tl, g.op64, g.c.mode == WFA_COEF_CELL, (const float*)g.c.kappa,
                    g.partials, g.sc, s};
   float** v = (float**)g.vec;
@@ -304,9 +334,9 @@ int refine_request(wfa_server* sv, Request* r, double scale_next, bool promote) 
 // Plain precisions: FP64 true residual of the final iterate into sc_aux.
 int final_residual(wfa_server* sv, Request* r) {
   wfa_grid& g = r->g;
-  hipStream_t s = sv->stream;
+  hipStream_t s = lane_of(sv, r).stream;
   const Scalars ha = fresh(1.0, 1);
-  if (int rc = put_scalars(sv, g.sc_aux, &ha, 1)) return rc;
+  if (int rc = put_scalars(sv, s, g.sc_aux, &ha, 1)) return rc;
   Launch<double> L{g.tl, g.op64, g.c.mode == WFA_COEF_CELL, (const float*)g.c.kappa,
                    g.partials, g.sc_aux, s};
   void** v = g.vec;
@@ -334,7 +364,7 @@ void retire(wfa_server* sv, Request* r, int code, double rel_true) {
   r->info.seconds = r->t_done - r->t_submit;
   r->phase = R_DONE;
   sv->heap.release(r->off, r->bytes);
-  sv->slots[r->slot] = nullptr;
+  lane_of(sv, r).slots[r->slot] = nullptr;
   r->slot = -1;
   --sv->inflight;
 }
@@ -351,7 +381,8 @@ int code_of(int st) {
 
 // Inspect one resident request after a round (scalars already on the host).
 int advance(wfa_server* sv, Request* r) {
-  const Scalars* hs = &sv->h_sc[r->slot * kScalarsPerSlot];
+  wfa_server::Lane& ln = lane_of(sv, r);
+  const Scalars* hs = &ln.h_sc[r->slot * kScalarsPerSlot];
   wfa_grid& g = r->g;
   if (r->phase == R_FINAL) {
     // IR: the outer block holds the FP64 residual of the last refinement;
@@ -372,7 +403,7 @@ int advance(wfa_server* sv, Request* r) {
       // x = 0 solves A x = 0.  The fill runs on the server's stream; the
       // request retires when the next round's readback, queued behind it,
       // comes back, so a caller never sees T before the fill has run.
-      launch_fill<double>(g.n, (double*)r->T, 0.0, sv->stream);
+      launch_fill<double>(g.n, (double*)r->T, 0.0, ln.stream);
       hipError_t e = hipGetLastError();
       if (e != hipSuccess) return fail(sv, "fill", e);
       r->code = WFA_OK;
@@ -433,13 +464,13 @@ int advance(wfa_server* sv, Request* r) {
     r->par = 0;  // the restart's residual goes to the parity-0 buffer
     if (g.prec == WFA_F64) {
       Launch<double> L{g.tl, g.op64, g.c.mode == WFA_COEF_CELL, (const float*)g.c.kappa,
-                       g.partials, g.sc, sv->stream};
+                       g.partials, g.sc, ln.stream};
       double** v = (double**)g.vec;
       L.shadow = kServerShadow;
       launch_init<double>(L, false, (double*)r->T, v[7], nullptr, v[0], v[1]);
     } else {
       Launch<float> L{g.tl, g.op32, g.c.mode == WFA_COEF_CELL, (const float*)g.c.kappa,
-                      g.partials, g.sc, sv->stream};
+                      g.partials, g.sc, ln.stream};
       float** v = (float**)g.vec;
       L.shadow = kServerShadow;
       launch_init<float>(L, false, (float*)r->T, v[7], nullptr, v[0], v[1]);
@@ -450,40 +481,36 @@ int advance(wfa_server* sv, Request* r) {
   r->last_rec = h.bb > 0.0 ? sqrt(h.rr / h.bb) : 0.0;
   r->code = code_of(h.status);
   if (h.status == ST_BZERO) {
-    if (g.prec == WFA_F64) launch_fill<double>(g.n, (double*)r->T, 0.0, sv->stream);
-    else launch_fill<float>(g.n, (float*)r->T, 0.0f, sv->stream);
+    if (g.prec == WFA_F64) launch_fill<double>(g.n, (double*)r->T, 0.0, ln.stream);
+    else launch_fill<float>(g.n, (float*)r->T, 0.0f, ln.stream);
   }
   return final_residual(sv, r);
 }
 
 // Rebuild the batched work tables of the resident set.
-int build_tables(wfa_server* sv, int* n32, int* tiles32, int* pw32, int* n64, int* tiles64,
-                 int* pw64) {
+int build_tables(wfa_server* sv, wfa_server::Lane& ln, int* n32, int* tiles32, int* pw32,
+                 int* n64, int* tiles64, int* pw64) {
   const int S = sv->max_slots;
   int a = 0, b = 0, t32 = 0, p32 = 0, t64 = 0, p64 = 0;
-  int* tb32 = &sv->h_bases[0];
-  int* pb32 = &sv->h_bases[S + 1];
-  int* tb64 = &sv->h_bases[2 * (S + 1)];
-  int* pb64 = &sv->h_bases[3 * (S + 1)];
+  int* tb32 = &ln.h_bases[0];
+  int* pb32 = &ln.h_bases[S + 1];
+  int* tb64 = &ln.h_bases[2 * (S + 1)];
+  int* pb64 = &ln.h_bases[3 * (S + 1)];
   for (int s = 0; s < S; ++s) {
-    Request* r = sv->slots[s];
+    Request* r = ln.slots[s];
     if (!r || (r->phase != R_ITER && r->phase != R_REFINE)) continue;
     const int ry = r->g.prec == WFA_F32_IR64 ? r->g.tl32.ry : r->g.tl.ry;
-    if (ry != sv->ry) {
-      snprintf(sv->worker_msg, sizeof sv->worker_msg, "tilings with different rows per wave");
-      sv->worker_error = WFA_ERR_INVALID;
-      return WFA_ERR_INVALID;
-    }
+    if (ry != ln.ry) return fail_code(sv, WFA_ERR_INVALID, "tilings with different rows per wave");
     if (is_f32_batch(r)) {
       float* x = r->g.prec == WFA_F32_IR64 ? r->g.d32 : (float*)r->T;
-      sv->h_d32[a] = make_desc<float>(r, x);
+      ln.h_d32[a] = make_desc<float>(r, x);
       tb32[a] = t32; pb32[a] = p32;
-      t32 += sv->h_d32[a].geo.ntiles; p32 += sv->h_d32[a].pw_blocks;
+      t32 += ln.h_d32[a].geo.ntiles; p32 += ln.h_d32[a].pw_blocks;
       ++a;
     } else {
-      sv->h_d64[b] = make_desc<double>(r, (double*)r->T);
+      ln.h_d64[b] = make_desc<double>(r, (double*)r->T);
       tb64[b] = t64; pb64[b] = p64;
-      t64 += sv->h_d64[b].geo.ntiles; p64 += sv->h_d64[b].pw_blocks;
+      t64 += ln.h_d64[b].geo.ntiles; p64 += ln.h_d64[b].pw_blocks;
       ++b;
     }
   }
@@ -499,15 +526,15 @@ int build_tables(wfa_server* sv, int* n32, int* tiles32, int* pw32, int* n64, in
 constexpr int kMaxPassOver = 16;
 constexpr int kAdmitScan = 64;   // queued requests looked at per round
 
-void admit(wfa_server* sv, std::vector<Request*>* admitted) {
+void admit(wfa_server* sv, wfa_server::Lane& ln, std::vector<Request*>* admitted) {
   Request* blocked = nullptr;  // the earliest request that did not fit
   int scanned = 0;
-  for (auto it = sv->queue.begin(); it != sv->queue.end() && scanned < kAdmitScan; ++scanned) {
+  for (auto it = ln.queue.begin(); it != ln.queue.end() && scanned < kAdmitScan; ++scanned) {
     Request* r = *it;
     if (blocked && blocked->passed_over >= kMaxPassOver) return;
     int slot = -1;
     for (int s = 0; s < sv->max_slots; ++s)
-      if (!sv->slots[s]) { slot = s; break; }
+      if (!ln.slots[s]) { slot = s; break; }
     if (slot < 0) return;
     size_t off = 0;
     if (!sv->heap.alloc(r->bytes, &off)) {
@@ -516,29 +543,46 @@ void admit(wfa_server* sv, std::vector<Request*>* admitted) {
       continue;
     }
     if (blocked) ++blocked->passed_over;
-    it = sv->queue.erase(it);
+    it = ln.queue.erase(it);
     r->slot = slot;
     r->off = off;
-    sv->slots[slot] = r;
+    ln.slots[slot] = r;
     admitted->push_back(r);
   }
 }
 
-void worker_main(wfa_server* sv) {
+// Fail every request of one class, resident or queued (under sv->mu).
+void fail_lane(wfa_server* sv, wfa_server::Lane& ln, int rc) {
+  for (auto*& r : ln.slots)
+    if (r) { r->code = rc; r->phase = R_DONE; r->t_done = now_s(); r = nullptr; --sv->inflight; }
+  for (auto* r : ln.queue) { r->code = rc; r->phase = R_DONE; r->t_done = now_s(); --sv->inflight; }
+  ln.queue.clear();
+  sv->cv_done.notify_all();
+}
+
+void worker_main(wfa_server* sv, int lane) {
+  wfa_server::Lane& ln = sv->lanes[lane];
   std::vector<Request*> admitted;
   while (true) {
     admitted.clear();
     int chunk = 0, persist = 0;  // this round's options
     {
       std::unique_lock<std::mutex> lk(sv->mu);
+      if (const int err = sv->worker_error.load()) {
+        // another class failed: the server stays unusable
+        fail_lane(sv, ln, err);
+        break;
+      }
       chunk = sv->chunk;
-      persist = sv->persistent;
-      admit(sv, &admitted);
+      // only the first class runs cooperative rounds (while it is on, new
+      // requests all go to that class)
+      persist = lane == 0 ? sv->persistent : 0;
+      admit(sv, ln, &admitted);
       bool any = false;
-      for (auto* r : sv->slots) any = any || r != nullptr;
+      for (auto* r : ln.slots) any = any || r != nullptr;
       if (!any && admitted.empty()) {
         if (sv->stop) break;
-        sv->cv_work.wait(lk);
+        ln.cv_work.wait(lk);
         continue;
       }
     }
@@ -553,96 +597,100 @@ void worker_main(wfa_server* sv) {
       if (tuned_tiling(r->nx, r->ny, r->nz, r->c.precision, r->c.mode, &t_ry, &t_zc) &&
           t_ry == shared_ry)
         apply_tiling(&r->g, t_ry, t_zc);
-      // the slot's scalar blocks live in the server's contiguous region
-      r->g.sc = sv->slot_sc + r->slot * kScalarsPerSlot;
+      // the slot's scalar blocks live in the class's contiguous region
+      r->g.sc = ln.slot_sc + r->slot * kScalarsPerSlot;
       r->g.sc_in = r->g.sc + 1;
       r->g.sc_aux = r->g.sc + 2;
       // every grid keeps the default rule's row count, so all share it
-      sv->ry = r->g.prec == WFA_F32_IR64 ? r->g.tl32.ry : r->g.tl.ry;
+      ln.ry = r->g.prec == WFA_F32_IR64 ? r->g.tl32.ry : r->g.tl.ry;
       if ((rc = start_request(sv, r))) break;
     }
     int n32 = 0, t32 = 0, p32 = 0, n64 = 0, t64 = 0, p64 = 0;
-    if (!rc) {
-      rc = build_tables(sv, &n32, &t32, &p32, &n64, &t64, &p64);
-    }
+    if (!rc) rc = build_tables(sv, ln, &n32, &t32, &p32, &n64, &t64, &p64);
     // persistent rounds carry two-reduction BiCGStab only: a round with a
     // CG1 solve resident makes one launch per pass
-    for (Request* r : sv->slots)
+    for (Request* r : ln.slots)
       if (r && r->cg1) persist = 0;
+    const int S = sv->max_slots;
     if (!rc) {
-      const int S = sv->max_slots;
-      rc = put_changed(sv, sv->d32, sv->h_d32, sizeof(SolveDesc<float>) * std::max(n32, 1),
-                       &sv->last_d32);
+      rc = put_changed(sv, ln.stream, ln.d32, ln.h_d32,
+                       sizeof(SolveDesc<float>) * std::max(n32, 1), &ln.last_d32);
       if (!rc)
-        rc = put_changed(sv, sv->d64, sv->h_d64, sizeof(SolveDesc<double>) * std::max(n64, 1),
-                         &sv->last_d64);
+        rc = put_changed(sv, ln.stream, ln.d64, ln.h_d64,
+                         sizeof(SolveDesc<double>) * std::max(n64, 1), &ln.last_d64);
       if (!rc)
-        rc = put_changed(sv, sv->bases, sv->h_bases, sizeof(int) * 4 * (S + 1), &sv->last_bases);
+        rc = put_changed(sv, ln.stream, ln.bases, ln.h_bases, sizeof(int) * 4 * (S + 1),
+                         &ln.last_bases);
     }
     if (!rc) {
-      const int S = sv->max_slots;
       // two-reduction BiCGStab iterations of every resident solve: one
       // launch per pass, or the whole round in one cooperative launch per
       // precision (bitwise the same iterates)
       hipError_t e = hipSuccess;
       if (persist) {
         if (n32)
-          e = launch_batch_persistent<float>(sv->d32, sv->bases, t32, n32, chunk, sv->ry, sv->bar,
-                                             kRoundSpinLimit, sv->stream);
+          e = launch_batch_persistent<float>(ln.d32, ln.bases, t32, n32, chunk, ln.ry, ln.bar,
+                                             kRoundSpinLimit, ln.stream);
         if (e == hipSuccess && n64)
-          e = launch_batch_persistent<double>(sv->d64, sv->bases + 2 * (S + 1), t64, n64, chunk,
-                                              sv->ry, sv->bar, kRoundSpinLimit, sv->stream);
+          e = launch_batch_persistent<double>(ln.d64, ln.bases + 2 * (S + 1), t64, n64, chunk,
+                                              ln.ry, ln.bar, kRoundSpinLimit, ln.stream);
       } else {
         for (int q = 0; q < chunk; ++q) {
           if (n32)
-            launch_batch_iteration2<float>(sv->d32, sv->bases, t32, n32, q, sv->ry, sv->stream);
+            launch_batch_iteration2<float>(ln.d32, ln.bases, t32, n32, q, ln.ry, ln.stream);
           if (n64)
-            launch_batch_iteration2<double>(sv->d64, sv->bases + 2 * (S + 1), t64, n64, q, sv->ry,
-                                            sv->stream);
+            launch_batch_iteration2<double>(ln.d64, ln.bases + 2 * (S + 1), t64, n64, q, ln.ry,
+                                            ln.stream);
         }
         e = hipGetLastError();
       }
       // (a CG1 solve's buffers return to parity 0 after each pair of passes)
-      for (Request* r : sv->slots)
+      for (Request* r : ln.slots)
         if (r && !r->cg1 && (r->phase == R_ITER || r->phase == R_REFINE)) r->par ^= (chunk & 1);
       if (e != hipSuccess) rc = fail(sv, "batched iteration", e);
     }
     if (!rc) {
-      hipError_t e = hipMemcpyAsync(sv->h_sc, sv->slot_sc,
+      hipError_t e = hipMemcpyAsync(ln.h_sc, ln.slot_sc,
                                     sizeof(Scalars) * kScalarsPerSlot * sv->max_slots,
-                                    hipMemcpyDeviceToHost, sv->stream);
+                                    hipMemcpyDeviceToHost, ln.stream);
       if (e == hipSuccess && persist)
-        e = hipMemcpyAsync(sv->h_bar, sv->bar, sizeof(GridBarrier), hipMemcpyDeviceToHost,
-                           sv->stream);
-      if (e == hipSuccess) e = hipEventRecord(sv->round_done, sv->stream);
-      if (e == hipSuccess) e = wait_event(sv->round_done);
-      if (e != hipSuccess) {
+        e = hipMemcpyAsync(ln.h_bar, ln.bar, sizeof(GridBarrier), hipMemcpyDeviceToHost,
+                           ln.stream);
+      if (e == hipSuccess) e = hipEventRecord(ln.round_done, ln.stream);
+      if (e == hipSuccess) e = wait_event(ln.round_done);
+      if (e != hipSuccess)
         rc = fail(sv, "scalar readback", e);
-      } else if (persist && sv->h_bar->timeout) {
-        snprintf(sv->worker_msg, sizeof sv->worker_msg,
-                 "persistent round: a grid barrier wait timed out");
-        sv->worker_error = rc = WFA_ERR_HIP;
-      }
+      else if (persist && ln.h_bar->timeout)
+        rc = fail_code(sv, WFA_ERR_HIP, "persistent round: a grid barrier wait timed out");
     }
     std::unique_lock<std::mutex> lk(sv->mu);
     if (rc) {
-      // fail every resident and queued request; the server stays unusable
-      for (auto*& r : sv->slots)
-        if (r) { r->code = rc; r->phase = R_DONE; r->t_done = now_s(); r = nullptr; }
-      for (auto* r : sv->queue) { r->code = rc; r->phase = R_DONE; r->t_done = now_s(); }
-      sv->queue.clear();
-      sv->inflight = 0;
-      sv->cv_done.notify_all();
+      // fail every request of this class; the other classes stop at their
+      // next round and the server stays unusable
+      fail_lane(sv, ln, rc);
+      for (auto& other : sv->lanes) other.cv_work.notify_all();
       break;
     }
     for (int s = 0; s < sv->max_slots; ++s) {
-      Request* r = sv->slots[s];
+      Request* r = ln.slots[s];
       if (!r || r->phase == R_START) continue;
       if ((rc = advance(sv, r))) break;
     }
     sv->cv_done.notify_all();
-    if (rc) break;
+    if (rc) {
+      fail_lane(sv, ln, rc);
+      for (auto& other : sv->lanes) other.cv_work.notify_all();
+      break;
+    }
   }
+}
+
+// The class a request of `cells` cells goes to.
+int lane_for(const wfa_server* sv, int64_t cells) {
+  if (sv->persistent) return 0;
+  int k = 0;
+  while (k < kMaxLanes - 1 && sv->class_bound[k] > 0 && cells > sv->class_bound[k]) ++k;
+  return k;
 }
 
 }  // namespace
@@ -653,54 +701,86 @@ extern "C" int wfa_server_create(void* arena, size_t arena_bytes, int max_slots,
   *out = nullptr;
   if (!arena || ((uintptr_t)arena & 255)) return set_error(WFA_ERR_INVALID, "arena must be non-NULL and 256-byte aligned");
   if (max_slots < 1 || max_slots > 4096) return set_error(WFA_ERR_INVALID, "max_slots must be in [1, 4096]");
+  // per class: slot scalars, the two descriptor tables, tile bases, barrier
   const size_t sc_bytes = align256(sizeof(Scalars) * kScalarsPerSlot * max_slots);
   const size_t d32_bytes = align256(sizeof(SolveDesc<float>) * max_slots);
   const size_t d64_bytes = align256(sizeof(SolveDesc<double>) * max_slots);
   const size_t b_bytes = align256(sizeof(int) * 4 * (max_slots + 1));
   const size_t bar_bytes = align256(sizeof(GridBarrier));
-  const size_t meta = sc_bytes + d32_bytes + d64_bytes + b_bytes + bar_bytes;
+  const size_t lane_bytes = sc_bytes + d32_bytes + d64_bytes + b_bytes + bar_bytes;
+  const size_t meta = kMaxLanes * lane_bytes;
   if (arena_bytes <= meta) return set_error(WFA_ERR_NOMEM, "arena smaller than the slot tables");
   wfa_server* sv = new (std::nothrow) wfa_server();
   if (!sv) return set_error(WFA_ERR_NOMEM, "host allocation failed");
   sv->arena = (char*)arena;
   sv->arena_bytes = arena_bytes;
   sv->max_slots = max_slots;
-  sv->stream = (hipStream_t)stream;
-  sv->slot_sc = (Scalars*)sv->arena;
-  sv->d32 = (SolveDesc<float>*)(sv->arena + sc_bytes);
-  sv->d64 = (SolveDesc<double>*)(sv->arena + sc_bytes + d32_bytes);
-  sv->bases = (int*)(sv->arena + sc_bytes + d32_bytes + d64_bytes);
-  sv->bar = (GridBarrier*)(sv->arena + sc_bytes + d32_bytes + d64_bytes + b_bytes);
+  for (int k = 0; k < kMaxLanes - 1; ++k) sv->class_bound[k] = kDefaultClassBound[k];
   sv->heap_base = meta;
   sv->heap.init(arena_bytes - meta);
-  {
-    const size_t hb = meta;  // same carving as the arena
-    hipError_t e = hipHostMalloc(&sv->pinned, hb, hipHostMallocDefault);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&sv->round_done, hipEventDisableTiming);
-    // the persistent rounds' barrier starts with no arrivals and no timeout
-    if (e == hipSuccess) e = hipMemsetAsync(sv->bar, 0, sizeof(GridBarrier), sv->stream);
-    if (e != hipSuccess) {
-      if (sv->round_done) (void)hipEventDestroy(sv->round_done);
-      if (sv->pinned) (void)hipHostFree(sv->pinned);
-      delete sv;
-      return set_error(WFA_ERR_HIP, "server host tables: %s", hipGetErrorString(e));
+  auto teardown = [&](const char* what, hipError_t e) {
+    for (auto& ln : sv->lanes) {
+      if (ln.round_done) (void)hipEventDestroy(ln.round_done);
+      if (ln.own_stream && ln.stream) (void)hipStreamDestroy(ln.stream);
     }
-    char* h = (char*)sv->pinned;
-    memset(h, 0, hb);
-    sv->h_sc = (Scalars*)h;
-    sv->h_d32 = (SolveDesc<float>*)(h + sc_bytes);
-    sv->h_d64 = (SolveDesc<double>*)(h + sc_bytes + d32_bytes);
-    sv->h_bases = (int*)(h + sc_bytes + d32_bytes + d64_bytes);
-    sv->h_bar = (GridBarrier*)(h + sc_bytes + d32_bytes + d64_bytes + b_bytes);
+    if (sv->pinned) (void)hipHostFree(sv->pinned);
+    delete sv;
+    return set_error(WFA_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+  };
+  hipError_t e = hipHostMalloc(&sv->pinned, meta, hipHostMallocDefault);
+  if (e != hipSuccess) return teardown("server host tables", e);
+  memset(sv->pinned, 0, meta);
+  for (int k = 0; k < kMaxLanes; ++k) {
+    wfa_server::Lane& ln = sv->lanes[k];
+    ln.id = k;
+    char* d = sv->arena + k * lane_bytes;
+    char* h = (char*)sv->pinned + k * lane_bytes;
+    ln.slot_sc = (Scalars*)d;
+    ln.d32 = (SolveDesc<float>*)(d + sc_bytes);
+    ln.d64 = (SolveDesc<double>*)(d + sc_bytes + d32_bytes);
+    ln.bases = (int*)(d + sc_bytes + d32_bytes + d64_bytes);
+    ln.bar = (GridBarrier*)(d + sc_bytes + d32_bytes + d64_bytes + b_bytes);
+    ln.h_sc = (Scalars*)h;
+    ln.h_d32 = (SolveDesc<float>*)(h + sc_bytes);
+    ln.h_d64 = (SolveDesc<double>*)(h + sc_bytes + d32_bytes);
+    ln.h_bases = (int*)(h + sc_bytes + d32_bytes + d64_bytes);
+    ln.h_bar = (GridBarrier*)(h + sc_bytes + d32_bytes + d64_bytes + b_bytes);
+    ln.slots.assign(max_slots, nullptr);
+    // the first class runs on the caller's stream, the others on streams of
+    // their own (default priority)
+    if (k == 0) {
+      ln.stream = (hipStream_t)stream;
+    } else {
+      e = hipStreamCreateWithFlags(&ln.stream, hipStreamNonBlocking);
+      if (e != hipSuccess) return teardown("server stream", e);
+      ln.own_stream = true;
+    }
+    e = hipEventCreateWithFlags(&ln.round_done, hipEventDisableTiming);
+    if (e != hipSuccess) return teardown("server event", e);
   }
-  sv->slots.assign(max_slots, nullptr);
+  // the persistent rounds' barrier starts with no arrivals and no timeout
+  e = hipMemsetAsync(sv->lanes[0].bar, 0, sizeof(GridBarrier), sv->lanes[0].stream);
+  if (e != hipSuccess) return teardown("server barrier", e);
+  int started = 0;
   try {
-    sv->worker = std::thread(worker_main, sv);
+    for (; started < kMaxLanes; ++started)
+      sv->lanes[started].worker = std::thread(worker_main, sv, started);
   } catch (...) {
-    (void)hipEventDestroy(sv->round_done);
+    {
+      std::lock_guard<std::mutex> lk(sv->mu);
+      sv->stop = true;
+    }
+    for (int k = 0; k < started; ++k) {
+      sv->lanes[k].cv_work.notify_all();
+      sv->lanes[k].worker.join();
+    }
+    for (auto& ln : sv->lanes) {
+      (void)hipEventDestroy(ln.round_done);
+      if (ln.own_stream) (void)hipStreamDestroy(ln.stream);
+    }
     (void)hipHostFree(sv->pinned);
     delete sv;
-    return set_error(WFA_ERR_NOMEM, "could not start the server thread");
+    return set_error(WFA_ERR_NOMEM, "could not start the server threads");
   }
   *out = sv;
   return WFA_OK;
@@ -728,6 +808,20 @@ extern "C" int wfa_server_set_option(wfa_server* sv, int option, int64_t value) 
         return set_error(WFA_ERR_INVALID, "iterations per round must be in [1, 1024]");
       sv->chunk = (int)value;
       return WFA_OK;
+    case WFA_OPT_SIZE_CLASS_1:
+    case WFA_OPT_SIZE_CLASS_2:
+    case WFA_OPT_SIZE_CLASS_3: {
+      if (value < 0) return set_error(WFA_ERR_INVALID, "size class bound must be >= 0");
+      int64_t b[kMaxLanes - 1];
+      for (int k = 0; k < kMaxLanes - 1; ++k) b[k] = sv->class_bound[k];
+      b[option - WFA_OPT_SIZE_CLASS_1] = value;
+      for (int k = 1; k < kMaxLanes - 1; ++k)
+        if (b[k] > 0 && !(b[k - 1] > 0 && b[k] > b[k - 1]))
+          return set_error(WFA_ERR_INVALID,
+                           "size class bounds must increase, each after a non-zero one");
+      for (int k = 0; k < kMaxLanes - 1; ++k) sv->class_bound[k] = b[k];
+      return WFA_OK;
+    }
     default:
       return set_error(WFA_ERR_INVALID, "option %d is not a server option", option);
   }
@@ -754,19 +848,20 @@ extern "C" int wfa_submit(wfa_server* sv, int nx, int ny, int nz, const wfa_coef
   r->t_submit = now_s();
   {
     std::lock_guard<std::mutex> lk(sv->mu);
-    if (sv->worker_error) {
+    if (const int err = sv->worker_error.load()) {
       delete r;
-      return set_error(sv->worker_error, "server failed: %s", sv->worker_msg);
+      return set_error(err, "server failed: %s", sv->worker_msg);
     }
     r->ticket = sv->next_ticket++;
     const int64_t cells = (int64_t)nx * ny * nz;
     r->cg1 = sv->method == WFA_METHOD_CG1 && c->u[0] == 0.0 && c->u[1] == 0.0 &&
              c->u[2] == 0.0 && (sv->cg1_max_cells == 0 || cells <= sv->cg1_max_cells);
+    r->lane = lane_for(sv, cells);
     sv->reqs[r->ticket] = r;
-    sv->queue.push_back(r);
+    sv->lanes[r->lane].queue.push_back(r);
     ++sv->inflight;
   }
-  sv->cv_work.notify_one();
+  sv->lanes[r->lane].cv_work.notify_one();
   *ticket = r->ticket;
   return WFA_OK;
 }
@@ -779,7 +874,7 @@ extern "C" int wfa_poll(wfa_server* sv, uint64_t ticket, wfa_solve_info* info) {
   Request* r = it->second;
   if (r->phase != R_DONE) return WFA_PENDING;
   if (info) *info = r->info;
-  if (r->code < 0 && r->code == sv->worker_error)
+  if (r->code < 0 && r->code == sv->worker_error.load())
     set_error(r->code, "server failed: %s", sv->worker_msg);
   return r->code;
 }
@@ -787,8 +882,9 @@ extern "C" int wfa_poll(wfa_server* sv, uint64_t ticket, wfa_solve_info* info) {
 extern "C" int wfa_server_drain(wfa_server* sv) {
   if (!sv) return set_error(WFA_ERR_INVALID, "server is NULL");
   std::unique_lock<std::mutex> lk(sv->mu);
-  sv->cv_done.wait(lk, [&] { return sv->inflight == 0 || sv->worker_error != 0; });
-  if (sv->worker_error) return set_error(sv->worker_error, "server failed: %s", sv->worker_msg);
+  sv->cv_done.wait(lk, [&] { return sv->inflight == 0 || sv->worker_error.load() != 0; });
+  if (const int err = sv->worker_error.load())
+    return set_error(err, "server failed: %s", sv->worker_msg);
   return WFA_OK;
 }
 
@@ -796,13 +892,21 @@ extern "C" int wfa_server_destroy(wfa_server* sv) {
   if (!sv) return set_error(WFA_ERR_INVALID, "server is NULL");
   {
     std::unique_lock<std::mutex> lk(sv->mu);
-    sv->cv_done.wait(lk, [&] { return sv->inflight == 0 || sv->worker_error != 0; });
+    sv->cv_done.wait(lk, [&] { return sv->inflight == 0 || sv->worker_error.load() != 0; });
     sv->stop = true;
   }
-  sv->cv_work.notify_all();
-  if (sv->worker.joinable()) sv->worker.join();
+  for (auto& ln : sv->lanes) ln.cv_work.notify_all();
+  for (auto& ln : sv->lanes)
+    if (ln.worker.joinable()) ln.worker.join();
   for (auto& kv : sv->reqs) delete kv.second;
-  (void)hipEventDestroy(sv->round_done);  // teardown: nothing to report a failure to
+  // teardown: nothing to report a failure to
+  for (auto& ln : sv->lanes) {
+    (void)hipEventDestroy(ln.round_done);
+    if (ln.own_stream) {
+      (void)hipStreamSynchronize(ln.stream);
+      (void)hipStreamDestroy(ln.stream);
+    }
+  }
   (void)hipHostFree(sv->pinned);
   delete sv;
   return WFA_OK;

@@ -25,6 +25,7 @@ OPT_METHOD, OPT_PERSISTENT, OPT_PROFILE, OPT_FORCE_BREAKDOWN, OPT_CHECK_EVERY = 
 OPT_IR_INNER_TOL, OPT_ZCHUNK, OPT_RY, OPT_JACOBI, OPT_GRAPH = 6, 7, 8, 9, 10
 OPT_EXPLICIT_FUSE, OPT_SHADOW, OPT_FORCE_DIVERGE, OPT_CG1_MAX_CELLS = 11, 12, 13, 14
 OPT_RECOMPUTE_T = 15
+OPT_SIZE_CLASS_1, OPT_SIZE_CLASS_2, OPT_SIZE_CLASS_3 = 16, 17, 18
 K_APPLY, K_INIT, K_PHASE_A, K_PHASE_B, K_PHASE_C, K_RESIDUAL, K_PROMOTE = 0, 1, 2, 3, 4, 5, 6
 K_CG_A, K_CG_B, K_PERSISTENT, K_PHASE_AC, K_PHASE_B2, K_EXPLICIT = 7, 8, 9, 10, 11, 12
 K_EXPLICIT_FUSED, K_CG1, K_COUNT = 13, 14, 15

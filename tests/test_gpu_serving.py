@@ -197,7 +197,39 @@ def test_server_options_are_validated(wfa):
     sv.set_option(wfa.OPT_PERSISTENT, 1)
     sv.set_option(wfa.OPT_METHOD, wfa.METHOD_CG1)
     sv.set_option(wfa.OPT_METHOD, wfa.METHOD_BICGSTAB2)
+    # size classes: bounds increase, each after a non-zero one
+    for opt, val in ((wfa.OPT_SIZE_CLASS_1, -1), (wfa.OPT_SIZE_CLASS_2, 100),
+                     (wfa.OPT_SIZE_CLASS_1, 0), (wfa.OPT_SIZE_CLASS_3, 1000)):
+        with pytest.raises(wfa.WfaError) as e:
+            sv.set_option(opt, val)
+        assert e.value.code == wfa.ERR_INVALID
+    sv.set_option(wfa.OPT_SIZE_CLASS_3, 8_000_000)
+    sv.set_option(wfa.OPT_SIZE_CLASS_3, 0)
+    sv.set_option(wfa.OPT_SIZE_CLASS_2, 0)
+    sv.set_option(wfa.OPT_SIZE_CLASS_1, 0)
+    sv.set_option(wfa.OPT_SIZE_CLASS_1, 40_000)
     sv.close()
+
+
+def test_size_classes_are_bitwise_one_class(wfa):
+    """Requests split into size classes (each with its own worker thread,
+    stream, slots and tables) give the bits they get with every request in
+    one class, in three precisions, with four classes, the default three,
+    and one; the classes run at the same time."""
+    dims = DIMS + [(96, 96, 64), (20, 30, 40), (128, 96, 96), (32, 32, 32)]
+    reqs = _requests(dims)
+    precs = [wfa.F32_IR64, wfa.F64, wfa.F32, wfa.F32_IR64, wfa.F64, wfa.F32_IR64, wfa.F32,
+             wfa.F64, wfa.F32_IR64, wfa.F32_IR64]
+    tols = [1e-5 if p == wfa.F32 else 1e-9 for p in precs]
+    one = {wfa.OPT_SIZE_CLASS_2: 0, wfa.OPT_SIZE_CLASS_1: 0}
+    four = {wfa.OPT_SIZE_CLASS_1: 40_000, wfa.OPT_SIZE_CLASS_2: 100_000,
+            wfa.OPT_SIZE_CLASS_3: 300_000}
+    ref, rinfo = _serve(wfa, reqs, 1 << 30, slots=8, precision=precs, tol=tols, options=one)
+    for opts in ({}, four):
+        got, ginfo = _serve(wfa, reqs, 1 << 30, slots=8, precision=precs, tol=tols, options=opts)
+        for rq, a, b, ia, ib in zip(reqs, ref, got, rinfo, ginfo):
+            assert np.array_equal(a, b), (opts, rq)
+            assert (ia.iterations, ia.refinements) == (ib.iterations, ib.refinements), (opts, rq)
 
 
 class _Given:
