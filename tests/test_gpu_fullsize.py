@@ -7,16 +7,18 @@ shadow residual where the benchmark uses it).
   iterates against the oracle's same variant, and one backward-Euler step
   whose result the oracle's operator must see at the benchmark's tolerance.
 * 512x512x1024 smooth-diffusivity diffusion in FP32: the whole operator, the
-  first iterate, and two iterations of the one-reduction CG.
+  first iterate, two iterations of the one-reduction CG, and the sixth
+  iterate of the benchmarked solve against the FP64 oracle.
 * 384^3 convection-diffusion (velocity x4): FP32 inside FP64 refinement to
   1e-12, judged by the oracle's FP64 operator.
 * The serving stream's first requests (their real grid sizes), batched
   together: each result meets 1e-10 under the oracle's operator, and equals
   the same request served alone, bit for bit.
 
-Where BiCGStab amplifies rounding, an iterate is held to 100x the oracle's
-own change under a one-ulp perturbation of b (as in the smaller trajectory
-tests), floored at the FP64 bar.
+Where BiCGStab amplifies rounding, an iterate is held to the trajectory bar
+of tests/parity_bars.py: 15 sqrt(m) times the oracle's own change under a
+one-ulp perturbation of b (m operator applications), floored at the FP64
+bar (the FP32 bar and a one-FP32-ulp perturbation for FP32 iterates).
 """
 import numpy as np
 import pytest
@@ -129,6 +131,33 @@ def test_poisson_512x512x1024_operator_and_first_iterate(wfa, oracle_mod):
     x2, info = g.solve(g.field(b), g.field(), tol=1e-300, maxit=2, method="cg1", check=False)
     assert info.iterations == 2
     assert rel_l2(_np(x2), xc) <= FP32_TOL
+
+
+def test_poisson_512x512x1024_fp32_trajectory(wfa, oracle_mod):
+    """The headline solve's first iterates beyond the first: FP32 on the GPU
+    against the FP64 oracle's same method (two-reduction, hashed shadow),
+    from the benchmark's x0 = T0.  FP32 arithmetic rounds every operator
+    application and every stored vector at 2^-24, and the iteration
+    amplifies it; the bar is the FP64 one's derivation (tests/parity_bars.py)
+    with a one-FP32-ulp perturbation of b and x0 in place of a one-FP64-ulp
+    one: 15 sqrt(m + 1) times the oracle's own change under it (m operator
+    applications, one more for the rounding of b and x0 to FP32), floored
+    at the FP32 bar."""
+    k = 6
+    prob = inputs.poisson_large()
+    o = oracle_mod.Oracle(prob)
+    x0 = prob.T0.astype(np.float32).astype(np.float64)
+    b = o.rhs(prob.T0)
+    run = lambda bb, xx: o.bicgstab2(bb, xx, 1e-300, k, hashed_shadow=True)[0]
+    xo = run(b, x0)
+    s32 = sensitivity(run, b, x0, eps=2.0 ** -23, seeds=(0,))
+    g = wfa.Grid.from_problem(prob, precision=wfa.F32)
+    g.set_option(wfa.OPT_SHADOW, 1)
+    xk, info = g.solve(g.field(b), g.field(x0), tol=1e-300, maxit=k, method="bicgstab2",
+                       check=False)
+    assert info.iterations == k
+    bound = trajectory_bound(s32, 2 * k + 1, floor=FP32_TOL)
+    check(f"poisson512x512x1024 fp32 k={k}", rel_l2(_np(xk), xo), bound, s32)
 
 
 def test_mixed_precision_384_reaches_1e12(wfa, oracle_mod):
