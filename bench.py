@@ -918,19 +918,29 @@ def leg_c1(args, torch, inputs, wfa, oracle_mod):
 
 
 def leg_c4(args, torch, inputs, wfa, oracle_mod):
-    """384^3 convection-diffusion (u x4), one step to 1e-10: FP32 inside FP64
-    refinement (inner tolerance 1e-3) against plain FP64, both two-reduction
-    BiCGStab with r^ = r0; oracle-evaluated true residuals."""
+    """384^3 convection-diffusion (u x4): FP32 inside FP64 refinement (inner
+    tolerance 1e-3) against plain FP64, both two-reduction BiCGStab with
+    r^ = r0.  One step to 1e-10 (the comparison tolerance), then a time
+    integration of args.c4_steps steps to 1e-12 (the workload's tolerance),
+    each from the previous step's result; oracle-evaluated true residuals of
+    the first and last steps."""
     prob = inputs.convdiff_384()
     o = oracle_mod.Oracle(prob)
-    b = o.rhs(prob.T0)
-    out = {"workload": "mixed_384^3_u4_tol1e-10"}
-    ref = None
-    for name, prec, itol in (("f64", wfa.F64, None), ("f32_ir64", wfa.F32_IR64, 1e-3)):
+    out = {"workload": "mixed_384^3_u4"}
+    variants = (("f64", wfa.F64, None), ("f32_ir64", wfa.F32_IR64, 1e-3))
+
+    def grid(prec, itol):
         g = wfa.Grid.from_problem(prob, precision=prec)
         g.set_option(wfa.OPT_METHOD, METHODS["bicgstab2"])
         if itol is not None:
             g.set_option(wfa.OPT_IR_INNER_TOL, int(round(itol * 1e12)))
+        return g
+
+    # one step to 1e-10
+    b = o.rhs(prob.T0)
+    step1, ref = {}, None
+    for name, prec, itol in variants:
+        g = grid(prec, itol)
         T = g.field(prob.T0)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -945,9 +955,44 @@ def leg_c4(args, torch, inputs, wfa, oracle_mod):
             ref = Tn
         else:
             rec["rel_l2_vs_f64"] = rel_l2(Tn, ref)
-        out[name] = rec
+        step1[name] = rec
         del g, T
-    out["speedup_f32_ir64"] = out["f64"]["seconds"] / out["f32_ir64"]["seconds"]
+    step1["speedup_f32_ir64"] = step1["f64"]["seconds"] / step1["f32_ir64"]["seconds"]
+    out["step1_tol1e-10"] = step1
+
+    # time integration to 1e-12
+    steps = args.c4_steps
+    integ, finals = {"steps": steps, "tol": 1e-12}, {}
+    for name, prec, itol in variants:
+        g = grid(prec, itol)
+        T = g.field(prob.T0)
+        prev = prob.T0
+        its, refs, worst, oracle_checks, ok = 0, 0, 0.0, {}, 0
+        t_total = 0.0
+        for k in range(1, steps + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = g.timestep(T, 1, tol=1e-12, maxit=100000, check=False)[0]
+            torch.cuda.synchronize()
+            t_total += time.perf_counter() - t0
+            its += info.iterations
+            refs += info.refinements
+            ok += info.status == wfa.OK
+            worst = max(worst, info.rel_res_true)
+            if k in (1, steps):   # the oracle's operator on this step's system
+                Tn = T.cpu().numpy()
+                oracle_checks[str(k)] = o.true_relres(o.rhs(prev), Tn)
+            if k == 1 or k == steps - 1:
+                prev = T.cpu().numpy()
+        finals[name] = T.cpu().numpy()
+        integ[name] = {"seconds": t_total, "ms_per_step": t_total / steps * 1e3,
+                       "iterations_per_step": its / steps, "refinements_per_step": refs / steps,
+                       "status_ok_steps": ok, "rel_res_true_max": worst,
+                       "rel_res_true_oracle_operator": oracle_checks}
+        del g, T
+    integ["f32_ir64"]["rel_l2_vs_f64_final"] = rel_l2(finals["f32_ir64"], finals["f64"])
+    integ["speedup_f32_ir64"] = integ["f64"]["seconds"] / integ["f32_ir64"]["seconds"]
+    out[f"{steps}_steps_tol1e-12"] = integ
     return out
 
 
@@ -1261,6 +1306,9 @@ def main():
     ap.add_argument("--recompute-t", type=int, default=0, choices=[0, 1],
                     help="two-reduction BiCGStab: 1 = pass 1 forms t = A s again instead of "
                          "pass 2 storing it (bitwise the same iterates, two streams fewer)")
+    ap.add_argument("--c4-steps", type=int, default=20,
+                    help="headline: steps of the 384^3 refinement-vs-FP64 time integration leg "
+                         "to 1e-12 (50: the workload's full length, about 145 s)")
     ap.add_argument("--c2-steps", type=int, default=50,
                     help="headline: steps of the 256^3 FP64 time integration leg")
     ap.add_argument("--no-profile", action="store_true",
