@@ -177,6 +177,44 @@ __device__ __forceinline__ T cell_apply(const Op<T>& op, T c, const T nb[6], T k
   return cell_apply<T, CELL, FORM>(op, c, nb, kP, kN, inside, dg, kz, false);
 }
 
+// The diffusion-only operator (op_form(op) == kFormDiffusion, per-cell
+// diffusivity) split into its coefficients and their application, for a
+// pass that applies A to two vectors on the same cells: D[f] = cD
+// harmonic(kP, kN[f]) on faces with a neighbour and 0 on the others, and
+// the diagonal 1 + sum_f (D[f], or cD kP on a Dirichlet face) summed in
+// face order.  With `carry` the z- face takes dz (the previous plane's z+
+// coefficient, the same value: see cell_apply); dz returns this plane's z+
+// one.  apply_coefs(D, diag, c, nb) then gives cell_apply's value bit for
+// bit: the zero coefficients add fma(0, nb, acc) = acc for finite nb.
+template <typename T>
+__device__ __forceinline__ T diffusion_coefs(const Op<T>& op, T kP, const T kN[6],
+                                             uint32_t inside, T (&D)[6], T& dz, bool carry) {
+#pragma clang fp contract(off)
+  T diag = T(1);
+#pragma unroll
+  for (int f = 0; f < 6; ++f) {
+    T d = T(0);
+    if (inside & (1u << f)) {
+      d = (f == 4 && carry) ? dz : op.cD * (T(2) * kP * kN[f] * pos_rcp(kP + kN[f]));
+      diag += d;
+    } else if (op.dir & (1u << f)) {
+      diag += op.cD * kP;
+    }
+    if (f == 5) dz = d;
+    D[f] = d;
+  }
+  return diag;
+}
+
+template <typename T>
+__device__ __forceinline__ T apply_coefs(const T (&D)[6], T diag, T c, const T nb[6]) {
+#pragma clang fp contract(off)
+  T acc = T(0);
+#pragma unroll
+  for (int f = 0; f < 6; ++f) acc = fma_t(D[f], nb[f], acc);
+  return fma_t(diag, c, -acc);
+}
+
 // Dirichlet contribution of cell P to the right-hand side.
 template <typename T, bool CELL>
 __device__ __forceinline__ T cell_bterm(const Op<T>& op, T kP, uint32_t inside) {

@@ -25,6 +25,13 @@
 // planes, the diffusivity in a ring of 4 and p' in a ring of 2, each with a
 // two-cell halo: with these depths one barrier per plane orders every write
 // after the last read of its slot.
+//
+// With the diffusion-only operator the two products on an own cell share
+// their coefficients: level 1 forms each face's coefficient and the
+// diagonal once (diffusion_coefs, the z- face carried from the plane below)
+// for t, keeps them, and level 2 applies them to p' a plane later
+// (apply_coefs) -- the same values bit for bit, and no harmonic mean in
+// level 2.
 #include <hip/hip_runtime.h>
 
 #include "device.hpp"
@@ -84,7 +91,7 @@ __device__ __forceinline__ bool ring2_cell(int hs, int& lx, int& ly) {
   return false;
 }
 
-template <typename T, bool CELL, int RY>
+template <typename T, bool CELL, int RY, int FORM>
 __global__ void __launch_bounds__(kThreads)
 k_phase_act(Geo g, Op<T> op, const float* __restrict__ kappa, ActArgs<T> a, double* partials,
             Scalars* sc) {
@@ -219,6 +226,18 @@ k_phase_act(Geo g, Op<T> op, const float* __restrict__ kappa, ActArgs<T> a, doub
     rh0[r] = ppm[r] = pp0[r] = pp1[r] = T(0);
   }
   double acc[3] = {0.0, 0.0, 0.0};  // (rh, v'), (rh, r'), (r', r')
+  // shared coefficients of own cells (diffusion-only operator): those of
+  // the plane level 1 just formed (n) and of the plane level 2 applies (o)
+  constexpr bool SHARE = CELL && FORM == kFormDiffusion;
+  T Dn[RY][6], dgn[RY], Do[RY][6], dgo[RY], dzc[RY];
+  bool zcar = false;   // dzc holds the z+ coefficients of the last level-1 plane
+#pragma unroll
+  for (int r = 0; r < RY; ++r) {
+    dgn[r] = dgo[r] = T(1);
+    dzc[r] = T(0);
+#pragma unroll
+    for (int f = 0; f < 6; ++f) Dn[r][f] = Do[r][f] = T(0);
+  }
 
   // stage plane q: s into LDS slot q and the "k+2" registers
   auto stage = [&](const Loads& L, int q) {
@@ -262,6 +281,11 @@ k_phase_act(Geo g, Op<T> op, const float* __restrict__ kappa, ActArgs<T> a, doub
       p1[r] = p2[r]; v1r[r] = v2r[r]; x1[r] = x2[r];
       rh0[r] = rh1[r]; rh1[r] = rh2[r];
       ppm[r] = pp0[r]; pp0[r] = pp1[r];
+      if (SHARE) {
+        dgo[r] = dgn[r];
+#pragma unroll
+        for (int f = 0; f < 6; ++f) Do[r][f] = Dn[r][f];
+      }
     }
     hs0 = hs1; hs1 = hs2;
     hk0 = hk1; hk1 = hk2;
@@ -281,7 +305,7 @@ k_phase_act(Geo g, Op<T> op, const float* __restrict__ kappa, ActArgs<T> a, doub
       for (int f = 0; f < 6; ++f) kn[f] = T(1);
     }
     T dg;
-    return cell_apply<T, CELL>(op, sc_, nb, (T)kc, kn, mask, dg);
+    return cell_apply<T, CELL, FORM>(op, sc_, nb, (T)kc, kn, mask, dg);
   };
   // level 1 on plane q = k + 1: t, r', p' on own cells (stored with x' on
   // output planes) and on the one-cell halo of output planes; p' into LDS
@@ -290,6 +314,7 @@ k_phase_act(Geo g, Op<T> op, const float* __restrict__ kappa, ActArgs<T> a, doub
     if (q < 0 || q >= nz) {
 #pragma unroll
       for (int r = 0; r < RY; ++r) pp1[r] = T(0);
+      zcar = false;
       return;
     }
     const T* S = sS + (q % 3) * SP;
@@ -301,9 +326,24 @@ k_phase_act(Geo g, Op<T> op, const float* __restrict__ kappa, ActArgs<T> a, doub
     for (int r = 0; r < RY; ++r) {
       T pn = T(0);
       if (own[r]) {
-        const T t = first ? T(0)
-                          : form_t(lo[r], S, K, s1[r], s0[r], s2[r], kk1[r], kk0[r], kk2[r],
-                                   mo[r] | mz);
+        T t;
+        if constexpr (SHARE) {
+          // this plane's coefficients, for t now and for v' a plane later
+          const int l = lo[r];
+          const T kn[6] = {(T)K[l - 1], (T)K[l + 1], (T)K[l - SW], (T)K[l + SW], (T)kk0[r],
+                           (T)kk2[r]};
+          dgn[r] = diffusion_coefs<T>(op, (T)kk1[r], kn, mo[r] | mz, Dn[r], dzc[r], zcar);
+          if (first) {
+            t = T(0);
+          } else {
+            const T nb[6] = {S[l - 1], S[l + 1], S[l - SW], S[l + SW], s0[r], s2[r]};
+            t = apply_coefs<T>(Dn[r], dgn[r], s1[r], nb);
+          }
+        } else {
+          t = first ? T(0)
+                    : form_t(lo[r], S, K, s1[r], s0[r], s2[r], kk1[r], kk0[r], kk2[r],
+                             mo[r] | mz);
+        }
         const T rn = minus_ax(s1[r], omega, t);
         pn = next_p(rn, p1[r], v1r[r], beta, omega);
         if (outp) {
@@ -318,6 +358,7 @@ k_phase_act(Geo g, Op<T> op, const float* __restrict__ kappa, ActArgs<T> a, doub
       P[lo[r]] = pn;
       pp1[r] = pn;
     }
+    zcar = SHARE;
     if (l1 >= 0 && outp) {
       T pn = T(0);
       if (v1) {
@@ -339,16 +380,21 @@ k_phase_act(Geo g, Op<T> op, const float* __restrict__ kappa, ActArgs<T> a, doub
       if (!own[r]) continue;
       const int l = lo[r];
       T nb[6] = {P[l - 1], P[l + 1], P[l - SW], P[l + SW], ppm[r], pp1[r]};
-      T kn[6];
-      if (CELL) {
-        kn[0] = (T)K[l - 1]; kn[1] = (T)K[l + 1]; kn[2] = (T)K[l - SW]; kn[3] = (T)K[l + SW];
-        kn[4] = (T)km[r]; kn[5] = (T)kk1[r];
+      T Av;
+      if constexpr (SHARE) {
+        Av = apply_coefs<T>(Do[r], dgo[r], pp0[r], nb);
       } else {
+        T kn[6];
+        if (CELL) {
+          kn[0] = (T)K[l - 1]; kn[1] = (T)K[l + 1]; kn[2] = (T)K[l - SW]; kn[3] = (T)K[l + SW];
+          kn[4] = (T)km[r]; kn[5] = (T)kk1[r];
+        } else {
 #pragma unroll
-        for (int f = 0; f < 6; ++f) kn[f] = T(1);
+          for (int f = 0; f < 6; ++f) kn[f] = T(1);
+        }
+        T dg;
+        Av = cell_apply<T, CELL, FORM>(op, pp0[r], nb, (T)kk0[r], kn, mo[r] | mz, dg);
       }
-      T dg;
-      const T Av = cell_apply<T, CELL>(op, pp0[r], nb, (T)kk0[r], kn, mo[r] | mz, dg);
       st_once(a.v_out + (size_t)k * plane + poff[r], Av);
       dot_acc(acc[0], (double)rh0[r], (double)Av);
     }
@@ -398,22 +444,23 @@ void launch_phase_act(const Launch<T>& L, const T* r, const T* v, const T* p, co
   const Geo g = L.tl.geo;
   ActArgs<T> a{r, v, p, rh, x, r_out, p_out, v_out, L.shadow};
   dim3 grid(g.ntiles), block(kThreads);
-#define WFA_ACT(CELLV, RYV)                                                               \
-  hipLaunchKernelGGL((k_phase_act<T, CELLV, RYV>), grid, block, 0, L.stream, g, L.op,      \
+#define WFA_ACT(CELLV, RYV, FV)                                                           \
+  hipLaunchKernelGGL((k_phase_act<T, CELLV, RYV, FV>), grid, block, 0, L.stream, g, L.op,  \
                      L.kappa, a, L.partials, L.sc)
-  if (L.cell) {
-    switch (L.tl.ry) {
-      case 1: WFA_ACT(true, 1); break;
-      case 4: WFA_ACT(true, 4); break;
-      default: WFA_ACT(true, 2); break;
-    }
-  } else {
-    switch (L.tl.ry) {
-      case 1: WFA_ACT(false, 1); break;
-      case 4: WFA_ACT(false, 4); break;
-      default: WFA_ACT(false, 2); break;
-    }
+#define WFA_ACT_RY(CELLV, FV)                      \
+  switch (L.tl.ry) {                               \
+    case 1: WFA_ACT(CELLV, 1, FV); break;          \
+    case 4: WFA_ACT(CELLV, 4, FV); break;          \
+    default: WFA_ACT(CELLV, 2, FV); break;         \
   }
+  if (L.cell && op_form(L.op) == kFormDiffusion) {
+    WFA_ACT_RY(true, kFormDiffusion);
+  } else if (L.cell) {
+    WFA_ACT_RY(true, kFormGeneral);
+  } else {
+    WFA_ACT_RY(false, kFormGeneral);
+  }
+#undef WFA_ACT_RY
 #undef WFA_ACT
 }
 
