@@ -86,3 +86,37 @@ def test_gpus_other_than_one_refused():
                          text=True, timeout=120)
     assert res.returncode == 2
     assert "one GPU" in res.stdout
+
+
+def test_gpu_busy_union_of_intervals():
+    """Busy time is the union of the kernel intervals over the span from the
+    first start to the last end (overlapping kernels of concurrent streams
+    count once), and the gaps are those between merged intervals."""
+    us = 1000
+    spans = [(0, 10 * us), (5 * us, 12 * us),      # overlap: one interval 0..12
+             (40 * us, 50 * us),                   # gap 28 us
+             (55 * us, 60 * us), (58 * us, 59 * us)]  # gap 5 us; nested interval
+    busy, gaps = bench.gpu_busy(spans)
+    assert abs(busy - (12 + 10 + 5) / 60) < 1e-12
+    assert gaps["over_20us"] == 1 and abs(gaps["over_20us_total_ms"] - 0.028) < 1e-12
+    assert gaps["median_us"] in (5.0, 28.0)
+    assert bench.gpu_busy([(3, 9)])[0] == 1.0
+
+
+def test_pmc_summary_means_per_working_dispatch(tmp_path):
+    """Counter means per kernel over working dispatches: a dispatch under a
+    fifth of the kernel's 90th percentile (a pass skipped after the solve
+    stopped) is left out, and every counter of every file gets a row."""
+    rows = []
+    for did, (name, v) in enumerate([(AC, 100.0)] * 5 + [(AC, 1.0)] + [(B2, 40.0)] * 4):
+        for c, scale in (("SQ_INSTS_VALU", 1.0), ("SQ_WAVES", 0.5)):
+            rows.append({"Dispatch_Id": did, "Kernel_Name": name, "Counter_Name": c,
+                         "Counter_Value": v * scale})
+    _write(tmp_path / "c.csv", ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"], rows)
+    md = bench.summarize_pmc([str(tmp_path / "c.csv")], "t", ["cmd"])
+    lines = {l.split("|")[1].strip(): l for l in md.splitlines() if l.startswith("| SQ_")}
+    assert set(lines) == {"SQ_INSTS_VALU", "SQ_WAVES"}
+    cols = [c.strip() for c in md.splitlines()[[i for i, l in enumerate(md.splitlines())
+                                                 if l.startswith("| counter")][0]].split("|")[2:-1]]
+    valu = [c.strip() for c in lines["SQ_INSTS_VALU"].split("|")[2:-1]]
+    assert dict(zip(cols, valu)) == {"phase_ac": "100", "phase_b2": "40"}
