@@ -56,7 +56,8 @@ HEADLINE_ITERS = 500
 
 # The files that define the single-grid solver kernels and their launch
 # shapes: counter figures taken from other sources are stale.
-KERNEL_SOURCES = ("device.hpp", "phases.hpp", "kernels.hip")
+# sources of the stencil passes, and of the copy that calibrates the counters
+KERNEL_SOURCES = ("device.hpp", "phases.hpp", "kernels.hip", "probes.hip")
 
 
 def kernel_source_hash() -> str:
@@ -796,7 +797,29 @@ def copy_ceiling(torch, wfa, nbytes: int = COPY_PROBE_BYTES) -> dict:
     torch.cuda.synchronize()
     memcpy = 2.0 * nbytes * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
     del src, dst
-    return {"copy_kernel_gbps": round(kern, 1), "memcpy_d2d_gbps": round(memcpy, 1)}
+    out = {"copy_kernel_gbps": round(kern, 1), "memcpy_d2d_gbps": round(memcpy, 1)}
+    out.update(mix_ceilings(torch, wfa, nbytes))
+    return out
+
+
+# the stream mix of each pass of the two-reduction BiCGStab: pass 1 reads
+# x, r, p, v, t and the diffusivity and writes x, r, p, v; pass 2 reads r, v
+# and the diffusivity and writes t
+KERNEL_MIX = {"phase_ac": "mix_6r4w_gbps", "phase_b2": "mix_3r1w_gbps"}
+
+
+def mix_ceilings(torch, wfa, stream_bytes: int) -> dict:
+    """GB/s of the library's stream-mix probes (the two passes' read/write
+    mixes, nontemporal, 16 B per lane) with streams of `stream_bytes`."""
+    out = {}
+    for kind, key in ((wfa.PROBE_MIX_6R4W, "mix_6r4w_gbps"), (wfa.PROBE_MIX_3R1W, "mix_3r1w_gbps")):
+        nr, nw = wfa.PROBE_STREAMS[kind]
+        src = torch.ones(nr * stream_bytes, dtype=torch.uint8, device="cuda")
+        dst = torch.empty(nw * stream_bytes, dtype=torch.uint8, device="cuda")
+        out[key] = round(wfa.bandwidth_probe(kind, src, dst, reps=10), 1)
+        del src, dst
+    torch.cuda.empty_cache()
+    return out
 
 
 def oracle_sample(prob, T0_32, iters: int):
@@ -1108,7 +1131,7 @@ def run_headline(args, torch, inputs, wfa):
     if profile:
         dom = max(kernels, key=lambda k: kernels[k]["ms_total"])
         achieved = kernels[dom]["gbps"]
-        best = max(ceiling.values())
+        best = max(ceiling["copy_kernel_gbps"], ceiling["memcpy_d2d_gbps"])
         roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                     "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBPS, 4),
@@ -1116,6 +1139,11 @@ def run_headline(args, torch, inputs, wfa):
                     "measured": "HIP events around every launch on the solve stream inside "
                                 "the timed steps",
                     "copy_ceiling_gbps": ceiling, "frac_of_best_copy": round(achieved / best, 4)}
+        if dom in KERNEL_MIX:
+            roofline["frac_of_own_mix"] = round(achieved / ceiling[KERNEL_MIX[dom]], 4)
+        for k, key in KERNEL_MIX.items():
+            if k in kernels:
+                kernels[k]["of_own_mix"] = round(kernels[k]["gbps"] / ceiling[key], 4)
     # two-reduction, hashed shadow: 9 + 3 vector streams, or 8 + 2 when pass 1
     # forms t again instead of pass 2 storing it
     streams = 10 if args.recompute_t else 12
@@ -1211,7 +1239,9 @@ def run_headline(args, torch, inputs, wfa):
 def run_ceilings(args, torch, inputs, wfa):
     """HBM bandwidth ceilings: the library's probe kernels (copy, 16 and 32
     bytes per lane, nontemporal and plain; read only; write only) over 1 and
-    4 GiB with 2048 to 16384 workgroups, and hipMemcpyAsync device to device."""
+    4 GiB with 2048 to 16384 workgroups, hipMemcpyAsync device to device, and
+    the two passes' stream mixes (six reads and four writes; three reads and
+    one write) with streams of 128 MiB and 1 GiB."""
     out = {"workload": "hbm_ceilings", "results": []}
     for gib in (1, 4):
         nbytes = gib << 30
@@ -1219,7 +1249,7 @@ def run_ceilings(args, torch, inputs, wfa):
         dst = torch.empty_like(src)
         src.fill_(1)
         dst.fill_(0)
-        for kind, name in enumerate(wfa.PROBE_NAMES):
+        for kind, name in enumerate(wfa.PROBE_NAMES[:wfa.PROBE_MIX_6R4W]):
             for blocks in (2048, 4096, 8192, 16384):
                 gbps = wfa.bandwidth_probe(kind, src, dst, reps=10, blocks=blocks)
                 out["results"].append({"bytes": nbytes, "kind": name, "blocks": blocks,
@@ -1237,9 +1267,23 @@ def run_ceilings(args, torch, inputs, wfa):
                                              / 1e9, 1)})
         del src, dst
         torch.cuda.empty_cache()
+    # the passes' stream mixes, with streams of a 256^3 FP64 and a
+    # 512x512x1024 FP32 vector
+    for sb in (128 << 20, 1 << 30):
+        for kind in (wfa.PROBE_MIX_6R4W, wfa.PROBE_MIX_3R1W):
+            nr, nw = wfa.PROBE_STREAMS[kind]
+            src = torch.ones(nr * sb, dtype=torch.uint8, device="cuda")
+            dst = torch.empty(nw * sb, dtype=torch.uint8, device="cuda")
+            for blocks in (2048, 4096, 8192, 16384):
+                gbps = wfa.bandwidth_probe(kind, src, dst, reps=10, blocks=blocks)
+                out["results"].append({"bytes": sb, "kind": wfa.PROBE_NAMES[kind],
+                                       "blocks": blocks, "gbps": round(gbps, 1)})
+            del src, dst
+            torch.cuda.empty_cache()
     best = {}
     for r in out["results"]:
-        key = f"{r['kind']}_{r['bytes'] >> 30}GiB"
+        key = (f"{r['kind']}_{r['bytes'] >> 30}GiB" if r["bytes"] >= 1 << 30
+               else f"{r['kind']}_{r['bytes'] >> 20}MiB")
         best[key] = max(best.get(key, 0.0), r["gbps"])
     out["best"] = best
     return out

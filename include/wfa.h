@@ -393,13 +393,21 @@ int wfa_stream_probe(const void* src, void* dst, size_t bytes, int reps, double*
  *   WFA_PROBE_READ        reads src only (nontemporal); may write the first
  *                         4096 bytes of dst
  *   WFA_PROBE_WRITE       writes dst only (nontemporal); src unused
- * bytes: a multiple of 16 (32 for COPY32), at least 4096 for READ; src and
- * dst: device buffers of `bytes` bytes, 16-byte (COPY32: 32-byte) aligned.
+ *   WFA_PROBE_MIX_6R4W    the fused update pass's stream mix: reads six
+ *                         streams and writes four, `bytes` each; src holds
+ *                         the six back to back (6 * bytes), dst the four
+ *                         (4 * bytes); written stream k is the xor of read
+ *                         streams k and k + 4 (k < 2) or stream k alone
+ *   WFA_PROBE_MIX_3R1W    the second pass's mix: reads three streams (src,
+ *                         3 * bytes) and writes their xor (dst, bytes)
+ * bytes: a multiple of 16 (32 for COPY32), at least 4096 for READ, at most
+ * 2^40; src and dst: device buffers of `bytes` bytes (the stream mixes: as
+ * above), 16-byte (COPY32: 32-byte) aligned.
  * Errors: WFA_ERR_INVALID (bad kind, size, alignment or null pointer),
  * WFA_ERR_HIP. */
 enum {
   WFA_PROBE_COPY = 0, WFA_PROBE_COPY_PLAIN = 1, WFA_PROBE_COPY32 = 2, WFA_PROBE_READ = 3,
-  WFA_PROBE_WRITE = 4
+  WFA_PROBE_WRITE = 4, WFA_PROBE_MIX_6R4W = 5, WFA_PROBE_MIX_3R1W = 6
 };
 int wfa_bandwidth_probe(int kind, int blocks, const void* src, void* dst, size_t bytes, int reps,
                         double* gbps, void* stream);

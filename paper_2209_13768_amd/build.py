@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libwfa.so")
 SOURCES = ["kernels.hip", "explicit_tb.hip", "persistent.hip", "batched.hip", "api.hip", "tune.hip",
-           "server.hip", "noalloc.hip", "fused_ac.hip"]
+           "server.hip", "noalloc.hip", "fused_ac.hip", "probes.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -1389,13 +1389,15 @@ extern "C" int wfa_stream_probe(const void* src, void* dst, size_t bytes, int re
 
 extern "C" int wfa_bandwidth_probe(int kind, int blocks, const void* src, void* dst, size_t bytes,
                                    int reps, double* gbps, void* stream) {
-  if (kind < WFA_PROBE_COPY || kind > WFA_PROBE_WRITE)
+  if (kind < WFA_PROBE_COPY || kind > WFA_PROBE_MIX_3R1W)
     return set_error(WFA_ERR_INVALID, "unknown probe kind %d", kind);
-  const bool reads = kind != WFA_PROBE_WRITE;
+  const bool reads = probe_reads(kind) > 0;
   const size_t unit = kind == WFA_PROBE_COPY32 ? 32 : 16;
   if ((reads && !src) || !dst || !gbps || reps < 1 || bytes < unit || (bytes % unit) != 0 ||
       blocks < 0 || blocks > (1 << 20))
     return set_error(WFA_ERR_INVALID, "bad bandwidth probe arguments");
+  if (bytes > ((size_t)1 << 40))
+    return set_error(WFA_ERR_INVALID, "probe streams of at most 1 TiB");
   if (kind == WFA_PROBE_READ && bytes < (size_t)kThreads * 16)
     return set_error(WFA_ERR_INVALID, "read probe needs at least %d bytes", kThreads * 16);
   if ((((uintptr_t)src) | ((uintptr_t)dst)) & (unit - 1))

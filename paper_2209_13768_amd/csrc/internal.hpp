@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include "device.hpp"
+#include "wfa.h"
 
 namespace wfa {
 
@@ -114,6 +115,16 @@ template <typename T>
 hipError_t launch_persistent_bicgstab(const Launch<T>& L, T* x, T* r, const T* rh, T* p0, T* p1,
                                       T* v0, T* v1, T* t, int iters, int parity,
                                       GridBarrier* bar);
+
+// Streams a probe kind reads and writes: `bytes` each (a copy: 2; a stream
+// mix: its reads and writes).
+inline int probe_reads(int kind) {
+  return kind == WFA_PROBE_WRITE ? 0 : kind == WFA_PROBE_MIX_6R4W ? 6 : kind == WFA_PROBE_MIX_3R1W ? 3 : 1;
+}
+inline int probe_writes(int kind) {
+  return kind == WFA_PROBE_READ ? 0 : kind == WFA_PROBE_MIX_6R4W ? 4 : 1;
+}
+inline int probe_streams(int kind) { return probe_reads(kind) + probe_writes(kind); }
 
 // HBM bandwidth probe of one kind (WFA_PROBE_*): GB/s over `reps` launches
 // of `blocks` workgroups.

@@ -31,7 +31,11 @@ K_CG_A, K_CG_B, K_PERSISTENT, K_PHASE_AC, K_PHASE_B2, K_EXPLICIT = 7, 8, 9, 10, 
 K_EXPLICIT_FUSED, K_CG1, K_COUNT = 13, 14, 15
 VEC_R, VEC_RHAT, VEC_T, VEC_P0, VEC_P1, VEC_V0, VEC_V1, VEC_B, VEC_R1 = range(9)
 PROBE_COPY, PROBE_COPY_PLAIN, PROBE_COPY32, PROBE_READ, PROBE_WRITE = range(5)
-PROBE_NAMES = ("copy_nt16", "copy_plain16", "copy_nt32", "read_nt16", "write_nt16")
+PROBE_MIX_6R4W, PROBE_MIX_3R1W = 5, 6
+PROBE_NAMES = ("copy_nt16", "copy_plain16", "copy_nt32", "read_nt16", "write_nt16",
+               "mix_6r4w_nt16", "mix_3r1w_nt16")
+# streams read and written by each probe kind (a copy reads one, writes one)
+PROBE_STREAMS = ((1, 1), (1, 1), (1, 1), (1, 0), (0, 1), (6, 4), (3, 1))
 KERNEL_NAMES = ("apply", "init", "phase_a", "phase_b", "phase_c", "residual", "promote",
                 "cg_a", "cg_b", "persistent", "phase_ac", "phase_b2", "explicit", "explicit_fused",
                 "cg1")
@@ -403,10 +407,21 @@ def stream_probe(nbytes: int = 1 << 30, reps: int = 10, stream=None) -> float:
 
 def bandwidth_probe(kind: int, src, dst, reps: int = 10, blocks: int = 0, stream=None) -> float:
     """GB/s of one access pattern (PROBE_*) over the device tensors src and
-    dst (same size in bytes; src unused by PROBE_WRITE)."""
-    nbytes = dst.numel() * dst.element_size()
-    if src.numel() * src.element_size() != nbytes or not (src.is_cuda and dst.is_cuda):
-        raise ValueError("src and dst must be CUDA tensors of the same size in bytes")
+    dst (same size in bytes; src unused by PROBE_WRITE).  The stream mixes
+    take src holding their read streams back to back and dst their written
+    ones, all of one size."""
+    if not (src.is_cuda and dst.is_cuda):
+        raise ValueError("src and dst must be CUDA tensors")
+    nr, nw = PROBE_STREAMS[kind] if 0 <= kind < len(PROBE_STREAMS) else (1, 1)
+    sb, db = src.numel() * src.element_size(), dst.numel() * dst.element_size()
+    if kind in (PROBE_MIX_6R4W, PROBE_MIX_3R1W):
+        nbytes = db // nw
+        if sb != nr * nbytes or db != nw * nbytes:
+            raise ValueError(f"this stream mix takes src of {nr} and dst of {nw} streams of one size")
+    else:
+        nbytes = db
+        if sb != nbytes:
+            raise ValueError("src and dst must be of the same size in bytes")
     g = ctypes.c_double()
     _check(lib().wfa_bandwidth_probe(int(kind), int(blocks), ctypes.c_void_p(src.data_ptr()),
                                      ctypes.c_void_p(dst.data_ptr()), nbytes, int(reps),

@@ -142,3 +142,27 @@ def test_tuning_table_file_and_grid_creation(libwfa, tmp_path):
     with pytest.raises(wfa.WfaError):
         wfa.tune_load(str(tmp_path / "missing.txt"))
     wfa.tune_clear()
+
+
+def test_bandwidth_probe_kinds_and_validation(libwfa):
+    """The probe kinds of the header and the binding agree, and bad kinds,
+    sizes and pointers are refused before any device work."""
+    from paper_2209_13768_amd import wfa
+    text = open(os.path.join(ROOT, "include", "wfa.h")).read()
+    kinds = dict((k, int(v)) for k, v in re.findall(r"\bWFA_PROBE_([A-Z0-9_]+)\s*=\s*(\d+)", text))
+    assert kinds == {"COPY": wfa.PROBE_COPY, "COPY_PLAIN": wfa.PROBE_COPY_PLAIN,
+                     "COPY32": wfa.PROBE_COPY32, "READ": wfa.PROBE_READ,
+                     "WRITE": wfa.PROBE_WRITE, "MIX_6R4W": wfa.PROBE_MIX_6R4W,
+                     "MIX_3R1W": wfa.PROBE_MIX_3R1W}
+    assert len(wfa.PROBE_NAMES) == len(wfa.PROBE_STREAMS) == len(kinds)
+    g = ctypes.c_double()
+    fake = ctypes.c_void_p(1 << 20)
+    for kind, size, src in ((-1, 4096, fake), (7, 4096, fake), (wfa.PROBE_MIX_6R4W, 4104, fake),
+                            (wfa.PROBE_MIX_3R1W, 4096, None), (wfa.PROBE_COPY32, 4112, fake),
+                            (wfa.PROBE_READ, 1024, fake), (wfa.PROBE_MIX_6R4W, (1 << 40) + 16, fake)):
+        rc = libwfa.wfa_bandwidth_probe(kind, 0, src, fake, size, 1, ctypes.byref(g), None)
+        assert rc == wfa.ERR_INVALID, (kind, size)
+    # unaligned buffers
+    rc = libwfa.wfa_bandwidth_probe(wfa.PROBE_MIX_3R1W, 0, ctypes.c_void_p((1 << 20) + 8), fake,
+                                    4096, 1, ctypes.byref(g), None)
+    assert rc == wfa.ERR_INVALID
