@@ -506,7 +506,10 @@ struct PhResid {
 // and stages p' = r' + beta (p - omega v) (with halo) for v' = A p';
 // reduces sigma = (rh, v'), (rh, r'), ||r'||^2.  On the first pass of a
 // (re)start p' = r (and r is copied through so the r buffers alternate).
-template <typename T>
+// HASHED: the build for the index-hashed shadow residual alone; it forms rh
+// when the cell is staged instead of when its loads are issued (PD planes
+// earlier), so no register holds it meanwhile: the same value.
+template <typename T, bool HASHED = false>
 struct PhAC {
   static constexpr int NV = 3;
   static constexpr int PD = 2;  // measured: 4% faster than 1 at 256^3 FP64
@@ -527,7 +530,9 @@ struct PhAC {
   int x_zero;      // x is still the zero initial guess (refinement's correction)
   int hashed;      // shadow residual from the cell index (not stored)
   struct Raw { T r, v, t, p; };
-  struct ORaw { T r, v, t, p, x, rh; };
+  struct ORawStored { T r, v, t, p, x, rh; };
+  struct ORawHashed { T r, v, t, p, x; };
+  using ORaw = std::conditional_t<HASHED, ORawHashed, ORawStored>;
   struct ERaw {};
   __device__ void bind(const Scalars* sc) {
     alpha = (T)sc->alpha;
@@ -546,14 +551,22 @@ struct PhAC {
     return next_p(rn, q.p, q.v, beta, omega);
   }
   __device__ ORaw fetch_own(size_t i) const {
-    const T sh = hashed ? hashed_shadow<T>(i) : ld_once(rh + i);
-    if (first) return {r[i], T(0), T(0), T(0), T(0), sh};
-    return {r[i], v[i], t[i], p[i], x_zero ? T(0) : ld_once(x + i), sh};
+    if constexpr (HASHED) {
+      if (first) return {r[i], T(0), T(0), T(0), T(0)};
+      return {r[i], v[i], t[i], p[i], x_zero ? T(0) : ld_once(x + i)};
+    } else {
+      const T sh = hashed ? hashed_shadow<T>(i) : ld_once(rh + i);
+      if (first) return {r[i], T(0), T(0), T(0), T(0), sh};
+      return {r[i], v[i], t[i], p[i], x_zero ? T(0) : ld_once(x + i), sh};
+    }
   }
   // The previous iteration's update of this cell, applied and stored as soon
   // as the cell is staged: x' = x + alpha p + omega s, r' = s - omega t,
   // p' = r' + beta (p - omega v); (rh, r') and ||r'||^2 accumulate here.
   __device__ St combine_own(const ORaw& q, size_t i, double (&acc)[NV]) const {
+    T sh;
+    if constexpr (HASHED) sh = hashed_shadow<T>(i);
+    else sh = q.rh;
     T rn, pn;
     if (first) {
       rn = q.r;
@@ -566,9 +579,9 @@ struct PhAC {
     }
     st_once(r_out + i, rn);
     st_once(p_out + i, pn);
-    dot_acc(acc[1], (double)q.rh, (double)rn);
+    dot_acc(acc[1], (double)sh, (double)rn);
     dot_acc(acc[2], (double)rn, (double)rn);
-    return {pn, q.rh};
+    return {pn, sh};
   }
   __device__ T value_own(const ORaw& q) const {
     return combine(Raw{q.r, q.v, q.t, q.p});
@@ -582,7 +595,11 @@ struct PhAC {
 };
 
 // Pass 2: s = r - alpha v staged, t = A s; (t,s), (t,t), (rh,s), (rh,t).
-template <typename T>
+// HASHED: the build for the index-hashed shadow residual alone, which forms
+// rh from the cell index in the epilogue (the `hashed` flag is not read), so
+// that no register holds it from the plane's load issue to its epilogue:
+// the same value, computed later.  The other build takes either shadow.
+template <typename T, bool HASHED = false>
 struct PhB2 {
   static constexpr int NV = 4;
   static constexpr int PD = 1;  // measured: 4-6% faster than 2 (its epilogue loads nothing)
@@ -596,21 +613,27 @@ struct PhB2 {
   T alpha;
   int hashed;      // shadow residual from the cell index (not stored)
   struct Raw { T r, v; };
-  struct ERaw { T rh; };
+  struct StoredRh { T rh; };
+  struct NoRh {};
+  using ERaw = std::conditional_t<HASHED, NoRh, StoredRh>;
   WFA_PLAIN_OWN_STAGE
   __device__ void bind(const Scalars* sc) { alpha = (T)sc->alpha; }
   __device__ Raw fetch(size_t i) const { return {r[i], v[i]}; }
   __device__ T combine(const Raw& q) const { return minus_ax(q.r, alpha, q.v); }
   __device__ ERaw efetch(size_t i) const {
-    return {hashed ? hashed_shadow<T>(i) : ld_once(rh + i)};
+    if constexpr (HASHED) return {};
+    else return {hashed ? hashed_shadow<T>(i) : ld_once(rh + i)};
   }
   __device__ void epilogue(size_t i, T s, T Au, T, uint32_t, const ERaw& e, T dg,
                            double (&acc)[NV]) const {
     if (t) st_once(t + i, Au);   // none when pass 1 forms t again
+    T rhv;
+    if constexpr (HASHED) rhv = hashed_shadow<T>(i);
+    else rhv = e.rh;
     dot_acc(acc[0], (double)Au, (double)s);
     dot_acc(acc[1], (double)Au, (double)Au);
-    dot_acc(acc[2], (double)e.rh, (double)s);
-    dot_acc(acc[3], (double)e.rh, (double)Au);
+    dot_acc(acc[2], (double)rhv, (double)s);
+    dot_acc(acc[3], (double)rhv, (double)Au);
   }
 };
 
