@@ -249,7 +249,9 @@ def summarize_trace(stats_csv: str, title: str, command: str) -> str:
         lines += ["", f"GPU busy {100 * busy:.1f}% of the span from the first kernel to the last "
                       f"(union of kernel intervals); median gap between kernels "
                       f"{gaps['median_us']:.1f} us; {gaps['over_20us']} gaps over 20 us, "
-                      f"{gaps['over_20us_total_ms']:.1f} ms in all."]
+                      f"{gaps['over_20us_total_ms']:.1f} ms in all, of which {gaps['over_1ms']} "
+                      f"over 1 ms ({gaps['over_1ms_total_ms']:.1f} ms); busy "
+                      f"{100 * gaps['busy_without_over_1ms']:.1f}% of the span less those."]
     return "\n".join(lines) + "\n"
 
 
@@ -267,9 +269,13 @@ def gpu_busy(spans):
     covered = sum(b - a for a, b in merged)
     gaps = [(merged[q + 1][0] - merged[q][1]) / 1e3 for q in range(len(merged) - 1)]
     big = [g for g in gaps if g > 20.0]
+    idle = [g for g in gaps if g > 1000.0]   # over 1 ms: no kernel queued at all
+    rest = total - sum(idle) * 1e3
     return covered / total if total > 0 else 1.0, {
         "median_us": sorted(gaps)[len(gaps) // 2] if gaps else 0.0,
-        "over_20us": len(big), "over_20us_total_ms": sum(big) / 1e3}
+        "over_20us": len(big), "over_20us_total_ms": sum(big) / 1e3,
+        "over_1ms": len(idle), "over_1ms_total_ms": sum(idle) / 1e3,
+        "busy_without_over_1ms": covered / rest if rest > 0 else 1.0}
 
 
 def cpu_baseline(prob, iters: int):

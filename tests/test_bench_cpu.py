@@ -100,7 +100,14 @@ def test_gpu_busy_union_of_intervals():
     assert abs(busy - (12 + 10 + 5) / 60) < 1e-12
     assert gaps["over_20us"] == 1 and abs(gaps["over_20us_total_ms"] - 0.028) < 1e-12
     assert gaps["median_us"] in (5.0, 28.0)
+    assert gaps["over_1ms"] == 0 and gaps["busy_without_over_1ms"] == busy
     assert bench.gpu_busy([(3, 9)])[0] == 1.0
+    # a gap over 1 ms (nothing queued) is left out of the second figure
+    ms = 1000 * us
+    busy, gaps = bench.gpu_busy([(0, 1 * ms), (3 * ms, 4 * ms), (4 * ms + 10 * us, 5 * ms)])
+    assert abs(busy - (3 * ms - 10 * us) / (5 * ms)) < 1e-12
+    assert gaps["over_1ms"] == 1 and abs(gaps["over_1ms_total_ms"] - 2.0) < 1e-12
+    assert abs(gaps["busy_without_over_1ms"] - (3 * ms - 10 * us) / (3 * ms)) < 1e-12
 
 
 def test_pmc_summary_means_per_working_dispatch(tmp_path):
