@@ -244,10 +244,13 @@ enum {
   WFA_OPT_PERSISTENT = 2,      /* 0: one launch per phase (default),
                                   1: one persistent launch per solve chunk,
                                   -1: automatic by grid size                   */
-  WFA_OPT_PROFILE = 3,         /* 1: time every phase launch with HIP events
-                                  (the true residual then gets its own pass
-                                  after the solve, instead of one queued
-                                  behind each chunk of iterations)             */
+  WFA_OPT_PROFILE = 3,         /* n > 0: time every n-th launch of each
+                                  kernel with HIP events (1: every launch;
+                                  the count restarts when the option is
+                                  set).  While on, the true residual gets its
+                                  own pass after the solve, instead of one
+                                  queued behind each chunk of iterations.
+                                  0 (default): off                             */
   WFA_OPT_FORCE_BREAKDOWN = 4, /* n > 0: treat sigma as exactly 0 at full
                                   iteration n of the next solve (once), to
                                   exercise the restart path from the host      */
@@ -319,8 +322,8 @@ enum {
   WFA_K_CG_B = 8, WFA_K_PERSISTENT = 9, WFA_K_PHASE_AC = 10, WFA_K_PHASE_B2 = 11,
   WFA_K_EXPLICIT = 12, WFA_K_EXPLICIT_FUSED = 13, WFA_K_CG1 = 14, WFA_K_COUNT = 15
 };
-/* With WFA_OPT_PROFILE on: launches and summed event time (ms) of one
- * kernel since the last reset; `bytes` = algorithmic HBM bytes per launch
+/* With WFA_OPT_PROFILE on: timed launches and their summed event time (ms)
+ * of one kernel since the last reset; `bytes` = algorithmic HBM bytes per launch
  * (the streams the kernel must read and write once).  reset != 0 clears. */
 int wfa_kernel_stats(wfa_grid* g, int kernel, int64_t* launches, double* ms,
                      double* bytes_per_launch, int reset);

@@ -234,7 +234,9 @@ extern "C" int wfa_grid_set_option(wfa_grid* g, int option, int64_t value) {
       g->persistent = (int)value;
       return WFA_OK;
     case WFA_OPT_PROFILE:
-      g->profile = value != 0;
+      if (value < 0 || value > (1 << 20)) return set_error(WFA_ERR_INVALID, "bad profile interval");
+      g->profile = (int)value;
+      for (auto& c : g->prof.seen) c = 0;
       return WFA_OK;
     case WFA_OPT_FORCE_BREAKDOWN:
       if (value < 0) return set_error(WFA_ERR_INVALID, "bad breakdown iteration");
@@ -350,8 +352,10 @@ void Profiler::drain() {
 
 }  // namespace wfa
 
-// Bracket one launch with events when profiling.  A launch whose events
-// could not be created or recorded is simply not counted.
+// Bracket one launch with events when profiling: every launch, or every
+// profile-th launch of each kernel (the first, then one in profile).  A
+// launch whose events could not be created or recorded is simply not
+// counted.
 struct ProfScope {
   wfa_grid* g;
   int kernel;
@@ -359,7 +363,7 @@ struct ProfScope {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   bool armed = false;
   ProfScope(wfa_grid* g_, int k, hipStream_t s_) : g(g_), kernel(k), s(s_) {
-    if (g->profile) {
+    if (g->profile && (g->prof.seen[kernel]++ % g->profile) == 0) {
       e0 = g->prof.get();
       e1 = g->prof.get();
       armed = e0 && e1 && hipEventRecord(e0, s) == hipSuccess;

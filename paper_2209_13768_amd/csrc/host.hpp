@@ -34,8 +34,9 @@ struct Profiler {
   };
   std::vector<Pending> pending;
   std::vector<hipEvent_t> pool;
-  int64_t launches[WFA_K_COUNT] = {};
+  int64_t launches[WFA_K_COUNT] = {};  // timed launches
   double total_ms[WFA_K_COUNT] = {};
+  int64_t seen[WFA_K_COUNT] = {};      // launches since profiling was set (sampling)
   hipEvent_t get();
   void drain();
   void clear();

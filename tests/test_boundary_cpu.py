@@ -86,6 +86,10 @@ def test_grid_descriptor_host_only(libwfa):
     assert libwfa.wfa_grid_set_option(out, wfa.OPT_ZCHUNK, 32) == wfa.OK
     assert libwfa.wfa_grid_tiling(out, *[ctypes.byref(q) for q in v]) == wfa.OK
     assert v[2].value == 32
+    # launch timing: off, every launch, or every n-th launch of each kernel
+    for n, rc in ((-1, wfa.ERR_INVALID), ((1 << 20) + 1, wfa.ERR_INVALID), (8, wfa.OK),
+                  (1, wfa.OK), (0, wfa.OK)):
+        assert libwfa.wfa_grid_set_option(out, wfa.OPT_PROFILE, n) == rc, n
     assert libwfa.wfa_grid_destroy(out) == wfa.OK
 
 

@@ -126,3 +126,26 @@ def test_first_chunk_hint_leaves_results_unchanged(wfa, precision):
     assert ie.status == wfa.OK and ie.iterations < i1.iterations
     assert (i1.iterations, i1.rel_res_true) == (i2.iterations, i2.rel_res_true)
     assert np.array_equal(x1.cpu().numpy(), x2.cpu().numpy())
+
+
+def test_sampled_launch_timing(wfa):
+    """WFA_OPT_PROFILE = n times the first and then every n-th launch of each
+    kernel: a fixed-length solve times ceil(launches / n) of each kernel's
+    launches, and the iterates do not depend on the timing."""
+    prob = inputs.random_problem(152, 70, 20, 33, cell=True, u=(0.5, 0.0, -1.0))
+    counts, xs = {}, {}
+    for n in (1, 3, 8):
+        g = wfa.Grid.from_problem(prob, precision=wfa.F64)
+        g.set_option(wfa.OPT_PROFILE, n)
+        b = g.rhs(g.field(prob.T0))
+        x, info = g.solve(b, g.field(prob.T0), tol=1e-300, maxit=25, method="bicgstab2",
+                          check=False)
+        assert info.iterations == 25
+        counts[n] = [g.kernel_stats(k)[0] for k in range(wfa.K_COUNT)]
+        xs[n] = x.cpu().numpy()
+        ms = [g.kernel_stats(k)[1] for k in range(wfa.K_COUNT)]
+        assert all(m > 0 for c, m in zip(counts[n], ms) if c > 0)
+    assert counts[1][wfa.K_PHASE_AC] >= 25 and counts[1][wfa.K_PHASE_B2] >= 25
+    for n in (3, 8):
+        assert counts[n] == [-(-c // n) for c in counts[1]], (n, counts[n], counts[1])
+        assert np.array_equal(xs[n], xs[1])
