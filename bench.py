@@ -248,7 +248,7 @@ def summarize_trace(stats_csv: str, title: str, command: str) -> str:
     if spans:
         busy, gaps = gpu_busy(spans)
         lines += ["", f"GPU busy {100 * busy:.1f}% of the span from the first kernel to the last "
-                      f"(union of kernel intervals); median gap between kernels "
+                      f"(union of kernel intervals); median idle gap "
                       f"{gaps['median_us']:.1f} us; {gaps['over_20us']} gaps over 20 us, "
                       f"{gaps['over_20us_total_ms']:.1f} ms in all, of which {gaps['over_1ms']} "
                       f"over 1 ms ({gaps['over_1ms_total_ms']:.1f} ms); busy "
