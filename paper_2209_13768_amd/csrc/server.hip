@@ -127,9 +127,10 @@ struct wfa_server {
   size_t arena_bytes;
   int max_slots;               // resident solves per size class
   // One size class: its worker thread, stream, slots, device tables (inside
-  // the arena) and their pinned host mirrors.  The tables are uploaded and
-  // the slot scalars read back with asynchronous copies; the worker rewrites
-  // a table only after the round that uploaded it has been waited for.
+  // the arena) and their pinned host mirrors.  The tables are uploaded with
+  // asynchronous copies, and the slot scalars written back into their mapped
+  // mirror by a kernel at the end of each round; the worker rewrites a table
+  // only after the round that uploaded it has been waited for.
   struct Lane {
     int id = 0;
     hipStream_t stream = nullptr;
@@ -140,6 +141,7 @@ struct wfa_server {
     int* bases = nullptr;            // device: 4 * (max_slots + 1)
     GridBarrier* bar = nullptr;      // device: grid barrier of a persistent round
     Scalars* h_sc = nullptr;         // pinned mirrors of the above
+    uint32_t* h_sc_dev = nullptr;    // h_sc as the device addresses it
     SolveDesc<float>* h_d32 = nullptr;
     SolveDesc<double>* h_d64 = nullptr;
     int* h_bases = nullptr;
@@ -560,6 +562,16 @@ void fail_lane(wfa_server* sv, wfa_server::Lane& ln, int rc) {
   sv->cv_done.notify_all();
 }
 
+// Copies the slot scalar blocks of one class into their pinned host mirror
+// (mapped, coherent): a plain dispatch that follows the round's last pass
+// without the lead time of a device-to-host copy command.
+__global__ void __launch_bounds__(kThreads)
+k_readback(const uint32_t* __restrict__ src, uint32_t* __restrict__ dst, size_t n) {
+  for (size_t e = (size_t)blockIdx.x * kThreads + threadIdx.x; e < n;
+       e += (size_t)gridDim.x * kThreads)
+    dst[e] = src[e];
+}
+
 void worker_main(wfa_server* sv, int lane) {
   wfa_server::Lane& ln = sv->lanes[lane];
   std::vector<Request*> admitted;
@@ -650,9 +662,11 @@ void worker_main(wfa_server* sv, int lane) {
       if (e != hipSuccess) rc = fail(sv, "batched iteration", e);
     }
     if (!rc) {
-      hipError_t e = hipMemcpyAsync(ln.h_sc, ln.slot_sc,
-                                    sizeof(Scalars) * kScalarsPerSlot * sv->max_slots,
-                                    hipMemcpyDeviceToHost, ln.stream);
+      static_assert(sizeof(Scalars) % 4 == 0, "scalar blocks are copied as 32-bit words");
+      const size_t words = sizeof(Scalars) * kScalarsPerSlot * sv->max_slots / 4;
+      hipLaunchKernelGGL(k_readback, dim3((unsigned)std::min<size_t>((words + kThreads - 1) / kThreads, 8)),
+                         dim3(kThreads), 0, ln.stream, (const uint32_t*)ln.slot_sc, ln.h_sc_dev, words);
+      hipError_t e = hipGetLastError();
       if (e == hipSuccess && persist)
         e = hipMemcpyAsync(ln.h_bar, ln.bar, sizeof(GridBarrier), hipMemcpyDeviceToHost,
                            ln.stream);
@@ -727,7 +741,7 @@ extern "C" int wfa_server_create(void* arena, size_t arena_bytes, int max_slots,
     delete sv;
     return set_error(WFA_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
   };
-  hipError_t e = hipHostMalloc(&sv->pinned, meta, hipHostMallocDefault);
+  hipError_t e = hipHostMalloc(&sv->pinned, meta, hipHostMallocMapped | hipHostMallocCoherent);
   if (e != hipSuccess) return teardown("server host tables", e);
   memset(sv->pinned, 0, meta);
   for (int k = 0; k < kMaxLanes; ++k) {
@@ -741,6 +755,12 @@ extern "C" int wfa_server_create(void* arena, size_t arena_bytes, int max_slots,
     ln.bases = (int*)(d + sc_bytes + d32_bytes + d64_bytes);
     ln.bar = (GridBarrier*)(d + sc_bytes + d32_bytes + d64_bytes + b_bytes);
     ln.h_sc = (Scalars*)h;
+    {
+      void* hd = nullptr;
+      e = hipHostGetDevicePointer(&hd, h, 0);
+      if (e != hipSuccess) return teardown("server host tables", e);
+      ln.h_sc_dev = (uint32_t*)hd;
+    }
     ln.h_d32 = (SolveDesc<float>*)(h + sc_bytes);
     ln.h_d64 = (SolveDesc<double>*)(h + sc_bytes + d32_bytes);
     ln.h_bases = (int*)(h + sc_bytes + d32_bytes + d64_bytes);
