@@ -663,7 +663,12 @@ void worker_main(wfa_server* sv, int lane) {
     }
     if (!rc) {
       static_assert(sizeof(Scalars) % 4 == 0, "scalar blocks are copied as 32-bit words");
-      const size_t words = sizeof(Scalars) * kScalarsPerSlot * sv->max_slots / 4;
+      // the blocks of the slots up to the last resident one (the host reads
+      // only resident slots' blocks)
+      int used = 1;
+      for (int q = 0; q < sv->max_slots; ++q)
+        if (ln.slots[q]) used = q + 1;
+      const size_t words = sizeof(Scalars) * kScalarsPerSlot * (size_t)used / 4;
       hipLaunchKernelGGL(k_readback, dim3((unsigned)std::min<size_t>((words + kThreads - 1) / kThreads, 8)),
                          dim3(kThreads), 0, ln.stream, (const uint32_t*)ln.slot_sc, ln.h_sc_dev, words);
       hipError_t e = hipGetLastError();
