@@ -142,6 +142,9 @@ struct wfa_server {
     GridBarrier* bar = nullptr;      // device: grid barrier of a persistent round
     Scalars* h_sc = nullptr;         // pinned mirrors of the above
     uint32_t* h_sc_dev = nullptr;    // h_sc as the device addresses it
+    uint32_t* flag = nullptr;        // pinned: number of the last round read back
+    uint32_t* flag_dev = nullptr;    // the same word as the device addresses it
+    uint32_t round_seq = 0;
     SolveDesc<float>* h_d32 = nullptr;
     SolveDesc<double>* h_d64 = nullptr;
     int* h_bases = nullptr;
@@ -563,13 +566,18 @@ void fail_lane(wfa_server* sv, wfa_server::Lane& ln, int rc) {
 }
 
 // Copies the slot scalar blocks of one class into their pinned host mirror
-// (mapped, coherent): a plain dispatch that follows the round's last pass
-// without the lead time of a device-to-host copy command.
+// (mapped, coherent), then writes the round's number into the mirror's flag
+// word: every thread's stores are made visible at system scope before the
+// workgroup barrier, and the flag is stored after it, so a host that sees
+// the number sees the blocks.  One workgroup.
 __global__ void __launch_bounds__(kThreads)
-k_readback(const uint32_t* __restrict__ src, uint32_t* __restrict__ dst, size_t n) {
-  for (size_t e = (size_t)blockIdx.x * kThreads + threadIdx.x; e < n;
-       e += (size_t)gridDim.x * kThreads)
-    dst[e] = src[e];
+k_readback(const uint32_t* __restrict__ src, uint32_t* __restrict__ dst, size_t n,
+           uint32_t* __restrict__ flag, uint32_t seq) {
+  for (size_t e = threadIdx.x; e < n; e += kThreads) dst[e] = src[e];
+  __threadfence_system();
+  __syncthreads();
+  if (threadIdx.x == 0)
+    __hip_atomic_store(flag, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 void worker_main(wfa_server* sv, int lane) {
@@ -669,14 +677,30 @@ void worker_main(wfa_server* sv, int lane) {
       for (int q = 0; q < sv->max_slots; ++q)
         if (ln.slots[q]) used = q + 1;
       const size_t words = sizeof(Scalars) * kScalarsPerSlot * (size_t)used / 4;
-      hipLaunchKernelGGL(k_readback, dim3((unsigned)std::min<size_t>((words + kThreads - 1) / kThreads, 8)),
-                         dim3(kThreads), 0, ln.stream, (const uint32_t*)ln.slot_sc, ln.h_sc_dev, words);
+      const uint32_t seq = ++ln.round_seq;
+      hipLaunchKernelGGL(k_readback, dim3(1), dim3(kThreads), 0, ln.stream,
+                         (const uint32_t*)ln.slot_sc, ln.h_sc_dev, words, ln.flag_dev, seq);
       hipError_t e = hipGetLastError();
       if (e == hipSuccess && persist)
         e = hipMemcpyAsync(ln.h_bar, ln.bar, sizeof(GridBarrier), hipMemcpyDeviceToHost,
                            ln.stream);
       if (e == hipSuccess) e = hipEventRecord(ln.round_done, ln.stream);
-      if (e == hipSuccess) e = wait_event(ln.round_done);
+      // the round's number in the flag word shows the blocks have landed,
+      // a few microseconds before the event does; the event stays the
+      // fallback that reports a failed round (and carries persistent
+      // rounds, whose barrier block is copied after the kernel)
+      bool seen = false;
+      if (e == hipSuccess && !persist) {
+        const auto t0 = std::chrono::steady_clock::now();
+        while (!(seen = __atomic_load_n(ln.flag, __ATOMIC_ACQUIRE) == seq) &&
+               std::chrono::steady_clock::now() - t0 < std::chrono::milliseconds(2)) {
+        }
+      }
+      if (e == hipSuccess && !seen) {
+        e = wait_event(ln.round_done);
+        if (e == hipSuccess && !persist && __atomic_load_n(ln.flag, __ATOMIC_ACQUIRE) != seq)
+          e = hipErrorUnknown;   // the round completed without its readback
+      }
       if (e != hipSuccess)
         rc = fail(sv, "scalar readback", e);
       else if (persist && ln.h_bar->timeout)
@@ -770,6 +794,10 @@ extern "C" int wfa_server_create(void* arena, size_t arena_bytes, int max_slots,
     ln.h_d64 = (SolveDesc<double>*)(h + sc_bytes + d32_bytes);
     ln.h_bases = (int*)(h + sc_bytes + d32_bytes + d64_bytes);
     ln.h_bar = (GridBarrier*)(h + sc_bytes + d32_bytes + d64_bytes + b_bytes);
+    // the flag word shares the barrier mirror's 256-byte piece, past it
+    static_assert(sizeof(GridBarrier) + 64 + 4 <= 256, "flag word inside the barrier piece");
+    ln.flag = (uint32_t*)((char*)ln.h_bar + 64);
+    ln.flag_dev = (uint32_t*)((char*)ln.h_sc_dev + ((char*)ln.flag - h));
     ln.slots.assign(max_slots, nullptr);
     // the first class runs on the caller's stream, the others on streams of
     // their own (default priority)
