@@ -287,7 +287,11 @@ enum {
                                   a fixed field of the cell index (the 32-bit
                                   PCG hash of the index, top 24 bits mapped to
                                   [-1, 1)), computed where it is used, which
-                                  saves one vector stream per pass            */
+                                  saves one vector stream per pass.  Under
+                                  WFA_F32_IR64 a refinement whose inner solve
+                                  diverged under 1 without a usable iterate is
+                                  repeated with r0, kept for the rest of the
+                                  solve                                       */
   WFA_OPT_FORCE_DIVERGE = 13   /* n > 0: the first inner FP32 solve of the
                                   next WFA_F32_IR64 solve counts as diverged at
                                   inner iteration n (once), to exercise the
@@ -431,7 +435,9 @@ int wfa_bandwidth_probe(int kind, int blocks, const void* src, void* dst, size_t
  * two-reduction BiCGStab and the index-hashed shadow residual, as
  * wfa_timestep does with WFA_OPT_METHOD = WFA_METHOD_BICGSTAB2 and
  * WFA_OPT_SHADOW = 1; WFA_F32_IR64 requests run it as the inner solve of
- * refinement, as wfa_timestep does.  The first class's thread drives
+ * refinement, as wfa_timestep does (including its fall-back to r^ = r0
+ * for a refinement whose inner solve diverged without a usable
+ * iterate).  The first class's thread drives
  * the GPU on `stream`; the others on streams the server creates (default
  * priority).  Precision of every request: c->precision.  The server also
  * holds a pinned host mirror of its slot tables and scalars, one event per
@@ -468,7 +474,10 @@ int wfa_server_create(void* arena, size_t arena_bytes, int max_slots, void* stre
  *   WFA_OPT_SIZE_CLASS_1..3  upper cell-count bound of size classes 1..3
  *                        (class 4 takes the rest); 0 ends the list.
  *                        Non-zero bounds must increase.  A request's class
- *                        is fixed when it is submitted.
+ *                        is fixed when it is submitted;
+ *   WFA_OPT_IR_INNER_TOL (value / 1e12) = relative tolerance of the FP32
+ *                        inner solves of WFA_F32_IR64 requests submitted
+ *                        from then on, in (0, 1); default 1e-4 * 1e12.
  * Errors: WFA_ERR_INVALID (null server, unknown option, value out of range). */
 int wfa_server_set_option(wfa_server* sv, int option, int64_t value);
 

@@ -1104,7 +1104,11 @@ static int solve_ir(wfa_grid* g, const double* b_user, double* x, bool form_b, d
   float* w[2] = {v[0], v[1]};
   Launch<float> L32 = ctx<float>(g, g->sc_in, s);
   L32.op.jac = cg1 ? 0 : 1;
-  L32.shadow = g->shadow;  // the inner solve's shadow residual (as the residual pass wrote it)
+  // the inner solve's shadow residual (as the residual pass writes it); a
+  // refinement whose inner solve diverged without a usable iterate under the
+  // hashed one is repeated with r^ = r0, kept for the rest of the solve
+  int shadow = g->shadow;
+  L32.shadow = shadow;
   const double* b = b_user;
   if (form_b) {
     launch_rhs<double>(L64, x, g->b64);
@@ -1139,7 +1143,7 @@ static int solve_ir(wfa_grid* g, const double* b_user, double* x, bool form_b, d
     if ((rc = write_scalars(&hi, g->sc_in, s))) return rc;
     {
       ProfScope ps(g, WFA_K_RESIDUAL, s);
-      launch_residual<double>(L64, x, b, r, rh, g->sc_in, cg1 ? 1 : 2, g->shadow);
+      launch_residual<double>(L64, x, b, r, rh, g->sc_in, cg1 ? 1 : 2, shadow);
     }
     if ((rc = check_launch("residual"))) return rc;
     const bool last = ref >= max_ref || total_it >= maxit;
@@ -1182,6 +1186,12 @@ static int solve_ir(wfa_grid* g, const double* b_user, double* x, bool form_b, d
     if (hi.diverged) {
       if (inner_cap == 0 && hi.it_min > 0) {  // repeat it, stopped at its best iterate
         inner_cap = hi.it_min;
+        continue;
+      }
+      if (shadow && !cg1) {  // repeat it with r^ = r0 stored
+        shadow = 0;
+        L32.shadow = 0;
+        inner_cap = 0;
         continue;
       }
       status = WFA_ERR_NOCONV;  // no usable correction

@@ -92,8 +92,10 @@ struct Heap {
 
 enum Phase { Q_QUEUED, R_START, R_ITER, R_REFINE, R_FINAL, R_DONE };
 
-// Every served solve uses the index-hashed shadow residual (one vector
-// stream less per pass than storing r0), as a grid does with WFA_OPT_SHADOW.
+// Every served solve starts with the index-hashed shadow residual (one
+// vector stream less per pass than storing r0), as a grid does with
+// WFA_OPT_SHADOW; a refinement whose inner solve diverged without a usable
+// iterate is repeated with r^ = r0 stored, and the request keeps it.
 constexpr int kServerShadow = 1;
 
 struct Request {
@@ -113,6 +115,8 @@ struct Request {
   int lane = 0;         // size class serving the request
   int par = 0;        // buffer parity of the next iteration (0 after every (re)start)
   int cg1 = 0;        // 1: iterates with CG with one reduction (symmetric request)
+  int shadow = kServerShadow;  // 1: hashed r^; 0: r^ = r0, stored
+  double inner_tol = 1e-4;     // FP32 inner solve's relative tolerance (fixed at submission)
   double scale = 1.0;
   double last_rec = 0.0;
   double t_submit = 0.0, t_done = 0.0;
@@ -173,6 +177,7 @@ struct wfa_server {
   std::mutex err_mu;
   char worker_msg[256] = "";
   int chunk = 4;      // iterations per round (WFA_OPT_CHECK_EVERY)
+  double ir_inner_tol = 1e-4;  // WFA_OPT_IR_INNER_TOL for requests submitted from now on
   int persistent = 0; // 1: a round is one cooperative launch per precision (WFA_OPT_PERSISTENT)
   int method = WFA_METHOD_BICGSTAB2;  // WFA_OPT_METHOD: _CG1 for symmetric requests
   int64_t cg1_max_cells = 0;          // WFA_OPT_CG1_MAX_CELLS (0: no limit)
@@ -261,7 +266,7 @@ SolveDesc<T> make_desc(Request* r, T* x) {
   d.r = v[0]; d.rh = v[1]; d.t = v[2]; d.p0 = v[3]; d.p1 = v[4]; d.v0 = v[5]; d.v1 = v[6];
   d.r1 = v[8];
   d.par = r->par;
-  d.hashed = kServerShadow;
+  d.hashed = r->shadow;
   d.cg1 = r->cg1;
   d.partials = g.partials;
   d.sc = g.prec == WFA_F32_IR64 ? g.sc_in : g.sc;
@@ -278,7 +283,7 @@ int start_request(wfa_server* sv, Request* r) {
   hipStream_t s = lane_of(sv, r).stream;
   r->par = 0;  // the first residual goes to the parity-0 buffer
   if (g.prec == WFA_F32_IR64) {
-    Scalars h2[2] = {fresh(r->tol, r->maxit), fresh(1e-4, ir_inner_maxit(r->maxit, 0))};
+    Scalars h2[2] = {fresh(r->tol, r->maxit), fresh(r->inner_tol, ir_inner_maxit(r->maxit, 0))};
     h2[1].guard = kIrGuard;
     if (int rc = put_scalars(sv, s, g.sc, h2, 2)) return rc;
     Launch<double> L{g.tl, g.op64, g.c.mode == WFA_COEF_CELL, (const float*)g.c.kappa,
@@ -286,7 +291,7 @@ int start_request(wfa_server* sv, Request* r) {
     launch_rhs<double>(L, (const double*)r->T, g.b64);
     float** v = (float**)g.vec;
     launch_residual<double>(L, (const double*)r->T, g.b64, v[0], v[1], g.sc_in, r->cg1 ? 1 : 2,
-                            kServerShadow);
+                            r->shadow);
   } else {
     const Scalars h = fresh(r->tol, r->maxit);
     if (int rc = put_scalars(sv, s, g.sc, &h, 1)) return rc;
@@ -294,13 +299,13 @@ int start_request(wfa_server* sv, Request* r) {
       Launch<double> L{g.tl, g.op64, g.c.mode == WFA_COEF_CELL, (const float*)g.c.kappa,
                        g.partials, g.sc, s};
       double** v = (double**)g.vec;
-      L.shadow = kServerShadow;
+      L.shadow = r->shadow;
       launch_init<double>(L, true, (double*)r->T, nullptr, v[7], v[0], v[1]);
     } else {
       Launch<float> L{g.tl, g.op32, g.c.mode == WFA_COEF_CELL, (const float*)g.c.kappa,
                       g.partials, g.sc, s};
       float** v = (float**)g.vec;
-      L.shadow = kServerShadow;
+      L.shadow = r->shadow;
       launch_init<float>(L, true, (float*)r->T, nullptr, v[7], v[0], v[1]);
     }
   }
@@ -316,7 +321,7 @@ int refine_request(wfa_server* sv, Request* r, double scale_next, bool promote) 
   hipStream_t s = lane_of(sv, r).stream;
   if (promote) launch_promote(g.n, g.tl.pw_blocks, (double*)r->T, g.d32, g.sc_in, s);
   Scalars h2[2] = {fresh(r->tol, r->maxit),
-                   fresh(1e-4, r->inner_cap > 0 ? r->inner_cap : ir_inner_maxit(r->maxit, r->total_it))};
+                   fresh(r->inner_tol, r->inner_cap > 0 ? r->inner_cap : ir_inner_maxit(r->maxit, r->total_it))};
   Scalars& ho = h2[0];
   Scalars& hi = h2[1];
   ho.scale = scale_next; ho.inv_scale = 1.0 / scale_next;
@@ -327,7 +332,7 @@ int refine_request(wfa_server* sv, Request* r, double scale_next, bool promote) 
                    g.partials, g.sc, s};
   float** v = (float**)g.vec;
   launch_residual<double>(L, (const double*)r->T, g.b64, v[0], v[1], g.sc_in, r->cg1 ? 1 : 2,
-                          kServerShadow);
+                          r->shadow);
   r->par = 0;
   r->scale = scale_next;
   hipError_t e = hipGetLastError();
@@ -436,6 +441,15 @@ int advance(wfa_server* sv, Request* r) {
         r->phase = R_REFINE;
         return refine_request(sv, r, r->scale, false);
       }
+      if (r->shadow && !r->cg1) {
+        // no usable correction with the hashed shadow residual: repeat the
+        // refinement with r^ = r0 (the residual pass stores it), nothing
+        // promoted
+        r->shadow = 0;
+        r->inner_cap = 0;
+        r->phase = R_REFINE;
+        return refine_request(sv, r, r->scale, false);
+      }
       retire(sv, r, WFA_ERR_NOCONV, sqrt(o.rr / o.bb));  // no usable correction
       return WFA_OK;
     }
@@ -471,13 +485,13 @@ int advance(wfa_server* sv, Request* r) {
       Launch<double> L{g.tl, g.op64, g.c.mode == WFA_COEF_CELL, (const float*)g.c.kappa,
                        g.partials, g.sc, ln.stream};
       double** v = (double**)g.vec;
-      L.shadow = kServerShadow;
+      L.shadow = r->shadow;
       launch_init<double>(L, false, (double*)r->T, v[7], nullptr, v[0], v[1]);
     } else {
       Launch<float> L{g.tl, g.op32, g.c.mode == WFA_COEF_CELL, (const float*)g.c.kappa,
                       g.partials, g.sc, ln.stream};
       float** v = (float**)g.vec;
-      L.shadow = kServerShadow;
+      L.shadow = r->shadow;
       launch_init<float>(L, false, (float*)r->T, v[7], nullptr, v[0], v[1]);
     }
     return WFA_OK;
@@ -861,6 +875,11 @@ extern "C" int wfa_server_set_option(wfa_server* sv, int option, int64_t value) 
         return set_error(WFA_ERR_INVALID, "iterations per round must be in [1, 1024]");
       sv->chunk = (int)value;
       return WFA_OK;
+    case WFA_OPT_IR_INNER_TOL:
+      if (value <= 0 || value >= 1000000000000LL)
+        return set_error(WFA_ERR_INVALID, "inner tolerance must be in (0, 1)");
+      sv->ir_inner_tol = (double)value * 1e-12;
+      return WFA_OK;
     case WFA_OPT_SIZE_CLASS_1:
     case WFA_OPT_SIZE_CLASS_2:
     case WFA_OPT_SIZE_CLASS_3: {
@@ -910,6 +929,7 @@ extern "C" int wfa_submit(wfa_server* sv, int nx, int ny, int nz, const wfa_coef
     r->cg1 = sv->method == WFA_METHOD_CG1 && c->u[0] == 0.0 && c->u[1] == 0.0 &&
              c->u[2] == 0.0 && (sv->cg1_max_cells == 0 || cells <= sv->cg1_max_cells);
     r->lane = lane_for(sv, cells);
+    r->inner_tol = sv->ir_inner_tol;
     sv->reqs[r->ticket] = r;
     sv->lanes[r->lane].queue.push_back(r);
     ++sv->inflight;

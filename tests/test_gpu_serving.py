@@ -81,6 +81,30 @@ def test_server_matches_single_grid_path(wfa):
         assert gi.iterations == info.iterations and gi.refinements == info.refinements
 
 
+def test_inner_divergence_falls_back_to_stored_shadow(wfa, oracle_mod):
+    """Request 387 of the serving stream (96x64x192) with an inner relative
+    tolerance of 1e-3: in its third refinement the FP32 inner solve diverges
+    under the hashed shadow residual without a usable iterate.  The
+    refinement is repeated with r^ = r0 stored and the step converges;
+    served and single-grid results are bitwise equal and meet the tolerance
+    under the oracle's operator.  (Without the fall-back this request ended
+    WFA_ERR_NOCONV.)"""
+    rq = inputs.Request(387, 0.0, 96, 64, 192)
+    prob = rq.problem()
+    inner = 10 ** 9                     # 1e-3 in units of 1e-12
+    g = wfa.Grid.from_problem(prob, precision=wfa.F32_IR64)
+    g.set_option(wfa.OPT_SHADOW, 1)    # the server's shadow residual
+    g.set_option(wfa.OPT_IR_INNER_TOL, inner)
+    T = g.field(prob.T0)
+    gi = g.timestep(T, 1, tol=1e-10, maxit=20000)[0]
+    assert gi.status == wfa.OK, gi
+    served, infos = _serve(wfa, [rq], 1 << 30, slots=4, options={wfa.OPT_IR_INNER_TOL: inner})
+    assert np.array_equal(T.cpu().numpy(), served[0])
+    assert gi.iterations == infos[0].iterations and gi.refinements == infos[0].refinements
+    o = oracle_mod.Oracle(prob)
+    assert o.true_relres(o.rhs(prob.T0), served[0]) <= 1e-10
+
+
 def test_small_budget_admits_one_at_a_time(wfa):
     reqs = _requests(DIMS[:4])
     need = max(wfa.workspace_bytes(r.nx, r.ny, r.nz, wfa.F32_IR64) for r in reqs)
@@ -190,9 +214,11 @@ def test_server_options_are_validated(wfa):
     for opt, val in ((wfa.OPT_PERSISTENT, 2), (wfa.OPT_CHECK_EVERY, 0),
                      (wfa.OPT_CHECK_EVERY, 1025), (wfa.OPT_PROFILE, 1),
                      (wfa.OPT_METHOD, wfa.METHOD_CG), (wfa.OPT_METHOD, 9),
-                     (wfa.OPT_CG1_MAX_CELLS, -1)):
+                     (wfa.OPT_CG1_MAX_CELLS, -1), (wfa.OPT_IR_INNER_TOL, 0),
+                     (wfa.OPT_IR_INNER_TOL, 10 ** 12)):
         with pytest.raises(wfa.WfaError):
             sv.set_option(opt, val)
+    sv.set_option(wfa.OPT_IR_INNER_TOL, 10 ** 9)
     sv.set_option(wfa.OPT_CHECK_EVERY, 8)
     sv.set_option(wfa.OPT_PERSISTENT, 1)
     sv.set_option(wfa.OPT_METHOD, wfa.METHOD_CG1)
