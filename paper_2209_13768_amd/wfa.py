@@ -470,8 +470,11 @@ class Server:
         return t.value
 
     def set_option(self, option: int, value: int):
-        """OPT_CHECK_EVERY (iterations per round) or OPT_PERSISTENT (one
-        cooperative launch per round), from the next round on."""
+        """A server option (wfa_server_set_option): OPT_CHECK_EVERY
+        (iterations per round), OPT_PERSISTENT (one cooperative launch per
+        round), OPT_METHOD, OPT_CG1_MAX_CELLS, OPT_SIZE_CLASS_1..3, or
+        OPT_IR_INNER_TOL (inner tolerance x 1e12, for requests submitted
+        from then on)."""
         _check(lib().wfa_server_set_option(self._h, int(option), int(value)))
 
     def submit_problem(self, prob, T, **kw) -> int:
